@@ -1,0 +1,98 @@
+"""Workload recipes.
+
+Each recipe returns a `Problem`: a graph, the labelled node set with its labels, K and
+the solver settings the workload runs with.  The recipes are stand-ins for the paper's
+network and image data sets (Table 1 and Table 2 of the paper), which are not used:
+every input is generated from a seed.
+
+  sbm_small    SBM n = 1,200, three equal blocks, p_in = 0.10, p_out = 0.005, unit weights;
+               5% of each class labelled; FP64; 300 iterations.
+  knn_mixture  k-NN graph (k = 10, union-symmetrised) of a 10-class Gaussian mixture in
+               784 dimensions, n = 70,000, locally scaled Gaussian weights; 1% labelled;
+               FP32; 500 iterations.
+  sbm_large    SBM n = 2,000,000, K = 5, expected degree 24, p_in / p_out = 8, unit
+               weights; 0.5% labelled; FP32; 1,000 iterations.
+  batch_mix    256 graphs: even index SBM (expected degree 24, ratio 8), odd index
+               4-neighbour image grid; n log-uniform in [2e3, 2e5]; K uniform in 3..10;
+               labelled fraction uniform in [1%, 5%]; FP32; 300 iterations.
+  serve_mix    8-neighbour image grids with sides in {128, 256, 512, 1024}, K in {3, 4, 6},
+               2% scribble labels; FP32; 300 iterations.
+
+Networks use eps = 50 and omega0 = 1000, the values the paper selects for networks in its
+parameter study (Section 5.2).  The image-like grids also use eps = 50: the paper's image
+setting (eps = 0.1, omega0 = 1e5) is its one-shot regime on a fully connected graph, which
+on a sparse grid with few scribbles would label every unreached pixel by the lowest-index
+tie rule.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from . import graphs
+
+
+@dataclasses.dataclass
+class Problem:
+    graph: graphs.Graph
+    labelled_idx: np.ndarray  # int32, sorted
+    labels: np.ndarray        # int32 in [0, K)
+    K: int
+    dtype: str = "f32"        # "f32" or "f64"
+    eps: float = 50.0
+    omega0: float = 1000.0
+    max_iter: int = 300
+    tol: float = 1e-6
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return self.graph.n
+
+
+def sbm_small(seed: int = 0, n_per: int = 400, K: int = 3) -> Problem:
+    g = graphs.sbm([n_per] * K, 0.10, 0.005, seed)
+    idx, lab = graphs.stratified_labels(g.truth, K, 0.05, seed)
+    return Problem(g, idx, lab, K, "f64", 50.0, 1000.0, 300, 1e-6, "sbm_small")
+
+
+def knn_mixture(seed: int = 1, n: int = 70_000, d: int = 784, K: int = 10, device: str = "cpu") -> Problem:
+    g = graphs.gaussian_mixture_knn(n, d, K, 10, seed, device=device)
+    idx, lab = graphs.stratified_labels(g.truth, K, 0.01, seed)
+    return Problem(g, idx, lab, K, "f32", 50.0, 1000.0, 500, 1e-6, "knn_mixture")
+
+
+def sbm_large(seed: int = 2, n: int = 2_000_000, K: int = 5, avg_degree: float = 24.0) -> Problem:
+    g = graphs.sbm_by_degree(n, K, avg_degree, 8.0, seed)
+    idx, lab = graphs.stratified_labels(g.truth, K, 0.005, seed)
+    return Problem(g, idx, lab, K, "f32", 50.0, 1000.0, 1000, 1e-6, "sbm_large")
+
+
+def batch_member(seed: int, i: int, n_lo: float = 2e3, n_hi: float = 2e5) -> Problem:
+    rg = graphs.rng_for(seed, 100 + i)
+    n = int(round(math.exp(rg.uniform(math.log(n_lo), math.log(n_hi)))))
+    K = int(rg.integers(3, 11))
+    frac = float(rg.uniform(0.01, 0.05))
+    sub = seed * 100003 + i
+    if i % 2 == 0:
+        g = graphs.sbm_by_degree(n, K, 24.0, 8.0, sub)
+    else:
+        g = graphs.image_grid(n, K, sub, neighbours=4)
+    idx, lab = graphs.stratified_labels(g.truth, K, frac, sub)
+    return Problem(g, idx, lab, K, "f32", 50.0, 1000.0, 300, 1e-6, f"batch[{i}]")
+
+
+def batch_mix(seed: int = 3, count: int = 256, n_lo: float = 2e3, n_hi: float = 2e5) -> list:
+    return [batch_member(seed, i, n_lo, n_hi) for i in range(count)]
+
+
+def serve_request(seed: int, i: int, sides=(128, 256, 512, 1024), Ks=(3, 4, 6)) -> Problem:
+    rg = graphs.rng_for(seed, 200 + i)
+    side = int(sides[int(rg.integers(len(sides)))])
+    K = int(Ks[int(rg.integers(len(Ks)))])
+    sub = seed * 100003 + i
+    g = graphs.image_grid(side * side, K, sub, neighbours=8, side=side)
+    idx, lab = graphs.scribble_labels(g.truth, side, side, K, 0.02, sub)
+    return Problem(g, idx, lab, K, "f32", 50.0, 1000.0, 300, 1e-6, f"serve[{i}]")
