@@ -19,7 +19,9 @@
  *  - the stop test g_k <= tol sits after the GLMO and before the update
  *    (Alg. 3, step 4); a negative tol disables it; `iters` counts updates;
  *  - the update is written U_{k+1} = (1-a) U_k + a S_k, the second form the paper
- *    gives for step 6, so that a = 1 lands exactly on S_k;
+ *    gives for step 6, so that a = 1 lands exactly on S_k; rows whose direction
+ *    d_i = s_i - u_i is zero (binary rows kept by the GLMO) are not touched, which
+ *    keeps them exact for step sizes that are not powers of two;
  *  - "binary row" means every entry is exactly 0 or 1; supp(u_i) = {j : u_ij != 0}.
  */
 #include <math.h>
@@ -152,7 +154,7 @@ int orc_gradient_from_P(int64_t n, int32_t K, const double *P, const double *U, 
         for (int32_t c = 0; c < K; ++c) {
             double u = U[i * K + c];
             double fid = omega[i] != 0.0 ? omega[i] * (Uhat[i * K + c] - u) : 0.0;
-            G[i * K + c] = P[i * K + c] + inv_eps * (1.0 - u) - fid;
+            G[i * K + c] = P[i * K + c] + inv_eps * (1.0 - 2.0 * u) - fid;
         }
     }
     return 0;
@@ -347,12 +349,18 @@ int orc_solve(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const 
         set_hist(hist, hs, k, Ek, g, q, alpha, (double)nonbin);
         out.alpha_last = alpha;
 
-        /* step 6: U_{k+1} = (1 - a) U_k + a S_k */
-        for (int64_t i = 0; i < n; ++i)
+        /* step 6: U_{k+1} = (1 - a) U_k + a S_k; a row whose direction d_i is zero (a
+         * binary row kept by the GLMO) is left exactly as it is */
+        for (int64_t i = 0; i < n; ++i) {
+            int zero_dir = 1;
+            for (int32_t c = 0; c < K; ++c)
+                if (Dm[i * K + c] != 0.0) zero_dir = 0;
+            if (zero_dir) continue;
             for (int32_t c = 0; c < K; ++c) {
                 double sv = c == s[i] ? 1.0 : 0.0;
                 U[i * K + c] = (1.0 - alpha) * U[i * K + c] + alpha * sv;
             }
+        }
         if (prm->osfw) { ++k; break; }
     }
     out.iters = k;
