@@ -1,0 +1,691 @@
+// Host side of libgfw: argument checks, graph set-up, the solve driver, objective and
+// SpMM entry points.  See include/gfw.h for the contract of every exported function.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "gfw_internal.h"
+
+namespace gfw {
+
+static thread_local char g_last_error[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+}
+
+static gfw_status_t fail(gfw_status_t s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static inline void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+static int grid_for(int64_t work, int threads, int cap = 65535)
+{
+    int64_t b = cdiv(std::max<int64_t>(work, 1), threads);
+    return (int)std::min<int64_t>(b, cap);
+}
+
+// --------------------------------------------------------------------------------------
+// host validation (shared by gfw_check_problem and gfw_graph_create for host input)
+// --------------------------------------------------------------------------------------
+
+static gfw_status_t check_scalars(const gfw_problem_t *p)
+{
+    if (!p) return fail(GFW_E_INVALID_ARG, "problem is NULL");
+    if (p->n < 1) return fail(GFW_E_INVALID_ARG, "n must be >= 1 (got %lld)", (long long)p->n);
+    if (p->n >= (int64_t)INT32_MAX) return fail(GFW_E_UNSUPPORTED, "n must be < 2^31 - 1");
+    if (p->K < 2) return fail(GFW_E_INVALID_ARG, "K must be >= 2 (got %d)", p->K);
+    if (p->K > GFW_MAX_K) return fail(GFW_E_UNSUPPORTED, "K must be <= %d (got %d)", GFW_MAX_K, p->K);
+    if (p->nnz < 0) return fail(GFW_E_INVALID_ARG, "nnz must be >= 0");
+    if (p->nnz >= ((int64_t)1 << 31)) return fail(GFW_E_GRAPH, "nnz must be < 2^31");
+    if (p->kind != GFW_GRAPH_W && p->kind != GFW_GRAPH_L) return fail(GFW_E_INVALID_ARG, "bad graph kind");
+    if (p->dtype != GFW_F32 && p->dtype != GFW_F64) return fail(GFW_E_INVALID_ARG, "bad dtype");
+    if (p->location != GFW_HOST && p->location != GFW_DEVICE) return fail(GFW_E_INVALID_ARG, "bad location");
+    if (!p->row_ptr) return fail(GFW_E_INVALID_ARG, "row_ptr is NULL");
+    if (p->nnz > 0 && !p->col_idx) return fail(GFW_E_INVALID_ARG, "col_idx is NULL");
+    if (!p->vals && p->kind == GFW_GRAPH_L) return fail(GFW_E_INVALID_ARG, "vals may be NULL only for kind W");
+    if (p->n_labelled < 0 || p->n_labelled > p->n) return fail(GFW_E_LABELS, "n_labelled out of range");
+    if (p->n_labelled > 0 && (!p->labelled_idx || !p->labels))
+        return fail(GFW_E_INVALID_ARG, "labelled_idx / labels is NULL");
+    return GFW_OK;
+}
+
+template <typename T>
+static gfw_status_t validate_host_graph(const gfw_problem_t *p)
+{
+    const int64_t n = p->n, nnz = p->nnz;
+    const int64_t *rp = p->row_ptr;
+    const int32_t *ci = p->col_idx;
+    const T *w = (const T *)p->vals;
+    if (rp[0] != 0) return fail(GFW_E_GRAPH, "row_ptr[0] must be 0");
+    if (rp[n] != nnz) return fail(GFW_E_GRAPH, "row_ptr[n] (%lld) != nnz (%lld)", (long long)rp[n], (long long)nnz);
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return fail(GFW_E_GRAPH, "row_ptr decreases at row %lld", (long long)i);
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t prev = -1;
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+            const int32_t j = ci[q];
+            if (j < 0 || j >= n) return fail(GFW_E_GRAPH, "column %d out of range in row %lld", j, (long long)i);
+            if (j <= prev) return fail(GFW_E_GRAPH, "columns of row %lld unsorted or repeated", (long long)i);
+            prev = j;
+            if (w) {
+                const double v = (double)w[q];
+                if (!std::isfinite(v)) return fail(GFW_E_GRAPH, "non-finite value in row %lld", (long long)i);
+                if (p->kind == GFW_GRAPH_W && v < 0.0)
+                    return fail(GFW_E_GRAPH, "negative weight in row %lld", (long long)i);
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+            const int32_t j = ci[q];
+            const int32_t *b = ci + rp[j], *e = ci + rp[j + 1];
+            const int32_t *f = std::lower_bound(b, e, (int32_t)i);
+            if (f == e || *f != i)
+                return fail(GFW_E_GRAPH, "pattern not symmetric: (%lld,%d) has no mirror", (long long)i, j);
+            if (w && w[f - ci] != w[q])
+                return fail(GFW_E_GRAPH, "values not symmetric at (%lld,%d)", (long long)i, j);
+        }
+    }
+    return GFW_OK;
+}
+
+static gfw_status_t validate_host_labels(const gfw_problem_t *p)
+{
+    std::vector<char> seen((size_t)p->n, 0);
+    for (int64_t t = 0; t < p->n_labelled; ++t) {
+        const int32_t i = p->labelled_idx[t], c = p->labels[t];
+        if (i < 0 || i >= p->n) return fail(GFW_E_LABELS, "labelled index %d out of range", i);
+        if (seen[(size_t)i]) return fail(GFW_E_LABELS, "labelled index %d repeated", i);
+        seen[(size_t)i] = 1;
+        if (c < 0 || c >= p->K) return fail(GFW_E_LABELS, "label %d of node %d not in [0,K)", c, i);
+    }
+    return GFW_OK;
+}
+
+static gfw_status_t check_problem(const gfw_problem_t *p)
+{
+    gfw_status_t s = check_scalars(p);
+    if (s != GFW_OK || p->location != GFW_HOST) return s;
+    s = p->dtype == GFW_F32 ? validate_host_graph<float>(p) : validate_host_graph<double>(p);
+    if (s != GFW_OK) return s;
+    return validate_host_labels(p);
+}
+
+static gfw_status_t check_params(const gfw_params_t *p, int32_t K)
+{
+    if (!p) return fail(GFW_E_INVALID_ARG, "params is NULL");
+    if (!(p->eps > 0.0)) return fail(GFW_E_INVALID_ARG, "eps must be > 0 (got %g)", p->eps);
+    if (!(p->omega0 >= 0.0) || std::isinf(p->omega0)) return fail(GFW_E_INVALID_ARG, "omega0 must be finite and >= 0");
+    if (p->max_iter < 0) return fail(GFW_E_INVALID_ARG, "max_iter must be >= 0");
+    if (std::isnan(p->tol)) return fail(GFW_E_INVALID_ARG, "tol is NaN");
+    if (p->ls != GFW_LS_ARMIJO && p->ls != GFW_LS_EXACT && p->ls != GFW_LS_SHORT)
+        return fail(GFW_E_INVALID_ARG, "bad line search");
+    if (p->ls == GFW_LS_ARMIJO) {
+        if (!(p->delta > 0.0 && p->delta < 1.0)) return fail(GFW_E_INVALID_ARG, "delta must be in (0,1)");
+        if (!(p->gamma > 0.0 && p->gamma < 0.5)) return fail(GFW_E_INVALID_ARG, "gamma must be in (0,1/2)");
+    }
+    if (p->lmo != GFW_LMO_GREEDY && p->lmo != GFW_LMO_FULL) return fail(GFW_E_INVALID_ARG, "bad lmo");
+    if (p->one_shot != 0 && p->one_shot != 1) return fail(GFW_E_INVALID_ARG, "one_shot must be 0 or 1");
+    if (std::isnan(p->lipschitz)) return fail(GFW_E_INVALID_ARG, "lipschitz is NaN");
+    if (p->p_refresh < 0) return fail(GFW_E_INVALID_ARG, "p_refresh must be >= 0");
+    if (K < 2) return fail(GFW_E_INVALID_ARG, "K must be >= 2");
+    return GFW_OK;
+}
+
+// --------------------------------------------------------------------------------------
+// graph set-up
+// --------------------------------------------------------------------------------------
+
+static Shape shape_for(int64_t n, int64_t nnz, int32_t K)
+{
+    Shape s;
+    s.kmax = K <= 4 ? 4 : K <= 8 ? 8 : 16;
+    const double avg = (double)nnz / (double)n;
+    int l = 1;
+    while (l < 32 && l < avg * 0.75) l <<= 1;
+    s.lpr = l;
+    s.nb_row = (int)std::min<int64_t>(cdiv(n, kRowBlock), 2048);
+    s.nb_csr = (int)std::min<int64_t>(cdiv(n, kRowBlock / s.lpr), 8192);
+    return s;
+}
+
+static size_t dsize(gfw_dtype_t d) { return d == GFW_F32 ? 4 : 8; }
+
+static void free_graph(gfw_graph_s *g)
+{
+    if (!g) return;
+    dfree(g->row_ptr);
+    dfree(g->col);
+    dfree(g->vals);
+    dfree(g->lab);
+    Workspace &w = g->ws;
+    dfree(w.U);
+    dfree(w.P);
+    dfree(w.Q);
+    dfree(w.s0);
+    dfree(w.s1);
+    dfree(w.row_part);
+    dfree(w.lab_part);
+    dfree(w.scratch);
+    dfree(w.ctl);
+    dfree(w.hist);
+    delete g;
+}
+
+template <typename T>
+static gfw_status_t form_operator(gfw_graph_s *g, const T *wdev, hipStream_t st)
+{
+    double *dinv = nullptr, *rho = nullptr, *rmax = nullptr;
+    GFW_HIP_TRY(hipMalloc(&dinv, sizeof(double) * g->n));
+    GFW_HIP_TRY(hipMalloc(&rho, sizeof(double) * g->n));
+    GFW_HIP_TRY(hipMalloc(&rmax, sizeof(double)));
+    T *a = (T *)g->vals;
+    if (g->kind == GFW_GRAPH_W) {
+        k_degrees<T><<<grid_for(g->n, 256), 256, 0, st>>>(g->n, g->row_ptr, wdev, dinv);
+        k_scale_values<T><<<grid_for(g->n, 256), 256, 0, st>>>(g->n, g->row_ptr, g->col, wdev, dinv, a, rho);
+        g->diag_one = 1;
+    } else {
+        GFW_HIP_TRY(hipMemcpyAsync(a, wdev, sizeof(T) * g->nnz, hipMemcpyDeviceToDevice, st));
+        k_rho_plain<T><<<grid_for(g->n, 256), 256, 0, st>>>(g->n, g->row_ptr, a, rho);
+        g->diag_one = 0;
+    }
+    k_max_reduce<<<1, kFinishThreads, 0, st>>>(rho, g->n, rmax);
+    GFW_HIP_TRY(hipGetLastError());
+    GFW_HIP_TRY(hipMemcpyAsync(&g->rho_max, rmax, sizeof(double), hipMemcpyDeviceToHost, st));
+    GFW_HIP_TRY(hipStreamSynchronize(st));
+    dfree(dinv);
+    dfree(rho);
+    dfree(rmax);
+    return GFW_OK;
+}
+
+static gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st)
+{
+    gfw_status_t s = check_problem(p);
+    if (s != GFW_OK) return s;
+    GFW_HIP_TRY(hipSetDevice(ctx->device));
+    gfw_graph_s *g = new (std::nothrow) gfw_graph_s();
+    if (!g) return fail(GFW_E_NOMEM, "host allocation failed");
+    g->ctx = ctx;
+    g->n = p->n;
+    g->nnz = p->nnz;
+    g->K = p->K;
+    g->dtype = p->dtype;
+    g->kind = p->kind;
+    g->n_labelled = p->n_labelled;
+    const size_t vs = dsize(p->dtype);
+    const int64_t n = p->n, nnz = p->nnz;
+    struct Guard {
+        gfw_graph_s *g;
+        ~Guard() { if (g) free_graph(g); }
+    } guard{g};
+    auto dalloc = [&](void **ptr, size_t bytes) -> gfw_status_t {
+        hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess) return fail(GFW_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+        return GFW_OK;
+    };
+    if ((s = dalloc((void **)&g->row_ptr, 4 * (n + 1))) != GFW_OK) return s;
+    if ((s = dalloc((void **)&g->col, 4 * nnz)) != GFW_OK) return s;
+    if ((s = dalloc(&g->vals, vs * nnz)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&g->lab, 4 * n)) != GFW_OK) return s;
+
+    // raw weights staged on the device (the scaled operator overwrites g->vals later)
+    void *wraw = nullptr;
+    unsigned int *flags = nullptr;
+    if ((s = dalloc((void **)&flags, sizeof(unsigned int))) != GFW_OK) return s;
+    unsigned int zero = 0;
+    GFW_HIP_TRY(hipMemcpyAsync(flags, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+    k_fill_i32<<<grid_for(n, 256), 256, 0, st>>>(n, g->lab, -1);
+
+    if (p->location == GFW_HOST) {
+        std::vector<int32_t> rp32((size_t)n + 1);
+        for (int64_t i = 0; i <= n; ++i) rp32[(size_t)i] = (int32_t)p->row_ptr[i];
+        GFW_HIP_TRY(hipMemcpyAsync(g->row_ptr, rp32.data(), 4 * (n + 1), hipMemcpyHostToDevice, st));
+        if (nnz) GFW_HIP_TRY(hipMemcpyAsync(g->col, p->col_idx, 4 * nnz, hipMemcpyHostToDevice, st));
+        if (p->vals) {
+            if ((s = dalloc(&wraw, vs * nnz)) != GFW_OK) { dfree(flags); return s; }
+            if (nnz) GFW_HIP_TRY(hipMemcpyAsync(wraw, p->vals, vs * nnz, hipMemcpyHostToDevice, st));
+        }
+        if (p->n_labelled) {
+            int32_t *ti = nullptr, *tl = nullptr;
+            if ((s = dalloc((void **)&ti, 4 * p->n_labelled)) != GFW_OK) { dfree(flags); dfree(wraw); return s; }
+            if ((s = dalloc((void **)&tl, 4 * p->n_labelled)) != GFW_OK) { dfree(flags); dfree(wraw); dfree(ti); return s; }
+            GFW_HIP_TRY(hipMemcpyAsync(ti, p->labelled_idx, 4 * p->n_labelled, hipMemcpyHostToDevice, st));
+            GFW_HIP_TRY(hipMemcpyAsync(tl, p->labels, 4 * p->n_labelled, hipMemcpyHostToDevice, st));
+            k_scatter_labels<<<grid_for(p->n_labelled, 256), 256, 0, st>>>(n, p->n_labelled, p->K, ti, tl, g->lab, flags);
+            GFW_HIP_TRY(hipStreamSynchronize(st));
+            dfree(ti);
+            dfree(tl);
+        }
+    } else {
+        // device input: bounds of row_ptr first, then a validation kernel
+        int64_t ends[2] = {0, 0};
+        GFW_HIP_TRY(hipMemcpyAsync(&ends[0], p->row_ptr, 8, hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipMemcpyAsync(&ends[1], p->row_ptr + n, 8, hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipStreamSynchronize(st));
+        if (ends[0] != 0 || ends[1] != nnz) {
+            dfree(flags);
+            return fail(GFW_E_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+        }
+        if (p->dtype == GFW_F32)
+            k_validate_graph<float><<<grid_for(n, 256), 256, 0, st>>>(n, nnz, p->row_ptr, p->col_idx,
+                                                                     (const float *)p->vals, p->kind == GFW_GRAPH_L, flags);
+        else
+            k_validate_graph<double><<<grid_for(n, 256), 256, 0, st>>>(n, nnz, p->row_ptr, p->col_idx,
+                                                                      (const double *)p->vals, p->kind == GFW_GRAPH_L, flags);
+        if (p->n_labelled)
+            k_scatter_labels<<<grid_for(p->n_labelled, 256), 256, 0, st>>>(n, p->n_labelled, p->K, p->labelled_idx,
+                                                                             p->labels, g->lab, flags);
+        unsigned int hf = 0;
+        GFW_HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipStreamSynchronize(st));
+        if (hf & 1u) { dfree(flags); return fail(GFW_E_GRAPH, "CSR malformed (row_ptr, column range or order)"); }
+        if (hf & 4u) { dfree(flags); return fail(GFW_E_GRAPH, "negative or non-finite weight"); }
+        if (hf & 2u) { dfree(flags); return fail(GFW_E_GRAPH, "graph is not symmetric"); }
+        if (hf & 8u) { dfree(flags); return fail(GFW_E_LABELS, "labelled set invalid (range, repeat or class)"); }
+        k_rowptr_narrow<<<grid_for(n + 1, 256), 256, 0, st>>>(n, p->row_ptr, g->row_ptr);
+        if (nnz) GFW_HIP_TRY(hipMemcpyAsync(g->col, p->col_idx, 4 * nnz, hipMemcpyDeviceToDevice, st));
+        if (p->vals) {
+            if ((s = dalloc(&wraw, vs * nnz)) != GFW_OK) { dfree(flags); return s; }
+            if (nnz) GFW_HIP_TRY(hipMemcpyAsync(wraw, p->vals, vs * nnz, hipMemcpyDeviceToDevice, st));
+        }
+    }
+    GFW_HIP_TRY(hipGetLastError());
+    if (p->location == GFW_HOST) {
+        unsigned int hf = 0;
+        GFW_HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipStreamSynchronize(st));
+        if (hf) { dfree(flags); dfree(wraw); return fail(GFW_E_LABELS, "labelled set invalid"); }
+    }
+    dfree(flags);
+    s = p->dtype == GFW_F32 ? form_operator<float>(g, (const float *)wraw, st)
+                            : form_operator<double>(g, (const double *)wraw, st);
+    dfree(wraw);
+    if (s != GFW_OK) return s;
+    g->shape = shape_for(n, nnz, p->K);
+    g->graph_bytes = 4 * (n + 1) + (4 + vs) * nnz + 4 * n;
+    g->solve_bytes = 3 * vs * n * p->K + 2 * n + sizeof(double) * (kRowParts * g->shape.nb_row + g->shape.nb_csr + 64) +
+                     sizeof(Ctl);
+    guard.g = nullptr;
+    *out = g;
+    return GFW_OK;
+}
+
+static gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
+{
+    Workspace &w = g->ws;
+    const size_t vs = dsize(g->dtype);
+    const size_t nK = (size_t)g->n * g->K;
+    auto dalloc = [&](void **ptr, size_t bytes) -> gfw_status_t {
+        if (*ptr) return GFW_OK;
+        hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess) return fail(GFW_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+        return GFW_OK;
+    };
+    gfw_status_t s;
+    if ((s = dalloc(&w.U, vs * nK)) != GFW_OK) return s;
+    if ((s = dalloc(&w.P, vs * nK)) != GFW_OK) return s;
+    if ((s = dalloc(&w.Q, vs * nK)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.s0, g->n)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.s1, g->n)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.row_part, sizeof(double) * kRowParts * g->shape.nb_row)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.lab_part, sizeof(double) * g->shape.nb_csr)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.scratch, sizeof(double) * 3 * std::max(g->shape.nb_row, 64))) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.ctl, sizeof(Ctl))) != GFW_OK) return s;
+    const int64_t need = 5 * ((int64_t)max_iter + 1);
+    if (w.hist_cap < need) {
+        dfree(w.hist);
+        w.hist = nullptr;
+        if ((s = dalloc((void **)&w.hist, sizeof(double) * need)) != GFW_OK) return s;
+        w.hist_cap = need;
+    }
+    return GFW_OK;
+}
+
+// --------------------------------------------------------------------------------------
+// kernel dispatch on the K bucket and the lanes-per-row of the CSR kernels
+// --------------------------------------------------------------------------------------
+
+template <typename T, int KMAX, int LPR>
+static void launch_spmm_l(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
+{
+    k_spmm<T, KMAX, LPR><<<g->shape.nb_csr, kRowBlock, 0, st>>>(g->n, g->K, g->row_ptr, g->col, (const T *)g->vals,
+                                                                g->diag_one, U, P);
+}
+
+template <typename T, int KMAX, int LPR>
+static void launch_label_l(const gfw_graph_s *g, const uint8_t *s, T *Q, const Ctl *ctl, double *part, hipStream_t st)
+{
+    k_label<T, uint8_t, KMAX, LPR><<<g->shape.nb_csr, kRowBlock, 0, st>>>(g->n, g->K, g->row_ptr, g->col,
+                                                                          (const T *)g->vals, g->diag_one, s, Q, ctl,
+                                                                          part);
+}
+
+#define GFW_LPR_SWITCH(LPR, CALL)                  \
+    switch (LPR) {                                 \
+    case 1: { constexpr int L_ = 1; CALL; } break;  \
+    case 2: { constexpr int L_ = 2; CALL; } break;  \
+    case 4: { constexpr int L_ = 4; CALL; } break;  \
+    case 8: { constexpr int L_ = 8; CALL; } break;  \
+    case 16: { constexpr int L_ = 16; CALL; } break; \
+    default: { constexpr int L_ = 32; CALL; } break; \
+    }
+
+template <typename T, int KMAX>
+static void launch_spmm(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
+{
+    GFW_LPR_SWITCH(g->shape.lpr, (launch_spmm_l<T, KMAX, L_>(g, U, P, st)));
+}
+
+template <typename T, int KMAX>
+static void launch_label(const gfw_graph_s *g, const uint8_t *s, T *Q, const Ctl *ctl, double *part, hipStream_t st)
+{
+    GFW_LPR_SWITCH(g->shape.lpr, (launch_label_l<T, KMAX, L_>(g, s, Q, ctl, part, st)));
+}
+
+template <typename T>
+static void spmm_any(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
+{
+    switch (g->shape.kmax) {
+    case 4: launch_spmm<T, 4>(g, U, P, st); break;
+    case 8: launch_spmm<T, 8>(g, U, P, st); break;
+    default: launch_spmm<T, 16>(g, U, P, st); break;
+    }
+}
+
+static SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm)
+{
+    SolveParams sp;
+    sp.inv_eps = std::isinf(prm->eps) ? 0.0 : 1.0 / prm->eps;
+    sp.omega0 = prm->omega0;
+    sp.tol = prm->tol;
+    sp.delta = prm->delta;
+    sp.gamma = prm->gamma;
+    sp.lipschitz = prm->lipschitz > 0.0 ? prm->lipschitz : g->rho_max + 2.0 * sp.inv_eps + prm->omega0;
+    sp.ls = (int32_t)prm->ls;
+    sp.lmo = (int32_t)prm->lmo;
+    return sp;
+}
+
+template <typename T, int KMAX>
+static void launch_row(gfw_graph_s *g, int apply_only, const uint8_t *s_prev, uint8_t *s_cur, const SolveParams &sp,
+                       hipStream_t st)
+{
+    Workspace &w = g->ws;
+    k_row<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, 0, st>>>(g->n, g->K, g->lab, (T *)w.U, (T *)w.P,
+                                                                  (const T *)w.Q, s_prev, s_cur, w.ctl, sp,
+                                                                  w.row_part, apply_only);
+}
+
+template <typename T, int KMAX>
+static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_out, int32_t *labels_out,
+                               int32_t *s_out, gfw_stats_t *stats, double *history, hipStream_t st)
+{
+    gfw_status_t s = ensure_workspace(g, prm->max_iter);
+    if (s != GFW_OK) return s;
+    Workspace &w = g->ws;
+    const SolveParams sp = solve_params(g, prm);
+    T *U = (T *)w.U, *P = (T *)w.P;
+    Ctl c0;
+    std::memset(&c0, 0, sizeof(c0));
+    c0.active = prm->max_iter > 0 ? 1 : 0;
+    c0.max_iter = prm->max_iter;
+    c0.one_shot = prm->one_shot;
+    c0.last_eval = -1;
+    c0.alpha = 0.0;
+    c0.alpha_last = std::numeric_limits<double>::quiet_NaN();
+    c0.gap = std::numeric_limits<double>::quiet_NaN();
+    GFW_HIP_TRY(hipMemcpyAsync(w.ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, st));
+    const int64_t nK = g->n * g->K;
+    k_init_u<T><<<grid_for(nK, 256, 16384), 256, 0, st>>>(g->n, g->K, g->lab, (const T *)prm->U0, U);
+    spmm_any<T>(g, U, P, st);
+    const int nbr = g->shape.nb_row;
+    uint8_t *sb[2] = {w.s0, w.s1};
+    for (int32_t k = 0; k < prm->max_iter; ++k) {
+        if (prm->p_refresh > 0 && k > 0 && k % prm->p_refresh == 0) {
+            launch_row<T, KMAX>(g, 1, sb[(k + 1) & 1], sb[k & 1], sp, st);
+            k_clear_pending<<<1, 64, 0, st>>>(w.ctl);
+            spmm_any<T>(g, U, P, st);
+        }
+        launch_row<T, KMAX>(g, 0, sb[(k + 1) & 1], sb[k & 1], sp, st);
+        launch_label<T, KMAX>(g, sb[k & 1], (T *)w.Q, w.ctl, w.lab_part, st);
+        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, nbr, w.lab_part, g->shape.nb_csr, w.ctl, sp,
+                                               w.hist, prm->max_iter + 1);
+    }
+    // commit the last pending update
+    const int kl = prm->max_iter;
+    launch_row<T, KMAX>(g, 1, sb[(kl + 1) & 1], sb[kl & 1], sp, st);
+    GFW_HIP_TRY(hipGetLastError());
+    if (U_out) GFW_HIP_TRY(hipMemcpyAsync(U_out, U, sizeof(T) * nK, hipMemcpyDeviceToDevice, st));
+    if (labels_out || s_out)
+        k_outputs<T, uint8_t><<<grid_for(g->n, 256), 256, 0, st>>>(g->n, g->K, U, w.s0, w.s1, w.ctl, labels_out,
+                                                                  s_out);
+    GFW_HIP_TRY(hipGetLastError());
+    if (stats || history) {
+        Ctl ch;
+        GFW_HIP_TRY(hipMemcpyAsync(&ch, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        std::vector<double> hh;
+        if (history) {
+            hh.resize(5 * ((size_t)prm->max_iter + 1));
+            GFW_HIP_TRY(hipMemcpyAsync(hh.data(), w.hist, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, st));
+        }
+        GFW_HIP_TRY(hipStreamSynchronize(st));
+        if (history) {
+            const int64_t hs = (int64_t)prm->max_iter + 1;
+            const int32_t nev = ch.last_eval + 1; // evaluated iterates
+            for (int64_t t = 0; t < 5 * hs; ++t) {
+                const int64_t k = t % hs;
+                history[t] = k < nev ? hh[(size_t)t] : std::numeric_limits<double>::quiet_NaN();
+            }
+        }
+        if (stats) {
+            stats->iters = ch.iters;
+            stats->stop_reason = ch.stop_reason;
+            stats->gap = ch.gap;
+            stats->alpha_last = ch.alpha_last;
+            stats->objective = std::numeric_limits<double>::quiet_NaN();
+        }
+    }
+    return GFW_OK;
+}
+
+template <typename T>
+static gfw_status_t objective_impl(gfw_graph_s *g, const gfw_params_t *prm, const T *U, double *E, hipStream_t st)
+{
+    gfw_status_t s = ensure_workspace(g, 0);
+    if (s != GFW_OK) return s;
+    T *P = (T *)g->ws.Q; // Q is free between solves
+    spmm_any<T>(g, U, P, st);
+    const int nb = g->shape.nb_row;
+    k_energy_rows<T><<<nb, kRowBlock, 0, st>>>(g->n, g->K, g->lab, U, P, prm->omega0, g->ws.scratch);
+    k_sum_parts<<<1, kFinishThreads, 0, st>>>(g->ws.scratch, nb, 3, g->ws.row_part);
+    double t[3];
+    GFW_HIP_TRY(hipGetLastError());
+    GFW_HIP_TRY(hipMemcpyAsync(t, g->ws.row_part, sizeof(t), hipMemcpyDeviceToHost, st));
+    GFW_HIP_TRY(hipStreamSynchronize(st));
+    const double inv_eps = std::isinf(prm->eps) ? 0.0 : 1.0 / prm->eps;
+    *E = 0.5 * t[0] + inv_eps * t[1] + 0.5 * t[2];
+    return GFW_OK;
+}
+
+} // namespace gfw
+
+using namespace gfw;
+
+// ======================================================================================
+// exported C ABI
+// ======================================================================================
+
+extern "C" {
+
+const char *gfw_status_string(gfw_status_t s)
+{
+    switch (s) {
+    case GFW_OK: return "ok";
+    case GFW_E_INVALID_ARG: return "invalid argument";
+    case GFW_E_GRAPH: return "malformed graph";
+    case GFW_E_LABELS: return "invalid labelled set";
+    case GFW_E_NOMEM: return "out of device memory";
+    case GFW_E_HIP: return "HIP runtime error";
+    case GFW_E_UNSUPPORTED: return "unsupported";
+    case GFW_E_BUDGET: return "over the HBM budget";
+    case GFW_E_NOT_READY: return "not ready";
+    case GFW_E_NUMERIC: return "numeric failure (NaN)";
+    }
+    return "unknown status";
+}
+
+const char *gfw_last_error(void) { return gfw::g_last_error; }
+
+void gfw_params_default(gfw_params_t *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->eps = 50.0;
+    p->omega0 = 1000.0;
+    p->max_iter = 30;
+    p->tol = 1e-6;
+    p->ls = GFW_LS_ARMIJO;
+    p->delta = 0.5;
+    p->gamma = 1e-6;
+    p->lmo = GFW_LMO_GREEDY;
+    p->one_shot = 0;
+    p->lipschitz = 0.0;
+    p->U0 = nullptr;
+    p->p_refresh = 0;
+}
+
+gfw_status_t gfw_check_problem(const gfw_problem_t *p) { return check_problem(p); }
+
+gfw_status_t gfw_check_params(const gfw_params_t *p, int32_t K) { return check_params(p, K); }
+
+gfw_status_t gfw_context_create(gfw_context_t *ctx, int device)
+{
+    if (!ctx) return fail(GFW_E_INVALID_ARG, "ctx is NULL");
+    *ctx = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return fail(GFW_E_HIP, "no HIP device available");
+    if (device < 0 || device >= count) return fail(GFW_E_INVALID_ARG, "device %d out of range", device);
+    hipDeviceProp_t prop;
+    GFW_HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GFW_E_UNSUPPORTED, "device %d is %s, this library is built for gfx950", device, prop.gcnArchName);
+    gfw_context_s *c = new (std::nothrow) gfw_context_s();
+    if (!c) return fail(GFW_E_NOMEM, "host allocation failed");
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    *ctx = c;
+    return GFW_OK;
+}
+
+gfw_status_t gfw_context_destroy(gfw_context_t ctx)
+{
+    delete ctx;
+    return GFW_OK;
+}
+
+gfw_status_t gfw_graph_create(gfw_context_t ctx, const gfw_problem_t *p, gfw_graph_t *out, void *stream)
+{
+    if (!ctx || !out) return fail(GFW_E_INVALID_ARG, "ctx or out is NULL");
+    *out = nullptr;
+    return graph_create(ctx, p, out, (hipStream_t)stream);
+}
+
+gfw_status_t gfw_graph_destroy(gfw_graph_t g)
+{
+    if (g) (void)hipDeviceSynchronize();
+    free_graph(g);
+    return GFW_OK;
+}
+
+gfw_status_t gfw_graph_footprint(gfw_graph_t g, size_t *graph_bytes, size_t *solve_bytes)
+{
+    if (!g) return fail(GFW_E_INVALID_ARG, "graph is NULL");
+    if (graph_bytes) *graph_bytes = g->graph_bytes;
+    if (solve_bytes) *solve_bytes = g->solve_bytes;
+    return GFW_OK;
+}
+
+gfw_status_t gfw_solve(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm, void *U_out, int32_t *labels_out,
+                       int32_t *s_out, gfw_stats_t *stats, double *history, void *stream)
+{
+    if (!ctx || !g) return fail(GFW_E_INVALID_ARG, "ctx or graph is NULL");
+    gfw_status_t s = check_params(prm, g->K);
+    if (s != GFW_OK) return s;
+    if (g->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by this build");
+    GFW_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    if (g->dtype == GFW_F32) {
+        switch (g->shape.kmax) {
+        case 4: s = solve_impl<float, 4>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
+        case 8: s = solve_impl<float, 8>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
+        default: s = solve_impl<float, 16>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
+        }
+    } else {
+        switch (g->shape.kmax) {
+        case 4: s = solve_impl<double, 4>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
+        case 8: s = solve_impl<double, 8>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
+        default: s = solve_impl<double, 16>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
+        }
+    }
+    if (s != GFW_OK) return s;
+    if (stats) {
+        double E = 0.0;
+        s = g->dtype == GFW_F32 ? objective_impl<float>(g, prm, (const float *)g->ws.U, &E, st)
+                                : objective_impl<double>(g, prm, (const double *)g->ws.U, &E, st);
+        if (s != GFW_OK) return s;
+        stats->objective = E;
+        if (stats->stop_reason == GFW_STOP_NUMERIC) return fail(GFW_E_NUMERIC, "NaN met during the iteration");
+    }
+    return GFW_OK;
+}
+
+gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm, const void *U, double *E_host,
+                           void *stream)
+{
+    if (!ctx || !g || !U || !E_host) return fail(GFW_E_INVALID_ARG, "NULL argument");
+    gfw_status_t s = check_params(prm, g->K);
+    if (s != GFW_OK) return s;
+    if (g->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by this build");
+    GFW_HIP_TRY(hipSetDevice(ctx->device));
+    return g->dtype == GFW_F32 ? objective_impl<float>(g, prm, (const float *)U, E_host, (hipStream_t)stream)
+                               : objective_impl<double>(g, prm, (const double *)U, E_host, (hipStream_t)stream);
+}
+
+gfw_status_t gfw_spmm(gfw_context_t ctx, gfw_graph_t g, const void *U, void *P, void *stream)
+{
+    if (!ctx || !g || !U || !P) return fail(GFW_E_INVALID_ARG, "NULL argument");
+    if (g->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by this build");
+    GFW_HIP_TRY(hipSetDevice(ctx->device));
+    if (g->dtype == GFW_F32) spmm_any<float>(g, (const float *)U, (float *)P, (hipStream_t)stream);
+    else spmm_any<double>(g, (const double *)U, (double *)P, (hipStream_t)stream);
+    GFW_HIP_TRY(hipGetLastError());
+    return GFW_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,69 @@
+// Internal declarations shared by the host-side translation units of libgfw.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/gfw.h"
+#include "gfw_kernels.h"
+
+namespace gfw {
+
+void set_error(const char *fmt, ...);
+
+#define GFW_HIP_TRY(expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            ::gfw::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                             __LINE__);                                                     \
+            return GFW_E_HIP;                                                               \
+        }                                                                                   \
+    } while (0)
+
+// Per-solve device workspace, owned by a graph (one solve at a time per graph).
+struct Workspace {
+    void *U = nullptr, *P = nullptr, *Q = nullptr; // n x K of the graph dtype
+    uint8_t *s0 = nullptr, *s1 = nullptr;          // vertex indices (ping-pong)
+    double *row_part = nullptr, *lab_part = nullptr, *scratch = nullptr;
+    Ctl *ctl = nullptr;
+    double *hist = nullptr;
+    int64_t hist_cap = 0;
+};
+
+// Launch shape derived from the graph (fixed per graph, so reductions are deterministic
+// for that graph whatever else runs).
+struct Shape {
+    int kmax = 4;       // register bucket for K
+    int lpr = 8;        // lanes per row of the CSR kernels
+    int nb_row = 1;     // blocks of the row kernel
+    int nb_csr = 1;     // blocks of the CSR kernels
+};
+
+} // namespace gfw
+
+struct gfw_context_s {
+    int device = 0;
+    int num_cu = 0;
+    std::string arch;
+};
+
+struct gfw_graph_s {
+    gfw_context_s *ctx = nullptr;
+    int64_t n = 0, nnz = 0;
+    int32_t K = 0;
+    gfw_dtype_t dtype = GFW_F32;
+    gfw_graph_kind_t kind = GFW_GRAPH_W;
+    int32_t *row_ptr = nullptr; // int32[n+1]
+    int32_t *col = nullptr;     // int32[nnz]
+    void *vals = nullptr;       // scaled operator values, dtype[nnz]
+    int32_t *lab = nullptr;     // int32[n], class of labelled nodes, -1 elsewhere
+    int64_t n_labelled = 0;
+    double rho_max = 0.0;       // max Gershgorin radius of the operator
+    int diag_one = 1;           // 1: operator is I + A (kind W); 0: operator is A (kind L)
+    gfw::Shape shape;
+    gfw::Workspace ws;
+    size_t graph_bytes = 0, solve_bytes = 0;
+};

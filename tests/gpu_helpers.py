@@ -1,0 +1,103 @@
+"""Helpers shared by the GPU tests: one synthetic instance handed to both the oracle and
+the HIP library, and comparisons with near-tie accounting."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_2508_09738_amd import gfw
+
+
+def say(*a):
+    """Print and flush, so that the case under test is named before any GPU step."""
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+_ctx = None
+
+
+def ctx():
+    global _ctx
+    if _ctx is None:
+        _ctx = gfw.Context(0)
+    return _ctx
+
+
+def gpu_graph(graph, K, idx, lab, dtype=gfw.F32, kind=gfw.GRAPH_W, data="graph"):
+    data = graph.data if data == "graph" else data
+    return gfw.Graph.from_host(ctx(), graph.n, K, graph.indptr, graph.indices, data, idx, lab, dtype, kind)
+
+
+def torch_u(U, dtype):
+    import torch
+    return torch.tensor(np.ascontiguousarray(U), dtype=torch.float32 if dtype == gfw.F32 else torch.float64,
+                        device="cuda")
+
+
+def glmo_margin(U, G, mode=O.LMO_GREEDY):
+    """Per row: gap between the smallest and second smallest G over the GLMO's candidate set
+    (inf where there is a single candidate or the row is kept as binary)."""
+    n, K = U.shape
+    m = np.full(n, np.inf)
+    for i in range(n):
+        binary = np.all((U[i] == 0) | (U[i] == 1))
+        if binary and mode == O.LMO_GREEDY:
+            continue
+        cand = np.sort(G[i][(U[i] != 0) | (mode == O.LMO_FULL)])
+        if cand.size >= 2:
+            m[i] = cand[1] - cand[0]
+    return m
+
+
+def armijo_ratio_near_power(g, q, gamma=1e-6, delta=0.5, rel=1e-6):
+    """True if the Armijo bound 2 (1 - gamma) g / q lies within `rel` of a power of delta."""
+    if not (q > 0):
+        return False
+    r = 2 * (1 - gamma) * g / q
+    if r >= 1:
+        return abs(r - 1) <= rel
+    j = math.log(r) / math.log(delta)
+    for jj in (math.floor(j), math.ceil(j)):
+        if abs(delta ** jj - r) <= rel * r:
+            return True
+    return False
+
+
+def relabelled(prob, seed):
+    """The same problem with its nodes renumbered by a random permutation (an equivalent
+    problem whose FP64 evaluation order differs).  Returns (problem, perm) with perm[i] the
+    new index of node i."""
+    import scipy.sparse as sp
+
+    from synth import configs, graphs
+
+    g = prob.graph
+    n = g.n
+    perm = np.random.default_rng(seed).permutation(n)
+    inv = np.argsort(perm)
+    W = sp.csr_matrix((g.data, g.indices, g.indptr), shape=(n, n))
+    Pm = sp.csr_matrix((np.ones(n), (perm, np.arange(n))), shape=(n, n))
+    W2 = (Pm @ W @ Pm.T).tocsr()
+    W2.sort_indices()
+    g2 = graphs.Graph(n, g.K, W2.indptr.astype(np.int64), W2.indices.astype(np.int32), W2.data, g.truth[inv])
+    idx2 = perm[prob.labelled_idx].astype(np.int32)
+    o = np.argsort(idx2)
+    p2 = configs.Problem(g2, idx2[o], prob.labels[o], prob.K, prob.dtype, prob.eps, prob.omega0, prob.max_iter,
+                         prob.tol)
+    return p2, perm
+
+
+def oracle_order_spread(prob, seeds=(0, 1, 2)):
+    """Largest |E - E'| / |E| between the oracle's free-running result and its results on
+    relabelled copies of the problem: the spread that rounding-level tie breaks alone give."""
+    r0 = O.solve_problem(prob)
+    worst = 0.0
+    for s in seeds:
+        p2, _ = relabelled(prob, s)
+        r = O.solve_problem(p2)
+        worst = max(worst, abs(r["objective"] - r0["objective"]) / abs(r0["objective"]))
+    return r0, worst
