@@ -200,6 +200,24 @@ GFW_API gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_p
 /* P = L_s U (the graph-Laplacian times n x K product of eq. gradgl_vv2g); DEVICE U, P. */
 GFW_API gfw_status_t gfw_spmm(gfw_context_t ctx, gfw_graph_t g, const void *U, void *P, void *stream);
 
+/* ---- tracing ------------------------------------------------------------------------ */
+/* Kernel classes of the hot path, for gfw_trace_get. */
+typedef enum {
+    GFW_KERNEL_ROW = 0,    /* pending update + gradient + GLMO + per-row partials           */
+    GFW_KERNEL_LABEL = 1,  /* L_s S with one-hot S (label pass)                            */
+    GFW_KERNEL_FINISH = 2, /* reductions, step size, stop test                             */
+    GFW_KERNEL_SPMM = 3,   /* L_s U                                                          */
+    GFW_KERNEL_FUSED = 4,  /* persistent single-launch iteration kernel                      */
+    GFW_KERNEL_COUNT = 5
+} gfw_kernel_t;
+/* When enabled, every hot-path launch made through ctx is bracketed by HIP events on the
+ * launch stream; durations are accumulated when the owning call completes (tracing makes
+ * gfw_solve synchronise its stream).  gfw_trace_get returns the summed milliseconds and
+ * the launch count of a kernel class since the last reset. */
+GFW_API gfw_status_t gfw_trace_enable(gfw_context_t ctx, int enable);
+GFW_API gfw_status_t gfw_trace_reset(gfw_context_t ctx);
+GFW_API gfw_status_t gfw_trace_get(gfw_context_t ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
 /* ---- serving ------------------------------------------------------------------------ */
 /*
  * A request server: submitted problems (HOST arrays, copied at submit) are admitted while

@@ -48,6 +48,55 @@ static int grid_for(int64_t work, int threads, int cap = 65535)
 }
 
 // --------------------------------------------------------------------------------------
+// tracing
+// --------------------------------------------------------------------------------------
+
+static hipEvent_t pool_event(gfw_context_s *c)
+{
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+hipEvent_t trace_begin(gfw_context_s *c, hipStream_t st)
+{
+    if (!c || !c->trace) return nullptr;
+    hipEvent_t a = pool_event(c);
+    if (a) (void)hipEventRecord(a, st);
+    return a;
+}
+
+void trace_end(gfw_context_s *c, int kernel, hipEvent_t a, hipStream_t st)
+{
+    if (!c || !c->trace || !a) return;
+    hipEvent_t b = pool_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    c->pending.push_back({kernel, a, b});
+}
+
+gfw_status_t trace_flush(gfw_context_s *c, hipStream_t st)
+{
+    if (!c || c->pending.empty()) {
+        if (c) c->ev_used = 0;
+        return GFW_OK;
+    }
+    GFW_HIP_TRY(hipStreamSynchronize(st));
+    for (const auto &r : c->pending) {
+        float ms = 0.f;
+        GFW_HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        c->trace_ms[r.kernel] += ms;
+        c->trace_n[r.kernel] += 1;
+    }
+    c->pending.clear();
+    c->ev_used = 0;
+    return GFW_OK;
+}
+
+// --------------------------------------------------------------------------------------
 // host validation (shared by gfw_check_problem and gfw_graph_create for host input)
 // --------------------------------------------------------------------------------------
 
@@ -165,9 +214,9 @@ static Shape shape_for(int64_t n, int64_t nnz, int32_t K)
     s.kmax = K <= 4 ? 4 : K <= 8 ? 8 : 16;
     const double avg = (double)nnz / (double)n;
     int l = 1;
-    while (l < 32 && l < avg * 0.75) l <<= 1;
+    while (l < 32 && l < avg * 0.25) l <<= 1;
     s.lpr = l;
-    s.nb_row = (int)std::min<int64_t>(cdiv(n, kRowBlock), 2048);
+    s.nb_row = (int)cdiv(n, kRowBlock);
     s.nb_csr = (int)std::min<int64_t>(cdiv(n, kRowBlock / s.lpr), 8192);
     return s;
 }
@@ -192,6 +241,11 @@ static void free_graph(gfw_graph_s *g)
     dfree(w.scratch);
     dfree(w.ctl);
     dfree(w.hist);
+    if (w.iter_exec) (void)hipGraphExecDestroy(w.iter_exec);
+    if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
+    if (w.h_flag) (void)hipHostFree(w.h_flag);
+    for (int i = 0; i < 2; ++i)
+        if (w.poll_ev[i]) (void)hipEventDestroy(w.poll_ev[i]);
     delete g;
 }
 
@@ -327,7 +381,7 @@ static gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw
     if (s != GFW_OK) return s;
     g->shape = shape_for(n, nnz, p->K);
     g->graph_bytes = 4 * (n + 1) + (4 + vs) * nnz + 4 * n;
-    g->solve_bytes = 3 * vs * n * p->K + 2 * n + sizeof(double) * (kRowParts * g->shape.nb_row + g->shape.nb_csr + 64) +
+    g->solve_bytes = 3 * vs * n * p->K + 2 * n + sizeof(double) * ((kRowParts + 4) * g->shape.nb_row + 64) +
                      sizeof(Ctl);
     guard.g = nullptr;
     *out = g;
@@ -352,7 +406,7 @@ static gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
     if ((s = dalloc((void **)&w.s0, g->n)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.s1, g->n)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.row_part, sizeof(double) * kRowParts * g->shape.nb_row)) != GFW_OK) return s;
-    if ((s = dalloc((void **)&w.lab_part, sizeof(double) * g->shape.nb_csr)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.lab_part, sizeof(double) * g->shape.nb_row)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.scratch, sizeof(double) * 3 * std::max(g->shape.nb_row, 64))) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.ctl, sizeof(Ctl))) != GFW_OK) return s;
     const int64_t need = 5 * ((int64_t)max_iter + 1);
@@ -376,14 +430,6 @@ static void launch_spmm_l(const gfw_graph_s *g, const T *U, T *P, hipStream_t st
                                                                 g->diag_one, U, P);
 }
 
-template <typename T, int KMAX, int LPR>
-static void launch_label_l(const gfw_graph_s *g, const uint8_t *s, T *Q, const Ctl *ctl, double *part, hipStream_t st)
-{
-    k_label<T, uint8_t, KMAX, LPR><<<g->shape.nb_csr, kRowBlock, 0, st>>>(g->n, g->K, g->row_ptr, g->col,
-                                                                          (const T *)g->vals, g->diag_one, s, Q, ctl,
-                                                                          part);
-}
-
 #define GFW_LPR_SWITCH(LPR, CALL)                  \
     switch (LPR) {                                 \
     case 1: { constexpr int L_ = 1; CALL; } break;  \
@@ -401,9 +447,13 @@ static void launch_spmm(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
 }
 
 template <typename T, int KMAX>
-static void launch_label(const gfw_graph_s *g, const uint8_t *s, T *Q, const Ctl *ctl, double *part, hipStream_t st)
+static void launch_label(const gfw_graph_s *g, const uint8_t *s0, const uint8_t *s1, T *Q, const Ctl *ctl,
+                         double *part, hipStream_t st)
 {
-    GFW_LPR_SWITCH(g->shape.lpr, (launch_label_l<T, KMAX, L_>(g, s, Q, ctl, part, st)));
+    const size_t lds = sizeof(T) * kRowBlock * g->K;
+    k_label<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(g->n, g->K, g->row_ptr, g->col,
+                                                                      (const T *)g->vals, g->diag_one, s0, s1, Q,
+                                                                      ctl, part);
 }
 
 template <typename T>
@@ -431,13 +481,57 @@ static SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm)
 }
 
 template <typename T, int KMAX>
-static void launch_row(gfw_graph_s *g, int apply_only, const uint8_t *s_prev, uint8_t *s_cur, const SolveParams &sp,
-                       hipStream_t st)
+static void launch_row(gfw_graph_s *g, int apply_only, hipStream_t st)
 {
     Workspace &w = g->ws;
-    k_row<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, 0, st>>>(g->n, g->K, g->lab, (T *)w.U, (T *)w.P,
-                                                                  (const T *)w.Q, s_prev, s_cur, w.ctl, sp,
-                                                                  w.row_part, apply_only);
+    const size_t lds = 3 * sizeof(T) * kRowBlock * g->K;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    k_row<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(g->n, g->K, g->lab, (T *)w.U, (T *)w.P,
+                                                                    (const T *)w.Q, w.s0, w.s1, w.ctl,
+                                                                    w.row_part, apply_only);
+}
+
+// One GFW iteration (row kernel, label pass, finish), optionally bracketed by trace events.
+// The iteration index lives in the device control block.
+template <typename T, int KMAX>
+static void launch_iteration(gfw_graph_s *g, hipStream_t st, bool traced)
+{
+    Workspace &w = g->ws;
+    gfw_context_s *cx = traced ? g->ctx : nullptr;
+    hipEvent_t ev = trace_begin(cx, st);
+    launch_row<T, KMAX>(g, 0, st);
+    trace_end(cx, GFW_KERNEL_ROW, ev, st);
+    ev = trace_begin(cx, st);
+    launch_label<T, KMAX>(g, w.s0, w.s1, (T *)w.Q, w.ctl, w.lab_part, st);
+    trace_end(cx, GFW_KERNEL_LABEL, ev, st);
+    ev = trace_begin(cx, st);
+    k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, g->shape.nb_row, w.lab_part, g->shape.nb_row, w.ctl);
+    trace_end(cx, GFW_KERNEL_FINISH, ev, st);
+}
+
+constexpr int kGraphChunk = 16; // iterations per captured graph
+
+// Captures kGraphChunk iterations once per graph object; the kernels take all per-solve
+// values from the device control block, so the same executable graph serves every solve.
+template <typename T, int KMAX>
+static gfw_status_t ensure_iteration_graph(gfw_graph_s *g)
+{
+    Workspace &w = g->ws;
+    if (w.iter_exec) return GFW_OK;
+    if (!w.cap_stream) GFW_HIP_TRY(hipStreamCreateWithFlags(&w.cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    GFW_HIP_TRY(hipStreamBeginCapture(w.cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int c = 0; c < kGraphChunk; ++c) launch_iteration<T, KMAX>(g, w.cap_stream, false);
+    GFW_HIP_TRY(hipStreamEndCapture(w.cap_stream, &graph));
+    hipError_t e = hipGraphInstantiate(&w.iter_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        w.iter_exec = nullptr;
+        return fail(GFW_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    return GFW_OK;
 }
 
 template <typename T, int KMAX>
@@ -447,7 +541,6 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     gfw_status_t s = ensure_workspace(g, prm->max_iter);
     if (s != GFW_OK) return s;
     Workspace &w = g->ws;
-    const SolveParams sp = solve_params(g, prm);
     T *U = (T *)w.U, *P = (T *)w.P;
     Ctl c0;
     std::memset(&c0, 0, sizeof(c0));
@@ -458,27 +551,49 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     c0.alpha = 0.0;
     c0.alpha_last = std::numeric_limits<double>::quiet_NaN();
     c0.gap = std::numeric_limits<double>::quiet_NaN();
+    c0.sp = solve_params(g, prm);
+    c0.hist = w.hist;
+    c0.hist_stride = prm->max_iter + 1;
     GFW_HIP_TRY(hipMemcpyAsync(w.ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, st));
     const int64_t nK = g->n * g->K;
     k_init_u<T><<<grid_for(nK, 256, 16384), 256, 0, st>>>(g->n, g->K, g->lab, (const T *)prm->U0, U);
+    gfw_context_s *cx = g->ctx;
+    hipEvent_t ev = trace_begin(cx, st);
     spmm_any<T>(g, U, P, st);
-    const int nbr = g->shape.nb_row;
-    uint8_t *sb[2] = {w.s0, w.s1};
-    for (int32_t k = 0; k < prm->max_iter; ++k) {
-        if (prm->p_refresh > 0 && k > 0 && k % prm->p_refresh == 0) {
-            launch_row<T, KMAX>(g, 1, sb[(k + 1) & 1], sb[k & 1], sp, st);
-            k_clear_pending<<<1, 64, 0, st>>>(w.ctl);
-            spmm_any<T>(g, U, P, st);
+    trace_end(cx, GFW_KERNEL_SPMM, ev, st);
+    const bool use_graph = !cx->trace && prm->p_refresh == 0 && prm->max_iter >= kGraphChunk;
+    if (use_graph) {
+        if ((s = ensure_iteration_graph<T, KMAX>(g)) != GFW_OK) return s;
+        if (!w.h_flag) GFW_HIP_TRY(hipHostMalloc((void **)&w.h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+        for (int i = 0; i < 2; ++i)
+            if (!w.poll_ev[i]) GFW_HIP_TRY(hipEventCreateWithFlags(&w.poll_ev[i], hipEventDisableTiming));
+        // replays; extra iterations past the stop are no-ops.  The stop flag is read back one
+        // replay behind, so the queue always holds a replay while the host waits.
+        const int reps = (int)cdiv(prm->max_iter, kGraphChunk);
+        for (int r = 0; r < reps; ++r) {
+            GFW_HIP_TRY(hipGraphLaunch(w.iter_exec, st));
+            if (prm->tol < 0.0 && !prm->one_shot) continue; // no early stop to watch for
+            GFW_HIP_TRY(hipMemcpyAsync(&w.h_flag[r & 1], &w.ctl->active, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            GFW_HIP_TRY(hipEventRecord(w.poll_ev[r & 1], st));
+            if (r >= 1) {
+                GFW_HIP_TRY(hipEventSynchronize(w.poll_ev[(r - 1) & 1]));
+                if (w.h_flag[(r - 1) & 1] == 0) break;
+            }
         }
-        launch_row<T, KMAX>(g, 0, sb[(k + 1) & 1], sb[k & 1], sp, st);
-        launch_label<T, KMAX>(g, sb[k & 1], (T *)w.Q, w.ctl, w.lab_part, st);
-        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, nbr, w.lab_part, g->shape.nb_csr, w.ctl, sp,
-                                               w.hist, prm->max_iter + 1);
+    } else {
+        for (int32_t k = 0; k < prm->max_iter; ++k) {
+            if (prm->p_refresh > 0 && k > 0 && k % prm->p_refresh == 0) {
+                launch_row<T, KMAX>(g, 1, st);
+                k_clear_pending<<<1, 64, 0, st>>>(w.ctl);
+                spmm_any<T>(g, U, P, st);
+            }
+            launch_iteration<T, KMAX>(g, st, cx->trace);
+        }
     }
     // commit the last pending update
-    const int kl = prm->max_iter;
-    launch_row<T, KMAX>(g, 1, sb[(kl + 1) & 1], sb[kl & 1], sp, st);
+    launch_row<T, KMAX>(g, 1, st);
     GFW_HIP_TRY(hipGetLastError());
+    if ((s = trace_flush(cx, st)) != GFW_OK) return s;
     if (U_out) GFW_HIP_TRY(hipMemcpyAsync(U_out, U, sizeof(T) * nK, hipMemcpyDeviceToDevice, st));
     if (labels_out || s_out)
         k_outputs<T, uint8_t><<<grid_for(g->n, 256), 256, 0, st>>>(g->n, g->K, U, w.s0, w.s1, w.ctl, labels_out,
@@ -605,6 +720,8 @@ gfw_status_t gfw_context_create(gfw_context_t *ctx, int device)
 
 gfw_status_t gfw_context_destroy(gfw_context_t ctx)
 {
+    if (ctx)
+        for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     return GFW_OK;
 }
@@ -675,6 +792,32 @@ gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t 
     GFW_HIP_TRY(hipSetDevice(ctx->device));
     return g->dtype == GFW_F32 ? objective_impl<float>(g, prm, (const float *)U, E_host, (hipStream_t)stream)
                                : objective_impl<double>(g, prm, (const double *)U, E_host, (hipStream_t)stream);
+}
+
+gfw_status_t gfw_trace_enable(gfw_context_t ctx, int enable)
+{
+    if (!ctx) return fail(GFW_E_INVALID_ARG, "ctx is NULL");
+    ctx->trace = enable != 0;
+    return GFW_OK;
+}
+
+gfw_status_t gfw_trace_reset(gfw_context_t ctx)
+{
+    if (!ctx) return fail(GFW_E_INVALID_ARG, "ctx is NULL");
+    for (int k = 0; k < GFW_KERNEL_COUNT; ++k) {
+        ctx->trace_ms[k] = 0.0;
+        ctx->trace_n[k] = 0;
+    }
+    return GFW_OK;
+}
+
+gfw_status_t gfw_trace_get(gfw_context_t ctx, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!ctx) return fail(GFW_E_INVALID_ARG, "ctx is NULL");
+    if (kernel < 0 || kernel >= GFW_KERNEL_COUNT) return fail(GFW_E_INVALID_ARG, "bad kernel id %d", kernel);
+    if (total_ms) *total_ms = ctx->trace_ms[kernel];
+    if (launches) *launches = ctx->trace_n[kernel];
+    return GFW_OK;
 }
 
 gfw_status_t gfw_spmm(gfw_context_t ctx, gfw_graph_t g, const void *U, void *P, void *stream)

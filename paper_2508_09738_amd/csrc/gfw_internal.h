@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/gfw.h"
 #include "gfw_kernels.h"
@@ -31,6 +32,11 @@ struct Workspace {
     Ctl *ctl = nullptr;
     double *hist = nullptr;
     int64_t hist_cap = 0;
+    // captured chunk of iterations (depends only on the buffers above)
+    hipGraphExec_t iter_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int32_t *h_flag = nullptr; // pinned host copies of the active flag
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
 };
 
 // Launch shape derived from the graph (fixed per graph, so reductions are deterministic
@@ -48,7 +54,27 @@ struct gfw_context_s {
     int device = 0;
     int num_cu = 0;
     std::string arch;
+    // tracing: events bracketing hot-path launches, resolved when the owning call ends
+    bool trace = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Rec {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    double trace_ms[GFW_KERNEL_COUNT] = {};
+    int64_t trace_n[GFW_KERNEL_COUNT] = {};
 };
+
+namespace gfw {
+// Records a start event for a traced launch (no-op when tracing is off); returns the
+// event to hand to trace_end.
+hipEvent_t trace_begin(gfw_context_s *c, hipStream_t st);
+void trace_end(gfw_context_s *c, int kernel, hipEvent_t a, hipStream_t st);
+// Waits for `st` and folds the pending records into the totals.
+gfw_status_t trace_flush(gfw_context_s *c, hipStream_t st);
+} // namespace gfw
 
 struct gfw_graph_s {
     gfw_context_s *ctx = nullptr;

@@ -24,21 +24,26 @@
 namespace gfw {
 
 constexpr int kRowBlock = 256;     // threads per block of the row-wise kernels
-constexpr int kFinishThreads = 1024;
-constexpr int kRowParts = 8;       // per-row partial sums written by the row kernel
-// partial slots of the row kernel
+constexpr int kFinishThreads = 512;
+constexpr int kRowParts = 5;       // per-row partial sums written by the row kernel
+// partial slots of the row kernel (per-row quantities combined in FP64 before summing)
 enum : int {
-    PART_GAP = 0,   // sum_c G_ic (u_ic - S_ic)               -> g_k
-    PART_UP = 1,    // <u_i, P_i>                              -> <U, L_s U>
-    PART_PS = 2,    // P_{i, s_i}                              -> <S, L_s U>
-    PART_DD = 3,    // ||d_i||^2                               -> ||D||^2
-    PART_WDD = 4,   // omega_i ||d_i||^2
-    PART_PEN = 5,   // sum_c u_ic (1 - u_ic)                   -> penalty
-    PART_FID = 6,   // omega_i ||uhat_i - u_i||^2              -> fidelity
-    PART_NB = 7     // 1 if row i is not binary
+    PART_GAP = 0,   // sum_c G_ic (u_ic - S_ic)                                   -> g_k
+    PART_E = 1,     // 1/2 <u_i,P_i> + (1/eps) sum_c u_ic(1-u_ic) + omega_i/2 ||uhat_i-u_i||^2 -> E(U_k)
+    PART_CURV = 2,  // <u_i,P_i> - 2 P_{i,s_i} - (2/eps)||d_i||^2 + omega_i ||d_i||^2
+                    //   -> q_k once <S, L_s S> (label pass) is added
+    PART_DD = 3,    // ||d_i||^2                                                  -> ||D||^2
+    PART_NB = 4     // 1 if row i is not binary
 };
 
-// Device-resident control block of one solve (written by the finish kernel only).
+struct SolveParams {
+    double inv_eps, omega0, tol, delta, gamma, lipschitz;
+    int32_t ls, lmo;
+};
+
+// Device-resident control block of one solve.  Written by the host before the first
+// launch and afterwards by the finish kernel only; every kernel reads its parameters from
+// here, so that a captured chunk of iterations carries no per-solve argument.
 struct Ctl {
     int32_t active;      // iteration `k` is to be evaluated
     int32_t pending;     // an update with `alpha` is due before the next evaluation
@@ -52,11 +57,10 @@ struct Ctl {
     double alpha_last;
     double gap;          // last g_k
     double E_last;       // last E(U_k)
-};
-
-struct SolveParams {
-    double inv_eps, omega0, tol, delta, gamma, lipschitz;
-    int32_t ls, lmo;
+    SolveParams sp;
+    double *hist;        // 5 x hist_stride history (may be null)
+    int32_t hist_stride;
+    int32_t pad_;
 };
 
 // ---------------------------------------------------------------------------------
@@ -252,175 +256,332 @@ __global__ void __launch_bounds__(kRowBlock) k_spmm(int64_t n, int32_t K, const 
     }
 }
 
-// Row kernel: pending update, gradient, GLMO, per-row partials.  One thread per row.
-template <typename T, typename ST, int KMAX>
+// Block sum of N per-thread values, stored at out[j * stride] (fixed order).
+template <int N>
+__device__ __forceinline__ void block_sum_store_strided(double (&v)[N], double *out, int64_t stride)
+{
+    __shared__ double red[kRowBlock / 64][N];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) red[wid][j] = v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x * stride] = s;
+    }
+}
+
+// Row kernel: pending update, gradient, GLMO, per-row partials.
+// A block owns kRowBlock consecutive rows.  Their U, P and Q rows form contiguous runs of
+// rows*K elements, moved between HBM and LDS with coalesced accesses; each thread then
+// works on one row out of LDS.  Partials are stored transposed: part[j * gridDim.x + b].
+// Dynamic LDS: 3 * kRowBlock * K * sizeof(T).
+template <typename T, typename ST, int KB>
 __global__ void __launch_bounds__(kRowBlock) k_row(int64_t n, int32_t K, const int32_t *__restrict__ lab,
                                                     T *__restrict__ U, T *__restrict__ P, const T *__restrict__ Q,
-                                                    const ST *__restrict__ s_prev, ST *__restrict__ s_cur,
-                                                    const Ctl *__restrict__ ctl, SolveParams sp,
-                                                    double *__restrict__ part, int apply_only)
+                                                    ST *__restrict__ s0, ST *__restrict__ s1,
+                                                    const Ctl *__restrict__ ctl, double *__restrict__ part,
+                                                    int apply_only)
 {
     // apply_only: commit the pending update and evaluate nothing
     const int32_t active = apply_only ? 0 : ctl->active, pending = ctl->pending;
     if (!active && !pending) return;
+    // iteration k writes its vertices to s[k & 1]; the pending update is the one of the
+    // last evaluated iteration
+    const ST *__restrict__ s_prev = (ctl->last_eval & 1) ? s1 : s0;
+    ST *__restrict__ s_cur = (ctl->k & 1) ? s1 : s0;
     const double alpha = ctl->alpha;
+    const SolveParams sp = ctl->sp;
+    extern __shared__ unsigned char lds_raw[];
+    T *lu = reinterpret_cast<T *>(lds_raw);
+    T *lp = lu + kRowBlock * K;
+    T *lq = lp + kRowBlock * K;
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kRowBlock;
+    const int rows = (int)min((int64_t)kRowBlock, n - r0);
+    const int cnt = rows * K;
+    const int64_t base = r0 * K;
+    // The block's run of rows*K elements starts on a 16-byte boundary (256*K*sizeof(T) is a
+    // multiple of 16); full blocks move it with 16-byte vectors, the ragged last block with
+    // scalars.  All loads are issued before the LDS stores.
+    constexpr int VE = 16 / sizeof(T);                  // elements per 16-byte vector
+    constexpr int VPT = (KB * kRowBlock / VE + kRowBlock - 1) / kRowBlock; // vectors per thread
+    const bool full = rows == kRowBlock;
+    if (full) {
+        const int nvec = cnt / VE;
+        const uint4 *gu = reinterpret_cast<const uint4 *>(U + base);
+        const uint4 *gp = reinterpret_cast<const uint4 *>(P + base);
+        const uint4 *gq = reinterpret_cast<const uint4 *>(Q + base);
+        uint4 vu[VPT], vp[VPT], vq[VPT];
+#pragma unroll
+        for (int m = 0; m < VPT; ++m) {
+            const int v = min(tid + m * kRowBlock, nvec - 1);
+            vu[m] = gu[v];
+            vp[m] = gp[v];
+            vq[m] = gq[v]; // Q is only used when an update is pending (every iteration but the first)
+        }
+#pragma unroll
+        for (int m = 0; m < VPT; ++m) {
+            const int v = tid + m * kRowBlock;
+            if (v < nvec) {
+                reinterpret_cast<uint4 *>(lu)[v] = vu[m];
+                reinterpret_cast<uint4 *>(lp)[v] = vp[m];
+                reinterpret_cast<uint4 *>(lq)[v] = vq[m];
+            }
+        }
+    } else {
+        for (int q = tid; q < cnt; q += kRowBlock) {
+            lu[q] = U[base + q];
+            lp[q] = P[base + q];
+            if (pending) lq[q] = Q[base + q];
+        }
+    }
+    __syncthreads();
+
     double acc[kRowParts];
 #pragma unroll
     for (int j = 0; j < kRowParts; ++j) acc[j] = 0.0;
-
-    for (int64_t i = blockIdx.x * (int64_t)kRowBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRowBlock) {
-        double u[KMAX], p[KMAX];
-        T *Ui = U + i * K;
-        T *Pi = P + i * K;
+    if (tid < rows) {
+        const int64_t i = r0 + tid;
+        T *ur = lu + tid * K;
+        T *pr = lp + tid * K;
+        double u[KB], p[KB];
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            u[c] = c < K ? (double)Ui[c] : 0.0;
-            p[c] = c < K ? (double)Pi[c] : 0.0;
+        for (int c = 0; c < KB; ++c) {
+            u[c] = c < K ? (double)ur[c] : 0.0;
+            p[c] = c < K ? (double)pr[c] : 0.0;
         }
         bool binary = true;
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c)
+        for (int c = 0; c < KB; ++c)
             if (c < K && !(u[c] == 0.0 || u[c] == 1.0)) binary = false;
         if (pending) {
             const int32_t sp_i = (int32_t)s_prev[i];
-            const T *Qi = Q + i * K;
+            const T *qr = lq + tid * K;
             const double om = 1.0 - alpha;
 #pragma unroll
-            for (int c = 0; c < KMAX; ++c) {
+            for (int c = 0; c < KB; ++c) {
                 if (c < K) {
-                    p[c] = (double)(T)(om * p[c] + alpha * (double)Qi[c]);
-                    Pi[c] = (T)p[c];
+                    p[c] = (double)(T)(om * p[c] + alpha * (double)qr[c]);
+                    pr[c] = (T)p[c];
                 }
             }
             // a row whose direction d_i = e_{s_i} - u_i is zero (a binary row kept by the
             // GLMO) is left exactly as it is; every other row moves to (1-a) u + a e_s
             double at_s = 0.0;
 #pragma unroll
-            for (int c = 0; c < KMAX; ++c)
+            for (int c = 0; c < KB; ++c)
                 if (c == sp_i) at_s = u[c];
             if (!(binary && at_s == 1.0)) {
 #pragma unroll
-                for (int c = 0; c < KMAX; ++c) {
+                for (int c = 0; c < KB; ++c) {
                     if (c < K) {
                         u[c] = (double)(T)(om * u[c] + (c == sp_i ? alpha : 0.0));
-                        Ui[c] = (T)u[c];
+                        ur[c] = (T)u[c];
                     }
                 }
                 binary = true;
 #pragma unroll
-                for (int c = 0; c < KMAX; ++c)
+                for (int c = 0; c < KB; ++c)
                     if (c < K && !(u[c] == 0.0 || u[c] == 1.0)) binary = false;
             }
         }
-        if (!active) continue;
-
-        const int32_t y = lab[i];
-        const double om_i = y >= 0 ? sp.omega0 : 0.0;
-        double g[KMAX];
+        if (active) {
+            const int32_t y = lab[i];
+            const double om_i = y >= 0 ? sp.omega0 : 0.0;
+            double g[KB];
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            if (c < K) {
-                const double uhat = y >= 0 ? (c == y ? 1.0 : 0.0) : 0.0;
-                const double fid = om_i != 0.0 ? om_i * (uhat - u[c]) : 0.0;
-                g[c] = p[c] + sp.inv_eps * (1.0 - 2.0 * u[c]) - fid;
+            for (int c = 0; c < KB; ++c) {
+                if (c < K) {
+                    const double uhat = (c == y) ? 1.0 : 0.0;
+                    const double fid = om_i != 0.0 ? om_i * (uhat - u[c]) : 0.0;
+                    g[c] = p[c] + sp.inv_eps * (1.0 - 2.0 * u[c]) - fid;
+                } else {
+                    g[c] = 0.0;
+                }
             }
-        }
-        int32_t s = 0;
-        if (binary && sp.lmo == 0) {
-            // GLMO keeps a binary row: its vertex is the position of its 1
+            int32_t s = 0;
+            if (binary && sp.lmo == 0) {
+                // the GLMO keeps a binary row: its vertex is the position of its 1
 #pragma unroll
-            for (int c = KMAX - 1; c >= 0; --c)
-                if (c < K && u[c] == 1.0) s = c;
+                for (int c = KB - 1; c >= 0; --c)
+                    if (c < K && u[c] == 1.0) s = c;
+            } else {
+                double best = 0.0;
+                int32_t bi = -1;
+#pragma unroll
+                for (int c = 0; c < KB; ++c) {
+                    if (c < K && (sp.lmo == 1 || u[c] != 0.0)) {
+                        if (bi < 0 || g[c] < best) {
+                            best = g[c];
+                            bi = c;
+                        }
+                    }
+                }
+                s = bi < 0 ? 0 : bi;
+            }
+            s_cur[i] = (ST)s;
+            double gap = 0.0, up = 0.0, dd = 0.0, pen = 0.0, fid = 0.0, ps = 0.0;
+#pragma unroll
+            for (int c = 0; c < KB; ++c) {
+                if (c < K) {
+                    const double d = (c == s ? 1.0 : 0.0) - u[c];
+                    gap -= g[c] * d;
+                    up += u[c] * p[c];
+                    dd += d * d;
+                    pen += u[c] * (1.0 - u[c]);
+                    if (c == s) ps = p[c];
+                    if (om_i != 0.0) {
+                        const double e = (y == c ? 1.0 : 0.0) - u[c];
+                        fid += e * e;
+                    }
+                }
+            }
+            acc[PART_GAP] = gap;
+            acc[PART_E] = 0.5 * up + sp.inv_eps * pen + 0.5 * (om_i * fid);
+            acc[PART_CURV] = up - 2.0 * ps - 2.0 * sp.inv_eps * dd + om_i * dd;
+            acc[PART_DD] = dd;
+            acc[PART_NB] = binary ? 0.0 : 1.0;
+        }
+    }
+    __syncthreads();
+    if (pending) {
+        if (full) {
+            const int nvec = cnt / VE;
+            uint4 *gu = reinterpret_cast<uint4 *>(U + base);
+            uint4 *gp = reinterpret_cast<uint4 *>(P + base);
+#pragma unroll
+            for (int m = 0; m < VPT; ++m) {
+                const int v = tid + m * kRowBlock;
+                if (v < nvec) {
+                    gu[v] = reinterpret_cast<const uint4 *>(lu)[v];
+                    gp[v] = reinterpret_cast<const uint4 *>(lp)[v];
+                }
+            }
         } else {
-            double best = 0.0;
-            int32_t bi = -1;
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c) {
-                if (c < K && (sp.lmo == 1 || u[c] != 0.0)) {
-                    if (bi < 0 || g[c] < best) { best = g[c]; bi = c; }
-                }
-            }
-            s = bi < 0 ? 0 : bi;
-        }
-        s_cur[i] = (ST)s;
-        double gap = 0.0, up = 0.0, dd = 0.0, pen = 0.0, fid = 0.0, ps = 0.0;
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c) {
-            if (c < K) {
-                const double d = (c == s ? 1.0 : 0.0) - u[c];
-                gap -= g[c] * d;
-                up += u[c] * p[c];
-                dd += d * d;
-                pen += u[c] * (1.0 - u[c]);
-                if (c == s) ps = p[c];
-                if (om_i != 0.0) {
-                    const double e = (y == c ? 1.0 : 0.0) - u[c];
-                    fid += e * e;
-                }
+            for (int q = tid; q < cnt; q += kRowBlock) {
+                U[base + q] = lu[q];
+                P[base + q] = lp[q];
             }
         }
-        acc[PART_GAP] += gap;
-        acc[PART_UP] += up;
-        acc[PART_PS] += ps;
-        acc[PART_DD] += dd;
-        acc[PART_WDD] += om_i * dd;
-        acc[PART_PEN] += pen;
-        acc[PART_FID] += om_i * fid;
-        acc[PART_NB] += binary ? 0.0 : 1.0;
     }
     if (!active) return;
-    block_sum_store<kRowParts>(acc, part + (int64_t)blockIdx.x * kRowParts);
+    block_sum_store_strided<kRowParts>(acc, part + blockIdx.x, gridDim.x);
 }
 
-// Label pass: Q = L_s S for one-hot S given by s, and the per-row terms Q_{i, s_i}.
-template <typename T, typename ST, int KMAX, int LPR>
+constexpr int kLabelTile = 2048; // CSR entries staged in LDS per step of the label pass
+
+// Label pass: Q = L_s S for the one-hot S given by s (a per-row histogram of neighbour
+// labels weighted by the stored values), and the per-row terms Q_{i, s_i}.
+// A block owns kRowBlock consecutive rows, i.e. one contiguous range of CSR entries.  The
+// range is streamed through LDS in tiles: all threads load column indices and values with
+// coalesced accesses and gather the one-byte labels of the columns; then each thread sums
+// the entries of its own row in CSR order.  Q is staged in LDS (dynamic, kRowBlock * K *
+// sizeof(T)) and written back coalesced.  One partial per block.
+template <typename T, typename ST, int KB>
 __global__ void __launch_bounds__(kRowBlock) k_label(int64_t n, int32_t K, const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ ci, const T *__restrict__ a,
-                                                      int diag_one, const ST *__restrict__ s, T *__restrict__ Q,
+                                                      int diag_one, const ST *__restrict__ s0,
+                                                      const ST *__restrict__ s1, T *__restrict__ Q,
                                                       const Ctl *__restrict__ ctl, double *__restrict__ part)
 {
     if (!ctl->active) return;
-    const int lane = threadIdx.x % LPR;
-    double tot = 0.0;
-    const int64_t rows_per_grid = (int64_t)gridDim.x * (kRowBlock / LPR);
-    for (int64_t i = blockIdx.x * (int64_t)(kRowBlock / LPR) + threadIdx.x / LPR; i < n; i += rows_per_grid) {
-        double acc[KMAX];
+    const ST *__restrict__ s = (ctl->k & 1) ? s1 : s0;
+    __shared__ ST ls[kLabelTile];
+    __shared__ T lv[kLabelTile];
+    extern __shared__ unsigned char lds_raw[];
+    T *lq = reinterpret_cast<T *>(lds_raw);
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kRowBlock;
+    const int rows = (int)min((int64_t)kRowBlock, n - r0);
+    const bool has_row = tid < rows;
+    const int64_t i = r0 + tid;
+    const int32_t b = has_row ? rp[i] : 0, e = has_row ? rp[i + 1] : 0;
+    const int32_t t_begin = rp[r0], t_end = rp[r0 + rows];
+    T acc[KB];
 #pragma unroll
-        for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
-        const int32_t b = rp[i], e = rp[i + 1];
-        for (int32_t p = b + lane; p < e; p += LPR) {
-            const int32_t sj = (int32_t)s[ci[p]];
-            const double av = (double)a[p];
+    for (int c = 0; c < KB; ++c) acc[c] = (T)0;
+    constexpr int PER = kLabelTile / kRowBlock;
+    for (int32_t t0 = t_begin; t0 < t_end; t0 += kLabelTile) {
+        const int cnt = (int)min((int32_t)kLabelTile, t_end - t0);
+        // issue every load of the tile before using any of them: indices and values (clamped
+        // to the last entry of the tile, so that every address is valid), then the label
+        // gathers, then the LDS stores
+        int32_t jj[PER];
+        T vv[PER];
 #pragma unroll
-            for (int c = 0; c < KMAX; ++c) acc[c] += (c == sj) ? av : 0.0;
+        for (int m = 0; m < PER; ++m) {
+            const int q = min(tid + m * kRowBlock, cnt - 1);
+            jj[m] = __builtin_nontemporal_load(ci + t0 + q);
+            vv[m] = __builtin_nontemporal_load(a + t0 + q);
         }
+        ST ss[PER];
 #pragma unroll
-        for (int off = LPR / 2; off > 0; off >>= 1)
+        for (int m = 0; m < PER; ++m) ss[m] = s[jj[m]];
+        __syncthreads(); // the previous tile has been consumed
 #pragma unroll
-            for (int c = 0; c < KMAX; ++c) acc[c] += __shfl_xor(acc[c], off, LPR);
-        if (lane == 0) {
-            const int32_t si = (int32_t)s[i];
-            double own = 0.0;
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c) {
-                if (c < K) {
-                    const double v = acc[c] + ((diag_one && c == si) ? 1.0 : 0.0);
-                    Q[i * K + c] = (T)v;
-                    if (c == si) own = (double)(T)v;
-                }
+        for (int m = 0; m < PER; ++m) {
+            const int q = tid + m * kRowBlock;
+            if (q < cnt) {
+                ls[q] = ss[m];
+                lv[q] = vv[m];
             }
-            tot += own;
+        }
+        __syncthreads();
+        if (has_row) {
+            const int32_t pb = max(b, t0), pe = min(e, t0 + cnt);
+            int32_t p = pb;
+            for (; p + 4 <= pe; p += 4) {
+                int32_t sj[4];
+                T v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    sj[u] = (int32_t)ls[p + u - t0];
+                    v[u] = lv[p + u - t0];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? v[u] : (T)0;
+            }
+            for (; p < pe; ++p) {
+                const int32_t sj = (int32_t)ls[p - t0];
+                const T v = lv[p - t0];
+#pragma unroll
+                for (int c = 0; c < KB; ++c) acc[c] += (c == sj) ? v : (T)0;
+            }
         }
     }
-    double v[1] = {tot};
-    block_sum_store<1>(v, part + blockIdx.x);
+    double own = 0.0;
+    if (has_row) {
+        const int32_t si = (int32_t)s[i];
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+            if (c < K) {
+                const T v = acc[c] + ((diag_one && c == si) ? (T)1 : (T)0);
+                lq[tid * K + c] = v;
+                if (c == si) own = (double)v;
+            }
+        }
+    }
+    __syncthreads();
+    const int cntq = rows * K;
+    const int64_t base = r0 * K;
+    for (int q = tid; q < cntq; q += kRowBlock) Q[base + q] = lq[q];
+    double v[1] = {own};
+    block_sum_store_strided<1>(v, part + blockIdx.x, gridDim.x);
 }
 
 // Finish: fixed-order reduction of the partials, gap, objective, curvature, step size.
+// row_part is [kRowParts][nb_row], lab_part is [nb_lab].
 __global__ void __launch_bounds__(kFinishThreads) k_finish(const double *__restrict__ row_part, int nb_row,
                                                            const double *__restrict__ lab_part, int nb_lab,
-                                                           Ctl *__restrict__ ctl, SolveParams sp,
-                                                           double *__restrict__ hist, int hist_stride)
+                                                           Ctl *__restrict__ ctl)
 {
     if (!ctl->active) {
         if (threadIdx.x == 0) ctl->pending = 0;
@@ -430,10 +591,32 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish(const double *__restr
     double v[kRowParts + 1];
 #pragma unroll
     for (int j = 0; j <= kRowParts; ++j) v[j] = 0.0;
-    for (int b = threadIdx.x; b < nb_row; b += kFinishThreads)
+    // four block partials per thread and quantity in flight
+    constexpr int CH = 4;
+    for (int b0 = 0; b0 < nb_row; b0 += CH * kFinishThreads) {
+        double x[kRowParts][CH];
 #pragma unroll
-        for (int j = 0; j < kRowParts; ++j) v[j] += row_part[(int64_t)b * kRowParts + j];
-    for (int b = threadIdx.x; b < nb_lab; b += kFinishThreads) v[kRowParts] += lab_part[b];
+        for (int j = 0; j < kRowParts; ++j)
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int b = b0 + threadIdx.x + c * kFinishThreads;
+                x[j][c] = b < nb_row ? row_part[(int64_t)j * nb_row + b] : 0.0;
+            }
+#pragma unroll
+        for (int j = 0; j < kRowParts; ++j)
+#pragma unroll
+            for (int c = 0; c < CH; ++c) v[j] += x[j][c];
+    }
+    for (int b0 = 0; b0 < nb_lab; b0 += 4 * kFinishThreads) {
+        double x[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int b = b0 + threadIdx.x + c * kFinishThreads;
+            x[c] = b < nb_lab ? lab_part[b] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[kRowParts] += x[c];
+    }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j <= kRowParts; ++j) v[j] = wave_sum(v[j]);
@@ -443,18 +626,23 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish(const double *__restr
     __syncthreads();
     if (threadIdx.x != 0) return;
     double t[kRowParts + 1];
+#pragma unroll
     for (int j = 0; j <= kRowParts; ++j) {
         double s = 0.0;
         for (int w = 0; w < kFinishThreads / 64; ++w) s += red[w][j];
         t[j] = s;
     }
+    const SolveParams sp = ctl->sp;
+    double *hist = ctl->hist;
+    const int hist_stride = ctl->hist_stride;
     const int k = ctl->k;
     ctl->last_eval = k;
     const double g = t[PART_GAP];
-    const double E = 0.5 * t[PART_UP] + sp.inv_eps * t[PART_PEN] + 0.5 * t[PART_FID];
-    // <D, L D> = <S, L S> - 2 <S, L U> + <U, L U> (L symmetric)
-    const double dld = t[kRowParts] - 2.0 * t[PART_PS] + t[PART_UP];
-    const double q = dld - 2.0 * sp.inv_eps * t[PART_DD] + t[PART_WDD];
+    const double E = t[PART_E];
+    // q = <D, L D> - (2/eps)||D||^2 + sum omega_i ||d_i||^2 with
+    // <D, L D> = <S, L S> - 2 <S, L U> + <U, L U> (L symmetric).  ||D||^2 is exactly 0 iff
+    // D = 0, and then q is exactly 0 (the assembled form would leave a rounding residue).
+    const double q = t[PART_DD] == 0.0 ? 0.0 : t[kRowParts] + t[PART_CURV];
     ctl->gap = g;
     ctl->E_last = E;
     double alpha = __builtin_nan("");

@@ -30,8 +30,9 @@ EXPORTED = [
     "gfw_status_string", "gfw_last_error", "gfw_params_default", "gfw_check_problem", "gfw_check_params",
     "gfw_context_create", "gfw_context_destroy", "gfw_graph_create", "gfw_graph_destroy", "gfw_graph_footprint",
     "gfw_solve", "gfw_solve_batched", "gfw_objective", "gfw_spmm", "gfw_server_create", "gfw_server_submit",
-    "gfw_server_poll", "gfw_server_destroy",
+    "gfw_server_poll", "gfw_server_destroy", "gfw_trace_enable", "gfw_trace_reset", "gfw_trace_get",
 ]
+KERNEL_ROW, KERNEL_LABEL, KERNEL_FINISH, KERNEL_SPMM, KERNEL_FUSED = 0, 1, 2, 3, 4
 
 
 class GfwError(RuntimeError):
@@ -93,6 +94,9 @@ def lib():
         L.gfw_server_submit.argtypes = [p, C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_uint64)]
         L.gfw_server_poll.argtypes = [p, C.c_uint64, C.c_int, p, p, C.POINTER(Stats)]
         L.gfw_server_destroy.argtypes = [p]
+        L.gfw_trace_enable.argtypes = [p, C.c_int]
+        L.gfw_trace_reset.argtypes = [p]
+        L.gfw_trace_get.argtypes = [p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         for name in EXPORTED:
             f = getattr(L, name)
             if f.restype is None and name != "gfw_params_default":
@@ -227,6 +231,21 @@ def solve(ctx: Context, g: Graph, prm: Params, want_U: bool = True, want_labels:
         h = hist.reshape(5, prm.max_iter + 1)
         out.update(E=h[0], g=h[1], q=h[2], alpha=h[3], nonbinary=h[4])
     return out
+
+
+def trace_enable(ctx: Context, on: bool = True) -> None:
+    check(lib().gfw_trace_enable(ctx.handle, int(on)))
+
+
+def trace_reset(ctx: Context) -> None:
+    check(lib().gfw_trace_reset(ctx.handle))
+
+
+def trace_get(ctx: Context, kernel: int):
+    """(total milliseconds, launches) of a kernel class since the last reset."""
+    ms, n = C.c_double(), C.c_int64()
+    check(lib().gfw_trace_get(ctx.handle, kernel, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
 
 
 def objective(ctx: Context, g: Graph, prm: Params, U, stream=None) -> float:
