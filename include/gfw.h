@@ -162,6 +162,15 @@ GFW_API gfw_status_t gfw_graph_create(gfw_context_t ctx, const gfw_problem_t *p,
 GFW_API gfw_status_t gfw_graph_destroy(gfw_graph_t g);
 /* Device bytes held by a graph and by one solve on it (workspace). */
 GFW_API gfw_status_t gfw_graph_footprint(gfw_graph_t g, size_t *graph_bytes, size_t *solve_bytes);
+/* Implementation choices of a graph (results are identical whichever is chosen):
+ *  GFW_TUNE_LABEL_PATH: 0 = automatic (chosen at gfw_graph_create from the graph's
+ *    locality), 1 = plain label pass, 2 = column-sorted label pass (builds, once, a copy
+ *    of the column indices sorted within tiles of rows; GFW_E_UNSUPPORTED if a row has more
+ *    than 65536 entries).
+ * gfw_graph_query returns the current value of a key (for GFW_TUNE_LABEL_PATH: 1 or 2). */
+typedef enum { GFW_TUNE_LABEL_PATH = 0 } gfw_tune_t;
+GFW_API gfw_status_t gfw_graph_tune(gfw_graph_t g, gfw_tune_t key, int64_t value);
+GFW_API gfw_status_t gfw_graph_query(gfw_graph_t g, gfw_tune_t key, int64_t *value);
 
 /* ---- solving ------------------------------------------------------------------------ */
 /*

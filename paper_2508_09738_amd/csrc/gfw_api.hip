@@ -9,6 +9,7 @@
 #include <cstring>
 #include <limits>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "gfw_internal.h"
@@ -230,6 +231,9 @@ static void free_graph(gfw_graph_s *g)
     dfree(g->col);
     dfree(g->vals);
     dfree(g->lab);
+    dfree(g->tile_rows);
+    dfree(g->gcol);
+    dfree(g->gpos);
     Workspace &w = g->ws;
     dfree(w.U);
     dfree(w.P);
@@ -273,6 +277,123 @@ static gfw_status_t form_operator(gfw_graph_s *g, const T *wdev, hipStream_t st)
     dfree(dinv);
     dfree(rho);
     dfree(rmax);
+    return GFW_OK;
+}
+
+// Mean number of distinct 128-node label lines touched by 64 consecutive CSR entries
+// (sampled): about 64 when the neighbours of consecutive rows are scattered over the graph,
+// a few when they are local (grids, ordered meshes).
+static double label_locality(int64_t nnz, const int32_t *col)
+{
+    if (nnz < 64) return 0.0;
+    const int samples = 256;
+    double tot = 0.0;
+    for (int t = 0; t < samples; ++t) {
+        const int64_t e = (nnz - 64) * (int64_t)t / samples;
+        int32_t lines[64];
+        for (int q = 0; q < 64; ++q) lines[q] = col[e + q] >> 7;
+        std::sort(lines, lines + 64);
+        tot += (double)(std::unique(lines, lines + 64) - lines);
+    }
+    return tot / samples;
+}
+
+// Row tiles for the column-sorted label pass and the per-tile column order of the entries.
+static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const int32_t *col, hipStream_t st)
+{
+    const int64_t n = g->n;
+    const size_t vs = g->dtype == GFW_F32 ? 4 : 8;
+    const int64_t rcap = std::min<int64_t>(4 * kSortedThreads, kSortedMaxEntries / (g->K * (int64_t)vs));
+    std::vector<int32_t> tr;
+    tr.push_back(0);
+    int64_t cr = 0, ce = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t d = rp[i + 1] - rp[i];
+        if (d > kSortedMaxEntries) return fail(GFW_E_UNSUPPORTED, "row %lld has more than %d entries", (long long)i,
+                                               kSortedMaxEntries);
+        if (cr + 1 > rcap || ce + d > kSortedMaxEntries) {
+            tr.push_back((int32_t)i);
+            cr = 0;
+            ce = 0;
+        }
+        ++cr;
+        ce += d;
+    }
+    tr.push_back((int32_t)n);
+    const int32_t nt = (int32_t)tr.size() - 1;
+    const int64_t nnz = g->nnz;
+    std::vector<int32_t> sc((size_t)std::max<int64_t>(nnz, 1));
+    std::vector<uint16_t> sp((size_t)std::max<int64_t>(nnz, 1));
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (unsigned w = 0; w < nth; ++w) {
+        pool.emplace_back([&, w]() {
+            std::vector<uint64_t> key;
+            for (int32_t t = (int32_t)w; t < nt; t += (int32_t)nth) {
+                const int64_t e0 = rp[tr[t]], e1 = rp[tr[t + 1]];
+                key.resize((size_t)(e1 - e0));
+                for (int64_t e = e0; e < e1; ++e) key[(size_t)(e - e0)] = ((uint64_t)(uint32_t)col[e] << 16) | (uint64_t)(e - e0);
+                std::sort(key.begin(), key.end());
+                for (int64_t e = e0; e < e1; ++e) {
+                    sc[(size_t)e] = (int32_t)(key[(size_t)(e - e0)] >> 16);
+                    sp[(size_t)e] = (uint16_t)(key[(size_t)(e - e0)] & 0xffff);
+                }
+            }
+        });
+    }
+    for (auto &th : pool) th.join();
+    dfree(g->tile_rows);
+    dfree(g->gcol);
+    dfree(g->gpos);
+    g->tile_rows = nullptr;
+    g->gcol = nullptr;
+    g->gpos = nullptr;
+    if (hipMalloc(&g->tile_rows, sizeof(int32_t) * (nt + 1)) != hipSuccess ||
+        hipMalloc(&g->gcol, sizeof(int32_t) * std::max<int64_t>(nnz, 4)) != hipSuccess ||
+        hipMalloc(&g->gpos, sizeof(uint16_t) * std::max<int64_t>(nnz, 8)) != hipSuccess)
+        return fail(GFW_E_NOMEM, "device allocation for the sorted label pass failed");
+    GFW_HIP_TRY(hipMemcpyAsync(g->tile_rows, tr.data(), sizeof(int32_t) * (nt + 1), hipMemcpyHostToDevice, st));
+    if (nnz) {
+        GFW_HIP_TRY(hipMemcpyAsync(g->gcol, sc.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+        GFW_HIP_TRY(hipMemcpyAsync(g->gpos, sp.data(), sizeof(uint16_t) * nnz, hipMemcpyHostToDevice, st));
+    }
+    GFW_HIP_TRY(hipStreamSynchronize(st));
+    g->n_tiles = nt;
+    g->graph_bytes += sizeof(int32_t) * (nt + 1) + 6 * (size_t)nnz;
+    return GFW_OK;
+}
+
+// Chooses and prepares the label path: the column-sorted pass for large graphs whose
+// neighbour labels are scattered, the plain pass otherwise.  mode: 0 auto, 1 plain, 2 sorted.
+static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st)
+{
+    if (mode == 1) {
+        g->label_path = 0;
+        return GFW_OK;
+    }
+    std::vector<int32_t> rp((size_t)g->n + 1), col((size_t)std::max<int64_t>(g->nnz, 1));
+    GFW_HIP_TRY(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToHost, st));
+    if (g->nnz) GFW_HIP_TRY(hipMemcpyAsync(col.data(), g->col, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToHost, st));
+    GFW_HIP_TRY(hipStreamSynchronize(st));
+    g->locality = label_locality(g->nnz, col.data());
+    const bool want = mode == 2 || (g->nnz >= (int64_t)4 << 20 && g->locality > 16.0);
+    if (!want) {
+        g->label_path = 0;
+        return GFW_OK;
+    }
+    if (!g->gcol) {
+        gfw_status_t s = build_sorted_tiles(g, rp.data(), col.data(), st);
+        if (s != GFW_OK) {
+            if (mode == 2) return s;
+            g->label_path = 0; // a row too long for the sorted tiles: keep the plain pass
+            return GFW_OK;
+        }
+    }
+    g->label_path = 1;
+    if (g->ws.iter_exec) { // the captured iteration graph holds the previous label kernel
+        (void)hipGraphExecDestroy(g->ws.iter_exec);
+        g->ws.iter_exec = nullptr;
+    }
     return GFW_OK;
 }
 
@@ -380,7 +501,8 @@ static gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw
     dfree(wraw);
     if (s != GFW_OK) return s;
     g->shape = shape_for(n, nnz, p->K);
-    g->graph_bytes = 4 * (n + 1) + (4 + vs) * nnz + 4 * n;
+    if ((s = choose_label_path(g, 0, st)) != GFW_OK) return s;
+    g->graph_bytes += 4 * (n + 1) + (4 + vs) * nnz + 4 * n;
     g->solve_bytes = 3 * vs * n * p->K + 2 * n + sizeof(double) * ((kRowParts + 4) * g->shape.nb_row + 64) +
                      sizeof(Ctl);
     guard.g = nullptr;
@@ -406,7 +528,8 @@ static gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
     if ((s = dalloc((void **)&w.s0, g->n)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.s1, g->n)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.row_part, sizeof(double) * kRowParts * g->shape.nb_row)) != GFW_OK) return s;
-    if ((s = dalloc((void **)&w.lab_part, sizeof(double) * g->shape.nb_row)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.lab_part, sizeof(double) * std::max<int64_t>(g->shape.nb_row, g->n_tiles)))
+        != GFW_OK) return s;
     if ((s = dalloc((void **)&w.scratch, sizeof(double) * 3 * std::max(g->shape.nb_row, 64))) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.ctl, sizeof(Ctl))) != GFW_OK) return s;
     const int64_t need = 5 * ((int64_t)max_iter + 1);
@@ -420,40 +543,69 @@ static gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
 }
 
 // --------------------------------------------------------------------------------------
-// kernel dispatch on the K bucket and the lanes-per-row of the CSR kernels
+// kernel dispatch
 // --------------------------------------------------------------------------------------
 
-template <typename T, int KMAX, int LPR>
-static void launch_spmm_l(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
+template <typename T>
+GraphView<T> make_view(const gfw_graph_s *g)
 {
-    k_spmm<T, KMAX, LPR><<<g->shape.nb_csr, kRowBlock, 0, st>>>(g->n, g->K, g->row_ptr, g->col, (const T *)g->vals,
-                                                                g->diag_one, U, P);
+    GraphView<T> v;
+    const Workspace &w = g->ws;
+    v.n = g->n;
+    v.K = g->K;
+    v.diag_one = g->diag_one;
+    v.rp = g->row_ptr;
+    v.ci = g->col;
+    v.a = (const T *)g->vals;
+    v.lab = g->lab;
+    v.U = (T *)w.U;
+    v.P = (T *)w.P;
+    v.Q = (T *)w.Q;
+    v.s0 = w.s0;
+    v.s1 = w.s1;
+    v.ctl = w.ctl;
+    v.row_part = w.row_part;
+    v.lab_part = w.lab_part;
+    v.nb_row = g->shape.nb_row;
+    v.n_tiles = g->label_path == 1 ? g->n_tiles : 0;
+    v.tile_rows = g->tile_rows;
+    v.gcol = g->gcol;
+    v.gpos = g->gpos;
+    return v;
 }
 
-#define GFW_LPR_SWITCH(LPR, CALL)                  \
-    switch (LPR) {                                 \
-    case 1: { constexpr int L_ = 1; CALL; } break;  \
-    case 2: { constexpr int L_ = 2; CALL; } break;  \
-    case 4: { constexpr int L_ = 4; CALL; } break;  \
-    case 8: { constexpr int L_ = 8; CALL; } break;  \
-    case 16: { constexpr int L_ = 16; CALL; } break; \
-    default: { constexpr int L_ = 32; CALL; } break; \
-    }
+template <typename T, int KMAX>
+static void set_lds_limits()
+{
+    // the largest dynamic LDS any launch of these kernels asks for
+    (void)hipFuncSetAttribute((const void *)k_label_sorted<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kSortedMaxEntries);
+    (void)hipFuncSetAttribute((const void *)k_label_sorted_batch<T, uint8_t, KMAX>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kSortedMaxEntries);
+    const int row_lds = 3 * (int)sizeof(T) * kRowBlock * KMAX;
+    (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              row_lds);
+    (void)hipFuncSetAttribute((const void *)k_row_batch<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              row_lds);
+}
+
+static size_t row_lds_bytes(const gfw_graph_s *g) { return 3 * dsize(g->dtype) * kRowBlock * (size_t)g->K; }
 
 template <typename T, int KMAX>
 static void launch_spmm(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
 {
-    GFW_LPR_SWITCH(g->shape.lpr, (launch_spmm_l<T, KMAX, L_>(g, U, P, st)));
+    k_spmm<T, KMAX><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), U, P);
 }
 
 template <typename T, int KMAX>
-static void launch_label(const gfw_graph_s *g, const uint8_t *s0, const uint8_t *s1, T *Q, const Ctl *ctl,
-                         double *part, hipStream_t st)
+static void launch_label(const gfw_graph_s *g, hipStream_t st)
 {
+    if (g->label_path == 1) {
+        k_label_sorted<T, uint8_t, KMAX><<<g->n_tiles, kSortedThreads, kSortedMaxEntries, st>>>(make_view<T>(g));
+        return;
+    }
     const size_t lds = sizeof(T) * kRowBlock * g->K;
-    k_label<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(g->n, g->K, g->row_ptr, g->col,
-                                                                      (const T *)g->vals, g->diag_one, s0, s1, Q,
-                                                                      ctl, part);
+    k_label<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(make_view<T>(g));
 }
 
 template <typename T>
@@ -483,14 +635,7 @@ static SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm)
 template <typename T, int KMAX>
 static void launch_row(gfw_graph_s *g, int apply_only, hipStream_t st)
 {
-    Workspace &w = g->ws;
-    const size_t lds = 3 * sizeof(T) * kRowBlock * g->K;
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-    k_row<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(g->n, g->K, g->lab, (T *)w.U, (T *)w.P,
-                                                                    (const T *)w.Q, w.s0, w.s1, w.ctl,
-                                                                    w.row_part, apply_only);
+    k_row<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, row_lds_bytes(g), st>>>(make_view<T>(g), apply_only);
 }
 
 // One GFW iteration (row kernel, label pass, finish), optionally bracketed by trace events.
@@ -504,10 +649,11 @@ static void launch_iteration(gfw_graph_s *g, hipStream_t st, bool traced)
     launch_row<T, KMAX>(g, 0, st);
     trace_end(cx, GFW_KERNEL_ROW, ev, st);
     ev = trace_begin(cx, st);
-    launch_label<T, KMAX>(g, w.s0, w.s1, (T *)w.Q, w.ctl, w.lab_part, st);
+    launch_label<T, KMAX>(g, st);
     trace_end(cx, GFW_KERNEL_LABEL, ev, st);
     ev = trace_begin(cx, st);
-    k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, g->shape.nb_row, w.lab_part, g->shape.nb_row, w.ctl);
+    k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, g->shape.nb_row, w.lab_part,
+                                           g->label_path == 1 ? g->n_tiles : g->shape.nb_row, w.ctl);
     trace_end(cx, GFW_KERNEL_FINISH, ev, st);
 }
 
@@ -540,6 +686,11 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
 {
     gfw_status_t s = ensure_workspace(g, prm->max_iter);
     if (s != GFW_OK) return s;
+    static bool lds_set = false; // per instantiation
+    if (!lds_set) {
+        set_lds_limits<T, KMAX>();
+        lds_set = true;
+    }
     Workspace &w = g->ws;
     T *U = (T *)w.U, *P = (T *)w.P;
     Ctl c0;
@@ -556,7 +707,7 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     c0.hist_stride = prm->max_iter + 1;
     GFW_HIP_TRY(hipMemcpyAsync(w.ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, st));
     const int64_t nK = g->n * g->K;
-    k_init_u<T><<<grid_for(nK, 256, 16384), 256, 0, st>>>(g->n, g->K, g->lab, (const T *)prm->U0, U);
+    k_init_u<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), (const T *)prm->U0);
     gfw_context_s *cx = g->ctx;
     hipEvent_t ev = trace_begin(cx, st);
     spmm_any<T>(g, U, P, st);
@@ -635,14 +786,228 @@ static gfw_status_t objective_impl(gfw_graph_s *g, const gfw_params_t *prm, cons
     T *P = (T *)g->ws.Q; // Q is free between solves
     spmm_any<T>(g, U, P, st);
     const int nb = g->shape.nb_row;
-    k_energy_rows<T><<<nb, kRowBlock, 0, st>>>(g->n, g->K, g->lab, U, P, prm->omega0, g->ws.scratch);
-    k_sum_parts<<<1, kFinishThreads, 0, st>>>(g->ws.scratch, nb, 3, g->ws.row_part);
-    double t[3];
-    GFW_HIP_TRY(hipGetLastError());
-    GFW_HIP_TRY(hipMemcpyAsync(t, g->ws.row_part, sizeof(t), hipMemcpyDeviceToHost, st));
-    GFW_HIP_TRY(hipStreamSynchronize(st));
+    k_energy<T><<<nb, kRowBlock, 0, st>>>(make_view<T>(g), U, P, prm->omega0, g->ws.scratch);
     const double inv_eps = std::isinf(prm->eps) ? 0.0 : 1.0 / prm->eps;
-    *E = 0.5 * t[0] + inv_eps * t[1] + 0.5 * t[2];
+    k_energy_sum<<<1, kFinishThreads, 0, st>>>(g->ws.scratch, nb, inv_eps, g->ws.row_part);
+    GFW_HIP_TRY(hipGetLastError());
+    GFW_HIP_TRY(hipMemcpyAsync(E, g->ws.row_part, sizeof(double), hipMemcpyDeviceToHost, st));
+    GFW_HIP_TRY(hipStreamSynchronize(st));
+    return GFW_OK;
+}
+
+// --------------------------------------------------------------------------------------
+// batched solves
+// --------------------------------------------------------------------------------------
+
+static int bucket_of(int kmax) { return kmax == 4 ? 0 : kmax == 8 ? 1 : 2; }
+
+// Device tables of one batch: the graph views and, per K bucket, the (graph, tile) lists of
+// the row-wise kernels and of the two label passes.
+template <typename T>
+struct BatchTables {
+    std::vector<GraphView<T>> views;
+    std::vector<TileRef> rows[3], plain[3], sorted[3], all_rows;
+    GraphView<T> *d_views = nullptr;
+    TileRef *d_rows[3] = {}, *d_plain[3] = {}, *d_sorted[3] = {}, *d_all = nullptr;
+    int32_t *d_flag = nullptr;
+    int32_t *h_flag = nullptr;
+    const T **d_U0 = nullptr;
+    int32_t **d_lab_out = nullptr;
+    Ctl *d_ctl0 = nullptr, *d_ctl_out = nullptr;
+    double *d_E = nullptr;
+    ~BatchTables()
+    {
+        dfree(d_views);
+        for (int b = 0; b < 3; ++b) {
+            dfree(d_rows[b]);
+            dfree(d_plain[b]);
+            dfree(d_sorted[b]);
+        }
+        dfree(d_all);
+        dfree(d_flag);
+        dfree((void *)d_U0);
+        dfree(d_lab_out);
+        dfree(d_ctl0);
+        dfree(d_ctl_out);
+        dfree(d_E);
+        if (h_flag) (void)hipHostFree(h_flag);
+    }
+};
+
+template <typename T>
+static gfw_status_t upload(std::vector<T> &v, T **d, hipStream_t st)
+{
+    if (v.empty()) return GFW_OK;
+    if (hipMalloc((void **)d, sizeof(T) * v.size()) != hipSuccess) return fail(GFW_E_NOMEM, "batch table allocation");
+    GFW_HIP_TRY(hipMemcpyAsync(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    return GFW_OK;
+}
+
+template <typename T>
+static void batch_row_launch(BatchTables<T> &bt, int apply_only, hipStream_t st)
+{
+    if (!bt.rows[0].empty())
+        k_row_batch<T, uint8_t, 4><<<bt.rows[0].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 4, st>>>(
+            bt.d_views, bt.d_rows[0], apply_only);
+    if (!bt.rows[1].empty())
+        k_row_batch<T, uint8_t, 8><<<bt.rows[1].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 8, st>>>(
+            bt.d_views, bt.d_rows[1], apply_only);
+    if (!bt.rows[2].empty())
+        k_row_batch<T, uint8_t, 16><<<bt.rows[2].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 16, st>>>(
+            bt.d_views, bt.d_rows[2], apply_only);
+}
+
+template <typename T, int KB>
+static void batch_label_bucket(BatchTables<T> &bt, int b, hipStream_t st)
+{
+    if (!bt.plain[b].empty())
+        k_label_batch<T, uint8_t, KB><<<bt.plain[b].size(), kRowBlock, sizeof(T) * kRowBlock * KB, st>>>(bt.d_views,
+                                                                                                       bt.d_plain[b]);
+    if (!bt.sorted[b].empty())
+        k_label_sorted_batch<T, uint8_t, KB><<<bt.sorted[b].size(), kSortedThreads, kSortedMaxEntries, st>>>(
+            bt.d_views, bt.d_sorted[b]);
+}
+
+template <typename T>
+static void batch_iteration(BatchTables<T> &bt, hipStream_t st)
+{
+    batch_row_launch<T>(bt, 0, st);
+    batch_label_bucket<T, 4>(bt, 0, st);
+    batch_label_bucket<T, 8>(bt, 1, st);
+    batch_label_bucket<T, 16>(bt, 2, st);
+    k_finish_batch<T><<<bt.views.size(), kFinishThreads, 0, st>>>(bt.d_views);
+}
+
+template <typename T>
+static gfw_status_t solve_batched_impl(gfw_context_s *cx, int32_t count, gfw_graph_s *const *gs,
+                                       const gfw_params_t *const *prms, void *const *U_out,
+                                       int32_t *const *labels_out, gfw_stats_t *stats, hipStream_t st)
+{
+    static bool lds_set = false;
+    if (!lds_set) {
+        set_lds_limits<T, 4>();
+        set_lds_limits<T, 8>();
+        set_lds_limits<T, 16>();
+        lds_set = true;
+    }
+    BatchTables<T> bt;
+    std::vector<Ctl> ctl0((size_t)count);
+    std::vector<const T *> u0((size_t)count, nullptr);
+    std::vector<int32_t *> lab_out((size_t)count, nullptr);
+    int32_t max_iter = 0;
+    bool any_u0 = false, watch_stop = false;
+    for (int32_t i = 0; i < count; ++i) {
+        gfw_graph_s *g = gs[i];
+        const gfw_params_t *prm = prms[i];
+        gfw_status_t s = ensure_workspace(g, prm->max_iter);
+        if (s != GFW_OK) return s;
+        bt.views.push_back(make_view<T>(g));
+        const int b = bucket_of(g->shape.kmax);
+        for (int32_t t = 0; t < g->shape.nb_row; ++t) {
+            bt.rows[b].push_back({i, t});
+            bt.all_rows.push_back({i, t});
+            if (g->label_path != 1) bt.plain[b].push_back({i, t});
+        }
+        if (g->label_path == 1)
+            for (int32_t t = 0; t < g->n_tiles; ++t) bt.sorted[b].push_back({i, t});
+        Ctl &c = ctl0[(size_t)i];
+        std::memset(&c, 0, sizeof(c));
+        c.active = prm->max_iter > 0 ? 1 : 0;
+        c.max_iter = prm->max_iter;
+        c.one_shot = prm->one_shot;
+        c.last_eval = -1;
+        c.alpha_last = std::numeric_limits<double>::quiet_NaN();
+        c.gap = std::numeric_limits<double>::quiet_NaN();
+        c.sp = solve_params(g, prm);
+        c.hist = g->ws.hist;
+        c.hist_stride = prm->max_iter + 1;
+        u0[(size_t)i] = (const T *)prm->U0;
+        any_u0 = any_u0 || prm->U0;
+        lab_out[(size_t)i] = labels_out ? labels_out[i] : nullptr;
+        max_iter = std::max(max_iter, prm->max_iter);
+        watch_stop = watch_stop || prm->tol >= 0.0 || prm->one_shot;
+    }
+    gfw_status_t s;
+    if ((s = upload(bt.views, &bt.d_views, st)) != GFW_OK) return s;
+    for (int b = 0; b < 3; ++b) {
+        if ((s = upload(bt.rows[b], &bt.d_rows[b], st)) != GFW_OK) return s;
+        if ((s = upload(bt.plain[b], &bt.d_plain[b], st)) != GFW_OK) return s;
+        if ((s = upload(bt.sorted[b], &bt.d_sorted[b], st)) != GFW_OK) return s;
+    }
+    if ((s = upload(bt.all_rows, &bt.d_all, st)) != GFW_OK) return s;
+    if ((s = upload(ctl0, &bt.d_ctl0, st)) != GFW_OK) return s;
+    if (any_u0 && (s = upload(u0, (const T ***)&bt.d_U0, st)) != GFW_OK) return s;
+    if (labels_out && (s = upload(lab_out, &bt.d_lab_out, st)) != GFW_OK) return s;
+    if (hipMalloc(&bt.d_flag, sizeof(int32_t)) != hipSuccess) return fail(GFW_E_NOMEM, "batch flag allocation");
+    GFW_HIP_TRY(hipHostMalloc((void **)&bt.h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+
+    // U_0 and P_0 = L_s U_0 for every graph
+    k_set_ctl_batch<T><<<grid_for(count, 256), 256, 0, st>>>(bt.d_views, bt.d_ctl0, count);
+    k_init_u_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_U0);
+    if (!bt.rows[0].empty()) k_spmm_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
+    if (!bt.rows[1].empty()) k_spmm_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
+    if (!bt.rows[2].empty()) k_spmm_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
+    GFW_HIP_TRY(hipGetLastError());
+
+    // iterations: every graph advances in the same launches until its own stop; the host
+    // checks, one chunk behind, whether any graph is still running
+    constexpr int chunk = 8;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; ++i) GFW_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    const int reps = (int)cdiv(max_iter, chunk);
+    for (int r = 0; r < reps; ++r) {
+        for (int c = 0; c < chunk; ++c) batch_iteration<T>(bt, st);
+        if (!watch_stop) continue;
+        k_any_active<T><<<1, 256, 0, st>>>(bt.d_views, count, bt.d_flag);
+        GFW_HIP_TRY(hipMemcpyAsync(&bt.h_flag[r & 1], bt.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipEventRecord(ev[r & 1], st));
+        if (r >= 1) {
+            GFW_HIP_TRY(hipEventSynchronize(ev[(r - 1) & 1]));
+            if (bt.h_flag[(r - 1) & 1] == 0) break;
+        }
+    }
+    batch_row_launch<T>(bt, 1, st); // commit the last pending updates
+    GFW_HIP_TRY(hipGetLastError());
+    for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ev[i]);
+
+    // outputs
+    if (U_out)
+        for (int32_t i = 0; i < count; ++i)
+            if (U_out[i])
+                GFW_HIP_TRY(hipMemcpyAsync(U_out[i], gs[i]->ws.U, dsize(gs[i]->dtype) * gs[i]->n * gs[i]->K,
+                                           hipMemcpyDeviceToDevice, st));
+    if (labels_out) k_labels_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_lab_out);
+    if (stats) {
+        if (!bt.rows[0].empty())
+            k_spmm_to_q_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
+        if (!bt.rows[1].empty())
+            k_spmm_to_q_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
+        if (!bt.rows[2].empty())
+            k_spmm_to_q_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
+        k_energy_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all);
+        if (hipMalloc(&bt.d_E, sizeof(double) * count) != hipSuccess ||
+            hipMalloc(&bt.d_ctl_out, sizeof(Ctl) * count) != hipSuccess)
+            return fail(GFW_E_NOMEM, "batch stats allocation");
+        k_collect_batch<T><<<count, kFinishThreads, 0, st>>>(bt.d_views, bt.d_E, bt.d_ctl_out);
+        std::vector<double> E((size_t)count);
+        std::vector<Ctl> cs((size_t)count);
+        GFW_HIP_TRY(hipMemcpyAsync(E.data(), bt.d_E, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipMemcpyAsync(cs.data(), bt.d_ctl_out, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipStreamSynchronize(st));
+        bool nan = false;
+        for (int32_t i = 0; i < count; ++i) {
+            stats[i].iters = cs[(size_t)i].iters;
+            stats[i].stop_reason = cs[(size_t)i].stop_reason;
+            stats[i].gap = cs[(size_t)i].gap;
+            stats[i].alpha_last = cs[(size_t)i].alpha_last;
+            stats[i].objective = E[(size_t)i];
+            nan = nan || cs[(size_t)i].stop_reason == GFW_STOP_NUMERIC;
+        }
+        if (nan) return fail(GFW_E_NUMERIC, "NaN met in at least one graph of the batch");
+    } else {
+        GFW_HIP_TRY(hipStreamSynchronize(st)); // the batch tables are freed on return
+    }
+    GFW_HIP_TRY(hipGetLastError());
     return GFW_OK;
 }
 
@@ -748,6 +1113,29 @@ gfw_status_t gfw_graph_footprint(gfw_graph_t g, size_t *graph_bytes, size_t *sol
     return GFW_OK;
 }
 
+gfw_status_t gfw_graph_tune(gfw_graph_t g, gfw_tune_t key, int64_t value)
+{
+    if (!g) return fail(GFW_E_INVALID_ARG, "graph is NULL");
+    if (key != GFW_TUNE_LABEL_PATH) return fail(GFW_E_INVALID_ARG, "unknown tuning key %d", (int)key);
+    if (value < 0 || value > 2) return fail(GFW_E_INVALID_ARG, "label path must be 0, 1 or 2");
+    GFW_HIP_TRY(hipSetDevice(g->ctx->device));
+    const int before = g->label_path;
+    gfw_status_t s = choose_label_path(g, (int)value, nullptr);
+    if (s == GFW_OK && before != g->label_path && g->ws.iter_exec) {
+        (void)hipGraphExecDestroy(g->ws.iter_exec);
+        g->ws.iter_exec = nullptr;
+    }
+    return s;
+}
+
+gfw_status_t gfw_graph_query(gfw_graph_t g, gfw_tune_t key, int64_t *value)
+{
+    if (!g || !value) return fail(GFW_E_INVALID_ARG, "NULL argument");
+    if (key != GFW_TUNE_LABEL_PATH) return fail(GFW_E_INVALID_ARG, "unknown tuning key %d", (int)key);
+    *value = g->label_path == 1 ? 2 : 1;
+    return GFW_OK;
+}
+
 gfw_status_t gfw_solve(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm, void *U_out, int32_t *labels_out,
                        int32_t *s_out, gfw_stats_t *stats, double *history, void *stream)
 {
@@ -780,6 +1168,37 @@ gfw_status_t gfw_solve(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm
         if (stats->stop_reason == GFW_STOP_NUMERIC) return fail(GFW_E_NUMERIC, "NaN met during the iteration");
     }
     return GFW_OK;
+}
+
+gfw_status_t gfw_solve_batched(gfw_context_t ctx, int32_t count, const gfw_graph_t *graphs, const gfw_params_t *prm,
+                               int32_t shared_params, void *const *U_out, int32_t *const *labels_out,
+                               gfw_stats_t *stats, void *stream)
+{
+    if (!ctx || !graphs || !prm) return fail(GFW_E_INVALID_ARG, "NULL argument");
+    if (count < 0) return fail(GFW_E_INVALID_ARG, "count must be >= 0");
+    if (count == 0) return GFW_OK;
+    std::vector<gfw_graph_s *> gs((size_t)count);
+    std::vector<const gfw_params_t *> ps((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        gs[(size_t)i] = graphs[i];
+        if (!graphs[i]) return fail(GFW_E_INVALID_ARG, "graph %d is NULL", i);
+        if (graphs[i]->ctx != ctx) return fail(GFW_E_INVALID_ARG, "graph %d belongs to another context", i);
+        if (graphs[i]->dtype != graphs[0]->dtype) return fail(GFW_E_UNSUPPORTED, "a batch must share one dtype");
+        if (graphs[i]->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by the batched solver");
+        ps[(size_t)i] = shared_params ? prm : prm + i;
+        gfw_status_t s = check_params(ps[(size_t)i], graphs[i]->K);
+        if (s != GFW_OK) return s;
+        if (ps[(size_t)i]->p_refresh != 0) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported in batches");
+    }
+    std::vector<gfw_graph_s *> sorted_gs = gs;
+    std::sort(sorted_gs.begin(), sorted_gs.end());
+    if (std::adjacent_find(sorted_gs.begin(), sorted_gs.end()) != sorted_gs.end())
+        return fail(GFW_E_INVALID_ARG, "a graph appears twice in the batch");
+    GFW_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    return graphs[0]->dtype == GFW_F32
+               ? solve_batched_impl<float>(ctx, count, gs.data(), ps.data(), U_out, labels_out, stats, st)
+               : solve_batched_impl<double>(ctx, count, gs.data(), ps.data(), U_out, labels_out, stats, st);
 }
 
 gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm, const void *U, double *E_host,

@@ -88,6 +88,13 @@ struct gfw_graph_s {
     int32_t *lab = nullptr;     // int32[n], class of labelled nodes, -1 elsewhere
     int64_t n_labelled = 0;
     double rho_max = 0.0;       // max Gershgorin radius of the operator
+    // column-sorted copy of the CSR for the label pass (see k_label_sorted)
+    int label_path = 0;         // 0: plain (k_label), 1: column-sorted (k_label_sorted)
+    int32_t n_tiles = 0;
+    int32_t *tile_rows = nullptr; // int32[n_tiles + 1]
+    int32_t *gcol = nullptr;      // int32[nnz], columns sorted within each tile
+    uint16_t *gpos = nullptr;     // uint16[nnz], CSR offset inside the tile
+    double locality = 0.0;        // mean distinct 128-node label lines per 64 consecutive entries
     int diag_one = 1;           // 1: operator is I + A (kind W); 0: operator is A (kind L)
     gfw::Shape shape;
     gfw::Workspace ws;

@@ -204,58 +204,6 @@ __global__ void k_fill_i32(int64_t n, int32_t *p, int32_t v)
 // per-solve kernels
 // ---------------------------------------------------------------------------------
 
-// U_0 = Uhat: labelled rows one-hot, others 1/K (Section 5.1); or a copy of U0.
-template <typename T>
-__global__ void k_init_u(int64_t n, int32_t K, const int32_t *__restrict__ lab, const T *__restrict__ U0,
-                         T *__restrict__ U)
-{
-    const int64_t nK = n * K;
-    const T invK = (T)(1.0 / (double)K);
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nK; t += (int64_t)gridDim.x * blockDim.x) {
-        if (U0) { U[t] = U0[t]; continue; }
-        const int64_t i = t / K;
-        const int32_t c = (int32_t)(t - i * K);
-        const int32_t y = lab[i];
-        U[t] = y >= 0 ? (c == y ? (T)1 : (T)0) : invK;
-    }
-}
-
-// P = c U + A U with A the stored CSR values and c = 1 (L_s) or 0 (kind L).
-// LPR lanes cooperate on a row; each lane accumulates KMAX partial sums over its share of
-// the row's entries, and the lanes are combined by a butterfly.  K <= KMAX.
-template <typename T, int KMAX, int LPR>
-__global__ void __launch_bounds__(kRowBlock) k_spmm(int64_t n, int32_t K, const int32_t *__restrict__ rp,
-                                                     const int32_t *__restrict__ ci, const T *__restrict__ a,
-                                                     int diag_one, const T *__restrict__ U, T *__restrict__ P)
-{
-    const int lane = threadIdx.x % LPR;
-    const int64_t rows_per_grid = (int64_t)gridDim.x * (kRowBlock / LPR);
-    for (int64_t i = blockIdx.x * (int64_t)(kRowBlock / LPR) + threadIdx.x / LPR; i < n; i += rows_per_grid) {
-        double acc[KMAX];
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c) acc[c] = 0.0;
-        const int32_t b = rp[i], e = rp[i + 1];
-        for (int32_t p = b + lane; p < e; p += LPR) {
-            const int64_t j = ci[p];
-            const double av = (double)a[p];
-            const T *uj = U + j * K;
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c)
-                if (c < K) acc[c] += av * (double)uj[c];
-        }
-#pragma unroll
-        for (int off = LPR / 2; off > 0; off >>= 1)
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c) acc[c] += __shfl_xor(acc[c], off, LPR);
-        if (lane == 0) {
-            const T *ui = U + i * K;
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c)
-                if (c < K) P[i * K + c] = (T)(diag_one ? (double)ui[c] + acc[c] : acc[c]);
-        }
-    }
-}
-
 // Block sum of N per-thread values, stored at out[j * stride] (fixed order).
 template <int N>
 __device__ __forceinline__ void block_sum_store_strided(double (&v)[N], double *out, int64_t stride)
@@ -276,18 +224,54 @@ __device__ __forceinline__ void block_sum_store_strided(double (&v)[N], double *
     }
 }
 
-// Row kernel: pending update, gradient, GLMO, per-row partials.
-// A block owns kRowBlock consecutive rows.  Their U, P and Q rows form contiguous runs of
-// rows*K elements, moved between HBM and LDS with coalesced accesses; each thread then
-// works on one row out of LDS.  Partials are stored transposed: part[j * gridDim.x + b].
-// Dynamic LDS: 3 * kRowBlock * K * sizeof(T).
+constexpr int kLabelTile = 2048; // CSR entries staged in LDS per step of the label pass
+constexpr int kSortedThreads = 1024;   // threads per tile of the column-sorted label pass
+constexpr int kSortedMaxEntries = 65536; // CSR entries per tile (16-bit positions, 64 KB of labels)
+
+// Everything a per-iteration kernel needs to know about one graph and its solve state.
+// The single-graph kernels take one view as an argument; the batched kernels look up the
+// view of each workgroup's graph in a device array.  Both run the same device functions on
+// the same tiles, so a graph's results do not depend on what else shares the launch.
+template <typename T>
+struct GraphView {
+    int64_t n;
+    int32_t K, diag_one;
+    const int32_t *rp, *ci;
+    const T *a;
+    const int32_t *lab;
+    T *U, *P, *Q;
+    uint8_t *s0, *s1;
+    Ctl *ctl;
+    double *row_part, *lab_part;
+    int32_t nb_row;   // 256-row tiles (row kernel, plain label pass, SpMM)
+    int32_t n_tiles;  // tiles of the column-sorted label pass (0: plain pass)
+    const int32_t *tile_rows, *gcol;
+    const uint16_t *gpos;
+};
+
+// workgroup -> (graph, tile) of a batched launch
+struct TileRef {
+    int32_t graph, tile;
+};
+
+// Row kernel body (see the file header): pending update, gradient, GLMO, per-row partials.
+// A block owns tile `tile` (kRowBlock consecutive rows).  Their U, P and Q rows form
+// contiguous runs of rows*K elements, moved between HBM and LDS with coalesced accesses;
+// each thread then works on one row out of LDS.  Partials are stored transposed:
+// row_part[j * nb_row + tile].  Dynamic LDS: 3 * kRowBlock * K * sizeof(T).
 template <typename T, typename ST, int KB>
-__global__ void __launch_bounds__(kRowBlock) k_row(int64_t n, int32_t K, const int32_t *__restrict__ lab,
-                                                    T *__restrict__ U, T *__restrict__ P, const T *__restrict__ Q,
-                                                    ST *__restrict__ s0, ST *__restrict__ s1,
-                                                    const Ctl *__restrict__ ctl, double *__restrict__ part,
-                                                    int apply_only)
+__device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile, const int apply_only)
 {
+    const int64_t n = gv.n;
+    const int32_t K = gv.K;
+    const int32_t *__restrict__ lab = gv.lab;
+    T *__restrict__ U = gv.U;
+    T *__restrict__ P = gv.P;
+    const T *__restrict__ Q = gv.Q;
+    ST *__restrict__ s0 = gv.s0;
+    ST *__restrict__ s1 = gv.s1;
+    const Ctl *__restrict__ ctl = gv.ctl;
+    double *__restrict__ part = gv.row_part;
     // apply_only: commit the pending update and evaluate nothing
     const int32_t active = apply_only ? 0 : ctl->active, pending = ctl->pending;
     if (!active && !pending) return;
@@ -302,7 +286,7 @@ __global__ void __launch_bounds__(kRowBlock) k_row(int64_t n, int32_t K, const i
     T *lp = lu + kRowBlock * K;
     T *lq = lp + kRowBlock * K;
     const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * kRowBlock;
+    const int64_t r0 = (int64_t)tile * kRowBlock;
     const int rows = (int)min((int64_t)kRowBlock, n - r0);
     const int cnt = rows * K;
     const int64_t base = r0 * K;
@@ -471,25 +455,30 @@ __global__ void __launch_bounds__(kRowBlock) k_row(int64_t n, int32_t K, const i
         }
     }
     if (!active) return;
-    block_sum_store_strided<kRowParts>(acc, part + blockIdx.x, gridDim.x);
+    block_sum_store_strided<kRowParts>(acc, part + tile, gv.nb_row);
 }
 
-constexpr int kLabelTile = 2048; // CSR entries staged in LDS per step of the label pass
-
-// Label pass: Q = L_s S for the one-hot S given by s (a per-row histogram of neighbour
-// labels weighted by the stored values), and the per-row terms Q_{i, s_i}.
-// A block owns kRowBlock consecutive rows, i.e. one contiguous range of CSR entries.  The
-// range is streamed through LDS in tiles: all threads load column indices and values with
-// coalesced accesses and gather the one-byte labels of the columns; then each thread sums
-// the entries of its own row in CSR order.  Q is staged in LDS (dynamic, kRowBlock * K *
-// sizeof(T)) and written back coalesced.  One partial per block.
+// Label pass body (plain): Q = L_s S for the one-hot S given by s (a per-row histogram of
+// neighbour labels weighted by the stored values), and the per-row terms Q_{i, s_i}.
+// A block owns tile `tile` (kRowBlock consecutive rows, one contiguous range of CSR
+// entries), streamed through LDS in sub-tiles: all threads load column indices and values
+// with coalesced accesses and gather the one-byte labels of the columns; then each thread
+// sums the entries of its own row in CSR order.  Q is staged in LDS (dynamic, kRowBlock *
+// K * sizeof(T)) and written back coalesced.  One partial per tile: lab_part[tile].
 template <typename T, typename ST, int KB>
-__global__ void __launch_bounds__(kRowBlock) k_label(int64_t n, int32_t K, const int32_t *__restrict__ rp,
-                                                      const int32_t *__restrict__ ci, const T *__restrict__ a,
-                                                      int diag_one, const ST *__restrict__ s0,
-                                                      const ST *__restrict__ s1, T *__restrict__ Q,
-                                                      const Ctl *__restrict__ ctl, double *__restrict__ part)
+__device__ __forceinline__ void label_body(const GraphView<T> &gv, const int tile)
 {
+    const int64_t n = gv.n;
+    const int32_t K = gv.K;
+    const int32_t *__restrict__ rp = gv.rp;
+    const int32_t *__restrict__ ci = gv.ci;
+    const T *__restrict__ a = gv.a;
+    const int diag_one = gv.diag_one;
+    const ST *__restrict__ s0 = gv.s0;
+    const ST *__restrict__ s1 = gv.s1;
+    T *__restrict__ Q = gv.Q;
+    const Ctl *__restrict__ ctl = gv.ctl;
+    double *__restrict__ part = gv.lab_part;
     if (!ctl->active) return;
     const ST *__restrict__ s = (ctl->k & 1) ? s1 : s0;
     __shared__ ST ls[kLabelTile];
@@ -497,7 +486,7 @@ __global__ void __launch_bounds__(kRowBlock) k_label(int64_t n, int32_t K, const
     extern __shared__ unsigned char lds_raw[];
     T *lq = reinterpret_cast<T *>(lds_raw);
     const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * kRowBlock;
+    const int64_t r0 = (int64_t)tile * kRowBlock;
     const int rows = (int)min((int64_t)kRowBlock, n - r0);
     const bool has_row = tid < rows;
     const int64_t i = r0 + tid;
@@ -574,14 +563,150 @@ __global__ void __launch_bounds__(kRowBlock) k_label(int64_t n, int32_t K, const
     const int64_t base = r0 * K;
     for (int q = tid; q < cntq; q += kRowBlock) Q[base + q] = lq[q];
     double v[1] = {own};
-    block_sum_store_strided<1>(v, part + blockIdx.x, gridDim.x);
+    block_sum_store_strided<1>(v, part + tile, gv.nb_row);
 }
 
-// Finish: fixed-order reduction of the partials, gap, objective, curvature, step size.
-// row_part is [kRowParts][nb_row], lab_part is [nb_lab].
-__global__ void __launch_bounds__(kFinishThreads) k_finish(const double *__restrict__ row_part, int nb_row,
-                                                           const double *__restrict__ lab_part, int nb_lab,
-                                                           Ctl *__restrict__ ctl)
+// Column-sorted label pass body: the same Q = L_s S and per-tile partial as label_body, for
+// graphs whose neighbour labels are scattered (random node order).  A workgroup owns one
+// tile of consecutive rows holding at most kSortedMaxEntries CSR entries.  The tile's
+// entries are stored twice: in CSR order (values) and sorted by column (gcol, with gpos the
+// entry's offset inside the tile's CSR range).
+//  1. gather: consecutive threads take consecutive column-sorted entries, so the labels they
+//     load lie close together and share cache lines; each label is written into an LDS
+//     array at the entry's CSR offset.
+//  2. rows: each thread sums the histogram of its rows in CSR order, values read from
+//     global memory (a row's values are contiguous) and labels from LDS (the same order,
+//     hence the same result, as label_body).
+//  3. Q rows are staged in LDS (reusing the label array) and written coalesced.
+// Dynamic LDS: kSortedMaxEntries bytes (labels, later Q staging).
+// On a randomly ordered graph the gathers of phase 1 bound this kernel (the L1 address
+// path stalls on scattered lines); sorting within a tile halves the L2 requests of the
+// gathers compared with label_body.
+template <typename T, typename ST, int KB>
+__device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const int tile)
+{
+    const int32_t K = gv.K;
+    const int32_t *__restrict__ rp = gv.rp;
+    const int32_t *__restrict__ tile_rows = gv.tile_rows;
+    const int32_t *__restrict__ gcol = gv.gcol;
+    const uint16_t *__restrict__ gpos = gv.gpos;
+    const T *__restrict__ a = gv.a;
+    const int diag_one = gv.diag_one;
+    const ST *__restrict__ s0 = gv.s0;
+    const ST *__restrict__ s1 = gv.s1;
+    T *__restrict__ Q = gv.Q;
+    const Ctl *__restrict__ ctl = gv.ctl;
+    double *__restrict__ part = gv.lab_part;
+    if (!ctl->active) return;
+    const ST *__restrict__ s = (ctl->k & 1) ? s1 : s0;
+    extern __shared__ unsigned char lds_raw[];
+    uint8_t *llab = lds_raw;                                                  // [kSortedMaxEntries]
+    const int tid = threadIdx.x;
+    const int32_t r0 = tile_rows[tile], r1 = tile_rows[tile + 1];
+    const int32_t e0 = rp[r0], e1 = rp[r1];
+    const int E = e1 - e0;
+    const int rows = r1 - r0;
+
+    // 1. gather labels in column order, scatter them to CSR positions in LDS
+    constexpr int G = 8;
+    for (int b = 0; b < E; b += G * kSortedThreads) {
+        int32_t cc[G];
+        int pp[G];
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+            const int e = min(b + tid + m * kSortedThreads, E - 1);
+            cc[m] = __builtin_nontemporal_load(gcol + e0 + e);
+            pp[m] = (int)__builtin_nontemporal_load(gpos + e0 + e);
+        }
+        ST ss[G];
+#pragma unroll
+        for (int m = 0; m < G; ++m) ss[m] = s[cc[m]];
+#pragma unroll
+        for (int m = 0; m < G; ++m)
+            if (b + tid + m * kSortedThreads < E) llab[pp[m]] = (uint8_t)ss[m];
+    }
+    __syncthreads();
+
+    // 2. each thread owns rows r0 + tid + j * kSortedThreads (j < 4)
+    constexpr int RPT = 4;
+    T acc[RPT][KB];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+#pragma unroll
+        for (int c = 0; c < KB; ++c) acc[j][c] = (T)0;
+    int rb[RPT], re[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = tid + j * kSortedThreads;
+        rb[j] = r < rows ? rp[r0 + r] - e0 : 0;
+        re[j] = r < rows ? rp[r0 + r + 1] - e0 : 0;
+    }
+    // the values of a row are contiguous; each thread reads its rows' values directly
+    // (four at a time) and the labels from LDS
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        int p = rb[j];
+        for (; p + 4 <= re[j]; p += 4) {
+            T v[4];
+            int32_t sj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v[u] = a[e0 + p + u];
+                sj[u] = (int32_t)llab[p + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < KB; ++c) acc[j][c] += (c == sj[u]) ? v[u] : (T)0;
+        }
+        for (; p < re[j]; ++p) {
+            const T v = a[e0 + p];
+            const int32_t sj = (int32_t)llab[p];
+#pragma unroll
+            for (int c = 0; c < KB; ++c) acc[j][c] += (c == sj) ? v : (T)0;
+        }
+    }
+    __syncthreads(); // all label reads done: the label array becomes the Q staging area
+
+    // 3. Q rows (rows * K * sizeof(T) <= kSortedMaxEntries by construction of the tiles)
+    T *lq = reinterpret_cast<T *>(llab);
+    double own = 0.0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int r = tid + j * kSortedThreads;
+        if (r < rows) {
+            const int32_t si = (int32_t)s[r0 + r];
+#pragma unroll
+            for (int c = 0; c < KB; ++c) {
+                if (c < K) {
+                    const T v = acc[j][c] + ((diag_one && c == si) ? (T)1 : (T)0);
+                    lq[r * K + c] = v;
+                    if (c == si) own += (double)v;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int cntq = rows * K;
+    const int64_t base = (int64_t)r0 * K;
+    for (int q = tid; q < cntq; q += kSortedThreads) Q[base + q] = lq[q];
+    // fixed-order block sum (16 waves)
+    __shared__ double red[kSortedThreads / 64];
+    own = wave_sum(own);
+    if ((tid & 63) == 0) red[tid >> 6] = own;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kSortedThreads / 64; ++w) t += red[w];
+        part[tile] = t;
+    }
+}
+
+// Finish body: fixed-order reduction of the partials, gap, objective, curvature, step size,
+// stop test and history entry of one graph.  row_part is [kRowParts][nb_row], lab_part is
+// [nb_lab].  One workgroup of kFinishThreads threads per graph.
+__device__ __forceinline__ void finish_body(const double *__restrict__ row_part, int nb_row,
+                                            const double *__restrict__ lab_part, int nb_lab, Ctl *__restrict__ ctl)
 {
     if (!ctl->active) {
         if (threadIdx.x == 0) ctl->pending = 0;
@@ -692,6 +817,310 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish(const double *__restr
     }
 }
 
+// U_0 = Uhat (labelled rows one-hot, others 1/K; Section 5.1), or a copy of U0, for the rows
+// of tile `tile`.
+template <typename T>
+__device__ __forceinline__ void init_body(const GraphView<T> &gv, const T *__restrict__ U0, const int tile)
+{
+    const int32_t K = gv.K;
+    const int64_t r0 = (int64_t)tile * kRowBlock;
+    const int rows = (int)min((int64_t)kRowBlock, gv.n - r0);
+    const T invK = (T)(1.0 / (double)K);
+    for (int q = threadIdx.x; q < rows * K; q += kRowBlock) {
+        const int64_t t = r0 * K + q;
+        if (U0) {
+            gv.U[t] = U0[t];
+            continue;
+        }
+        const int64_t i = r0 + q / K;
+        const int32_t c = q % K;
+        const int32_t y = gv.lab[i];
+        gv.U[t] = y >= 0 ? (c == y ? (T)1 : (T)0) : invK;
+    }
+}
+
+// P = c U + A U (A the stored CSR values, c = 1 for L_s, 0 for a user operator) for the
+// rows of tile `tile`: the tile's column indices and values are staged through LDS with
+// coalesced loads, and each thread sums its row in CSR order in FP64, gathering the K-wide
+// rows u_j.  The result depends on nothing but the row, so it is the same in every launch
+// shape.  K <= KB.
+template <typename T, int KB>
+__device__ __forceinline__ void spmm_body(const GraphView<T> &gv, const T *__restrict__ Uin, T *__restrict__ Pout,
+                                          const int tile)
+{
+    __shared__ int32_t lc[kLabelTile];
+    __shared__ T lv[kLabelTile];
+    const int32_t K = gv.K;
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)tile * kRowBlock;
+    const int rows = (int)min((int64_t)kRowBlock, gv.n - r0);
+    const bool has_row = tid < rows;
+    const int64_t i = r0 + tid;
+    const int32_t b = has_row ? gv.rp[i] : 0, e = has_row ? gv.rp[i + 1] : 0;
+    const int32_t t_begin = gv.rp[r0], t_end = gv.rp[r0 + rows];
+    double acc[KB];
+#pragma unroll
+    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    constexpr int PER = kLabelTile / kRowBlock;
+    for (int32_t t0 = t_begin; t0 < t_end; t0 += kLabelTile) {
+        const int cnt = (int)min((int32_t)kLabelTile, t_end - t0);
+        int32_t jj[PER];
+        T vv[PER];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int q = min(tid + m * kRowBlock, cnt - 1);
+            jj[m] = gv.ci[t0 + q];
+            vv[m] = gv.a[t0 + q];
+        }
+        __syncthreads(); // the previous sub-tile has been consumed
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const int q = tid + m * kRowBlock;
+            if (q < cnt) {
+                lc[q] = jj[m];
+                lv[q] = vv[m];
+            }
+        }
+        __syncthreads();
+        if (has_row) {
+            const int32_t pb = max(b, t0), pe = min(e, t0 + cnt);
+            for (int32_t p = pb; p < pe; ++p) {
+                const T *uj = Uin + (int64_t)lc[p - t0] * K;
+                const double v = (double)lv[p - t0];
+#pragma unroll
+                for (int c = 0; c < KB; ++c)
+                    if (c < K) acc[c] += v * (double)uj[c];
+            }
+        }
+    }
+    if (has_row) {
+        const T *ui = Uin + i * K;
+#pragma unroll
+        for (int c = 0; c < KB; ++c)
+            if (c < K) Pout[i * K + c] = (T)(gv.diag_one ? (double)ui[c] + acc[c] : acc[c]);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) k_init_u(GraphView<T> gv, const T *__restrict__ U0)
+{
+    init_body<T>(gv, U0, blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) k_init_u_batch(const GraphView<T> *__restrict__ views,
+                                                             const TileRef *__restrict__ refs,
+                                                             const T *const *__restrict__ U0s)
+{
+    const TileRef r = refs[blockIdx.x];
+    init_body<T>(views[r.graph], U0s ? U0s[r.graph] : nullptr, r.tile);
+}
+
+template <typename T, int KB>
+__global__ void __launch_bounds__(kRowBlock) k_spmm(GraphView<T> gv, const T *__restrict__ Uin, T *__restrict__ Pout)
+{
+    spmm_body<T, KB>(gv, Uin, Pout, blockIdx.x);
+}
+
+// batched L_s U_0 -> P at the start of a batched solve
+template <typename T, int KB>
+__global__ void __launch_bounds__(kRowBlock) k_spmm_batch(const GraphView<T> *__restrict__ views,
+                                                           const TileRef *__restrict__ refs)
+{
+    const TileRef r = refs[blockIdx.x];
+    const GraphView<T> &gv = views[r.graph];
+    spmm_body<T, KB>(gv, gv.U, gv.P, r.tile);
+}
+
+// ---------------------------------------------------------------------------------
+// single-graph and batched entry points
+// ---------------------------------------------------------------------------------
+template <typename T, typename ST, int KB>
+__global__ void __launch_bounds__(kRowBlock) k_row(GraphView<T> gv, int apply_only)
+{
+    row_body<T, ST, KB>(gv, blockIdx.x, apply_only);
+}
+
+template <typename T, typename ST, int KB>
+__global__ void __launch_bounds__(kRowBlock) k_row_batch(const GraphView<T> *__restrict__ views,
+                                                          const TileRef *__restrict__ refs, int apply_only)
+{
+    const TileRef r = refs[blockIdx.x];
+    row_body<T, ST, KB>(views[r.graph], r.tile, apply_only);
+}
+
+template <typename T, typename ST, int KB>
+__global__ void __launch_bounds__(kRowBlock) k_label(GraphView<T> gv)
+{
+    label_body<T, ST, KB>(gv, blockIdx.x);
+}
+
+template <typename T, typename ST, int KB>
+__global__ void __launch_bounds__(kRowBlock) k_label_batch(const GraphView<T> *__restrict__ views,
+                                                            const TileRef *__restrict__ refs)
+{
+    const TileRef r = refs[blockIdx.x];
+    label_body<T, ST, KB>(views[r.graph], r.tile);
+}
+
+template <typename T, typename ST, int KB>
+__global__ void __launch_bounds__(kSortedThreads) k_label_sorted(GraphView<T> gv)
+{
+    label_sorted_body<T, ST, KB>(gv, blockIdx.x);
+}
+
+template <typename T, typename ST, int KB>
+__global__ void __launch_bounds__(kSortedThreads) k_label_sorted_batch(const GraphView<T> *__restrict__ views,
+                                                                        const TileRef *__restrict__ refs)
+{
+    const TileRef r = refs[blockIdx.x];
+    label_sorted_body<T, ST, KB>(views[r.graph], r.tile);
+}
+
+__global__ void __launch_bounds__(kFinishThreads) k_finish(const double *__restrict__ row_part, int nb_row,
+                                                           const double *__restrict__ lab_part, int nb_lab,
+                                                           Ctl *__restrict__ ctl)
+{
+    finish_body(row_part, nb_row, lab_part, nb_lab, ctl);
+}
+
+// Terms of E(U) (eq. gl_vv2) from their definitions given P = L U, for the rows of tile
+// `tile`: <u,P>, sum u(1-u), sum omega_i ||uhat_i - u_i||^2; stored at part[j * nb_row + tile].
+template <typename T>
+__device__ __forceinline__ void energy_body(const GraphView<T> &gv, const T *__restrict__ U, const T *__restrict__ P,
+                                            double omega0, double *__restrict__ part, const int tile)
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x;
+    if (i < gv.n) {
+        const int32_t y = gv.lab[i];
+        for (int32_t c = 0; c < gv.K; ++c) {
+            const double u = (double)U[i * gv.K + c];
+            acc[0] += u * (double)P[i * gv.K + c];
+            acc[1] += u * (1.0 - u);
+            if (y >= 0) {
+                const double e = (c == y ? 1.0 : 0.0) - u;
+                acc[2] += omega0 * e * e;
+            }
+        }
+    }
+    block_sum_store_strided<3>(acc, part + tile, gv.nb_row);
+}
+
+// E = 1/2 <U, L U> + (1/eps) sum u(1-u) + 1/2 sum omega ||uhat - u||^2 from the tile partials.
+__device__ __forceinline__ void energy_sum_body(const double *__restrict__ part, int nb, double inv_eps,
+                                                double *__restrict__ out)
+{
+    __shared__ double red[kFinishThreads / 64][3];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += kFinishThreads)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[j] += part[(int64_t)j * nb + b];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) v[j] = wave_sum(v[j]);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) red[threadIdx.x >> 6][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int w = 0; w < kFinishThreads / 64; ++w)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) t[j] += red[w][j];
+        *out = 0.5 * t[0] + inv_eps * t[1] + 0.5 * t[2];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) k_energy(GraphView<T> gv, const T *__restrict__ U, const T *__restrict__ P,
+                                                       double omega0, double *__restrict__ part)
+{
+    energy_body<T>(gv, U, P, omega0, part, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kFinishThreads) k_energy_sum(const double *__restrict__ part, int nb,
+                                                               double inv_eps, double *__restrict__ out)
+{
+    energy_sum_body(part, nb, inv_eps, out);
+}
+
+// batched objective of the final iterates: P = L U goes to Q (free after the solve), the
+// tile partials to row_part
+template <typename T, int KB>
+__global__ void __launch_bounds__(kRowBlock) k_spmm_to_q_batch(const GraphView<T> *__restrict__ views,
+                                                                const TileRef *__restrict__ refs)
+{
+    const TileRef r = refs[blockIdx.x];
+    const GraphView<T> &gv = views[r.graph];
+    spmm_body<T, KB>(gv, gv.U, gv.Q, r.tile);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) k_energy_batch(const GraphView<T> *__restrict__ views,
+                                                             const TileRef *__restrict__ refs)
+{
+    const TileRef r = refs[blockIdx.x];
+    const GraphView<T> &gv = views[r.graph];
+    energy_body<T>(gv, gv.U, gv.Q, gv.ctl->sp.omega0, gv.row_part, r.tile);
+}
+
+// one workgroup per graph: objective and a copy of the control block
+template <typename T>
+__global__ void __launch_bounds__(kFinishThreads) k_collect_batch(const GraphView<T> *__restrict__ views,
+                                                                  double *__restrict__ E, Ctl *__restrict__ ctls)
+{
+    const GraphView<T> &gv = views[blockIdx.x];
+    energy_sum_body(gv.row_part, gv.nb_row, gv.ctl->sp.inv_eps, E + blockIdx.x);
+    if (threadIdx.x == 0) ctls[blockIdx.x] = *gv.ctl;
+}
+
+// writes the initial control blocks of a batch
+template <typename T>
+__global__ void k_set_ctl_batch(const GraphView<T> *__restrict__ views, const Ctl *__restrict__ src, int count)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < count; g += gridDim.x * blockDim.x) *views[g].ctl = src[g];
+}
+
+// labels (lowest-index argmax of each row of U) for the rows of a tile
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) k_labels_batch(const GraphView<T> *__restrict__ views,
+                                                             const TileRef *__restrict__ refs,
+                                                             int32_t *const *__restrict__ outs)
+{
+    const TileRef r = refs[blockIdx.x];
+    const GraphView<T> &gv = views[r.graph];
+    int32_t *out = outs[r.graph];
+    const int64_t i = (int64_t)r.tile * kRowBlock + threadIdx.x;
+    if (!out || i >= gv.n) return;
+    const T *u = gv.U + i * gv.K;
+    int32_t at = 0;
+    T best = u[0];
+    for (int32_t c = 1; c < gv.K; ++c)
+        if (u[c] > best) {
+            best = u[c];
+            at = c;
+        }
+    out[i] = at;
+}
+
+// 1 while some graph of the batch still has an iteration to evaluate or an update to commit
+template <typename T>
+__global__ void k_any_active(const GraphView<T> *__restrict__ views, int count, int32_t *__restrict__ flag)
+{
+    int a = 0;
+    for (int g = threadIdx.x; g < count; g += blockDim.x) a |= views[g].ctl->active | views[g].ctl->pending;
+    a = __syncthreads_or(a);
+    if (threadIdx.x == 0) *flag = a;
+}
+
+// one workgroup per graph of the batch
+template <typename T>
+__global__ void __launch_bounds__(kFinishThreads) k_finish_batch(const GraphView<T> *__restrict__ views)
+{
+    const GraphView<T> &gv = views[blockIdx.x];
+    finish_body(gv.row_part, gv.nb_row, gv.lab_part, gv.n_tiles > 0 ? gv.n_tiles : gv.nb_row, gv.ctl);
+}
+
 // labels_i = lowest-index argmax_c U_ic; s_out = vertex indices of the last GLMO output
 // (-1 when no iteration was evaluated).
 template <typename T, typename ST>
@@ -717,46 +1146,6 @@ __global__ void k_outputs(int64_t n, int32_t K, const T *__restrict__ U, const S
 __global__ void k_clear_pending(Ctl *ctl)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) ctl->pending = 0;
-}
-
-// Terms of E(U) from its definition given P = L U: <u,P>, penalty, fidelity.
-template <typename T>
-__global__ void __launch_bounds__(kRowBlock) k_energy_rows(int64_t n, int32_t K, const int32_t *__restrict__ lab,
-                                                            const T *__restrict__ U, const T *__restrict__ P,
-                                                            double omega0, double *__restrict__ part)
-{
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = blockIdx.x * (int64_t)kRowBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRowBlock) {
-        const int32_t y = lab[i];
-        for (int32_t c = 0; c < K; ++c) {
-            const double u = (double)U[i * K + c];
-            acc[0] += u * (double)P[i * K + c];
-            acc[1] += u * (1.0 - u);
-            if (y >= 0) {
-                const double e = (c == y ? 1.0 : 0.0) - u;
-                acc[2] += omega0 * e * e;
-            }
-        }
-    }
-    block_sum_store<3>(acc, part + (int64_t)blockIdx.x * 3);
-}
-
-__global__ void k_sum_parts(const double *__restrict__ part, int nb, int width, double *__restrict__ out)
-{
-    __shared__ double red[kFinishThreads / 64];
-    for (int j = 0; j < width; ++j) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[(int64_t)b * width + j];
-        v = wave_sum(v);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-            out[j] = s;
-        }
-        __syncthreads();
-    }
 }
 
 __global__ void k_max_reduce(const double *__restrict__ v, int64_t n, double *__restrict__ out)

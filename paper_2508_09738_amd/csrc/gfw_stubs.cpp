@@ -7,12 +7,6 @@ void set_error(const char *fmt, ...);
 }
 
 extern "C" {
-gfw_status_t gfw_solve_batched(gfw_context_t, int32_t, const gfw_graph_t *, const gfw_params_t *, int32_t,
-                               void *const *, int32_t *const *, gfw_stats_t *, void *)
-{
-    gfw::set_error("batched solver not available in this build");
-    return GFW_E_UNSUPPORTED;
-}
 gfw_status_t gfw_server_create(gfw_context_t, size_t, int32_t, gfw_server_t *)
 {
     gfw::set_error("server not available in this build");

@@ -31,7 +31,9 @@ EXPORTED = [
     "gfw_context_create", "gfw_context_destroy", "gfw_graph_create", "gfw_graph_destroy", "gfw_graph_footprint",
     "gfw_solve", "gfw_solve_batched", "gfw_objective", "gfw_spmm", "gfw_server_create", "gfw_server_submit",
     "gfw_server_poll", "gfw_server_destroy", "gfw_trace_enable", "gfw_trace_reset", "gfw_trace_get",
+    "gfw_graph_tune", "gfw_graph_query",
 ]
+TUNE_LABEL_PATH = 0
 KERNEL_ROW, KERNEL_LABEL, KERNEL_FINISH, KERNEL_SPMM, KERNEL_FUSED = 0, 1, 2, 3, 4
 
 
@@ -87,13 +89,15 @@ def lib():
         L.gfw_graph_destroy.argtypes = [p]
         L.gfw_graph_footprint.argtypes = [p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.gfw_solve.argtypes = [p, p, C.POINTER(Params), p, p, p, C.POINTER(Stats), p, p]
-        L.gfw_solve_batched.argtypes = [p, C.c_int32, p, C.POINTER(Params), C.c_int32, p, p, C.POINTER(Stats), p]
+        L.gfw_solve_batched.argtypes = [p, C.c_int32, p, p, C.c_int32, p, p, p, p]
         L.gfw_objective.argtypes = [p, p, C.POINTER(Params), p, C.POINTER(C.c_double), p]
         L.gfw_spmm.argtypes = [p, p, p, p, p]
         L.gfw_server_create.argtypes = [p, C.c_size_t, C.c_int32, C.POINTER(p)]
         L.gfw_server_submit.argtypes = [p, C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_uint64)]
         L.gfw_server_poll.argtypes = [p, C.c_uint64, C.c_int, p, p, C.POINTER(Stats)]
         L.gfw_server_destroy.argtypes = [p]
+        L.gfw_graph_tune.argtypes = [p, C.c_int, C.c_int64]
+        L.gfw_graph_query.argtypes = [p, C.c_int, C.POINTER(C.c_int64)]
         L.gfw_trace_enable.argtypes = [p, C.c_int]
         L.gfw_trace_reset.argtypes = [p]
         L.gfw_trace_get.argtypes = [p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -186,6 +190,14 @@ class Graph:
         pb, keep = host_problem(n, K, indptr, indices, data, labelled_idx, labels, dtype, kind)
         return cls(ctx, pb, keep, stream)
 
+    def tune(self, key: int, value: int) -> None:
+        check(lib().gfw_graph_tune(self.handle, key, value))
+
+    def query(self, key: int) -> int:
+        v = C.c_int64()
+        check(lib().gfw_graph_query(self.handle, key, C.byref(v)))
+        return v.value
+
     def footprint(self):
         a, b = C.c_size_t(), C.c_size_t()
         check(lib().gfw_graph_footprint(self.handle, C.byref(a), C.byref(b)))
@@ -246,6 +258,36 @@ def trace_get(ctx: Context, kernel: int):
     ms, n = C.c_double(), C.c_int64()
     check(lib().gfw_trace_get(ctx.handle, kernel, C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def solve_batched(ctx: Context, graphs: list, prms, want_U: bool = True, want_labels: bool = True,
+                  want_stats: bool = True, stream=None) -> list:
+    """gfw_solve_batched over `graphs` (one Params, or one per graph); a list of per-graph dicts."""
+    import torch
+
+    n = len(graphs)
+    dev = torch.device("cuda", ctx.device)
+    shared = isinstance(prms, Params)
+    if shared:
+        parr = prms
+    else:
+        parr = (Params * n)(*prms)
+    gh = (C.c_void_p * n)(*[g.handle.value for g in graphs])
+    Us = [torch.empty((g.n, g.K), dtype=g.torch_dtype(), device=dev) if want_U else None for g in graphs]
+    labs = [torch.empty(g.n, dtype=torch.int32, device=dev) if want_labels else None for g in graphs]
+    uarr = (C.c_void_p * n)(*[u.data_ptr() for u in Us]) if want_U else None
+    larr = (C.c_void_p * n)(*[t.data_ptr() for t in labs]) if want_labels else None
+    st = (Stats * n)() if want_stats else None
+    check(lib().gfw_solve_batched(ctx.handle, n, gh, C.byref(parr) if shared else parr, int(shared), uarr, larr,
+                                  st, _stream(stream)))
+    out = []
+    for i in range(n):
+        d = dict(U=Us[i], labels=labs[i])
+        if st is not None:
+            d.update(iters=st[i].iters, stop_reason=st[i].stop_reason, gap=st[i].gap, objective=st[i].objective,
+                     alpha_last=st[i].alpha_last)
+        out.append(d)
+    return out
 
 
 def objective(ctx: Context, g: Graph, prm: Params, U, stream=None) -> float:

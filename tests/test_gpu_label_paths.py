@@ -1,0 +1,75 @@
+"""The column-sorted label pass against the plain one (and, in lockstep, against the oracle).
+
+Both passes sum every row's label histogram in CSR order, so Q = L_s S is the same; only the
+order of the per-tile partial sums differs.  Graphs here are forced onto the sorted path with
+gfw_graph_tune; they cover FP32/FP64, K = 2..16 (tile limits from the Q staging area),
+rows without entries and a ragged last tile."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_09738_amd import gfw
+from synth import configs, graphs
+
+from gpu_helpers import ctx, gpu_graph, say, torch_u
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype,K,n", [(gfw.F32, 5, 40001), (gfw.F64, 3, 9000), (gfw.F32, 16, 12000),
+                                       (gfw.F64, 16, 5000), (gfw.F32, 2, 70001)])
+def test_sorted_label_pass_matches_plain(dtype, K, n):
+    say(f"[gpu] sorted vs plain label pass dtype={dtype} K={K} n={n}")
+    g = graphs.sbm_by_degree(n, K, 24.0, 8.0, 70 + K)
+    # a few rows without entries: drop the edges of nodes 0..9
+    import scipy.sparse as sp
+    W = sp.csr_matrix((g.data, g.indices, g.indptr), shape=(g.n, g.n)).tolil()
+    for i in range(10):
+        W[i, :] = 0
+        W[:, i] = 0
+    W = W.tocsr()
+    W.eliminate_zeros()
+    W.sort_indices()
+    g = graphs.Graph(g.n, K, W.indptr.astype(np.int64), W.indices.astype(np.int32), W.data, g.truth)
+    idx, lab = graphs.stratified_labels(g.truth, K, 0.02, 70 + K)
+    G = gpu_graph(g, K, idx, lab, dtype)
+    prm = gfw.params(max_iter=25, tol=-1)
+    G.tune(gfw.TUNE_LABEL_PATH, 1)
+    assert G.query(gfw.TUNE_LABEL_PATH) == 1
+    a = gfw.solve(ctx(), G, prm, want_history=True)
+    G.tune(gfw.TUNE_LABEL_PATH, 2)
+    assert G.query(gfw.TUNE_LABEL_PATH) == 2
+    b = gfw.solve(ctx(), G, prm, want_history=True)
+    np.testing.assert_array_equal(a["alpha"], b["alpha"])
+    np.testing.assert_array_equal(_np(a["labels"]), _np(b["labels"]))
+    np.testing.assert_allclose(_np(a["U"]), _np(b["U"]), atol=1e-12 if dtype == gfw.F64 else 1e-6)
+    np.testing.assert_allclose(a["q"][:25], b["q"][:25], rtol=1e-9 if dtype == gfw.F64 else 1e-5)
+
+
+def test_sorted_label_pass_lockstep_against_oracle():
+    say("[gpu] sorted label pass lockstep")
+    prob = configs.sbm_small(5, n_per=3000)
+    L = O.operator_for(prob.graph)
+    G = gpu_graph(prob.graph, prob.K, prob.labelled_idx, prob.labels, gfw.F64)
+    G.tune(gfw.TUNE_LABEL_PATH, 2)
+    for k in (0, 7, 40):
+        Uk = O.fidelity(prob.n, prob.K, prob.labelled_idx, prob.labels, 1000.0)[0] if k == 0 else \
+            O.solve(L, prob.K, prob.labelled_idx, prob.labels, max_iter=k, tol=-1)["U"]
+        ro = O.solve(L, prob.K, prob.labelled_idx, prob.labels, max_iter=1, tol=-1, U0=Uk, record_s=True)
+        rg = gfw.solve(ctx(), G, gfw.params(max_iter=1, tol=-1, U0=torch_u(Uk, gfw.F64)), want_s=True,
+                       want_history=True)
+        if np.array_equal(_np(rg["s"]), ro["s"][0]):
+            assert rg["q"][0] == pytest.approx(ro["q"][0], rel=1e-9)
+            assert rg["alpha"][0] == ro["alpha"][0]
+            np.testing.assert_allclose(_np(rg["U"]), ro["U"], atol=1e-12)
+
+
+def test_auto_choice():
+    say("[gpu] automatic label path choice")
+    grid = graphs.image_grid(20000, 4, 1, neighbours=4)
+    G = gpu_graph(grid, 4, [0], [0], gfw.F32)
+    assert G.query(gfw.TUNE_LABEL_PATH) == 1  # small and local: plain pass
