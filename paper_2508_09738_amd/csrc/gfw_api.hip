@@ -26,26 +26,13 @@ void set_error(const char *fmt, ...)
     va_end(ap);
 }
 
-static gfw_status_t fail(gfw_status_t s, const char *fmt, ...)
+gfw_status_t fail(gfw_status_t s, const char *fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
     va_end(ap);
     return s;
-}
-
-static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-static inline void dfree(void *p)
-{
-    if (p) (void)hipFree(p);
-}
-
-static int grid_for(int64_t work, int threads, int cap = 65535)
-{
-    int64_t b = cdiv(std::max<int64_t>(work, 1), threads);
-    return (int)std::min<int64_t>(b, cap);
 }
 
 // --------------------------------------------------------------------------------------
@@ -175,7 +162,7 @@ static gfw_status_t validate_host_labels(const gfw_problem_t *p)
     return GFW_OK;
 }
 
-static gfw_status_t check_problem(const gfw_problem_t *p)
+gfw_status_t check_problem(const gfw_problem_t *p)
 {
     gfw_status_t s = check_scalars(p);
     if (s != GFW_OK || p->location != GFW_HOST) return s;
@@ -184,7 +171,7 @@ static gfw_status_t check_problem(const gfw_problem_t *p)
     return validate_host_labels(p);
 }
 
-static gfw_status_t check_params(const gfw_params_t *p, int32_t K)
+gfw_status_t check_params(const gfw_params_t *p, int32_t K)
 {
     if (!p) return fail(GFW_E_INVALID_ARG, "params is NULL");
     if (!(p->eps > 0.0)) return fail(GFW_E_INVALID_ARG, "eps must be > 0 (got %g)", p->eps);
@@ -222,9 +209,8 @@ static Shape shape_for(int64_t n, int64_t nnz, int32_t K)
     return s;
 }
 
-static size_t dsize(gfw_dtype_t d) { return d == GFW_F32 ? 4 : 8; }
 
-static void free_graph(gfw_graph_s *g)
+void free_graph(gfw_graph_s *g)
 {
     if (!g) return;
     dfree(g->row_ptr);
@@ -397,7 +383,7 @@ static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st)
     return GFW_OK;
 }
 
-static gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st)
+gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st)
 {
     gfw_status_t s = check_problem(p);
     if (s != GFW_OK) return s;
@@ -510,7 +496,7 @@ static gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw
     return GFW_OK;
 }
 
-static gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
+gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
 {
     Workspace &w = g->ws;
     const size_t vs = dsize(g->dtype);
@@ -546,33 +532,6 @@ static gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
 // kernel dispatch
 // --------------------------------------------------------------------------------------
 
-template <typename T>
-GraphView<T> make_view(const gfw_graph_s *g)
-{
-    GraphView<T> v;
-    const Workspace &w = g->ws;
-    v.n = g->n;
-    v.K = g->K;
-    v.diag_one = g->diag_one;
-    v.rp = g->row_ptr;
-    v.ci = g->col;
-    v.a = (const T *)g->vals;
-    v.lab = g->lab;
-    v.U = (T *)w.U;
-    v.P = (T *)w.P;
-    v.Q = (T *)w.Q;
-    v.s0 = w.s0;
-    v.s1 = w.s1;
-    v.ctl = w.ctl;
-    v.row_part = w.row_part;
-    v.lab_part = w.lab_part;
-    v.nb_row = g->shape.nb_row;
-    v.n_tiles = g->label_path == 1 ? g->n_tiles : 0;
-    v.tile_rows = g->tile_rows;
-    v.gcol = g->gcol;
-    v.gpos = g->gpos;
-    return v;
-}
 
 template <typename T, int KMAX>
 static void set_lds_limits()
@@ -580,13 +539,8 @@ static void set_lds_limits()
     // the largest dynamic LDS any launch of these kernels asks for
     (void)hipFuncSetAttribute((const void *)k_label_sorted<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kSortedMaxEntries);
-    (void)hipFuncSetAttribute((const void *)k_label_sorted_batch<T, uint8_t, KMAX>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kSortedMaxEntries);
-    const int row_lds = 3 * (int)sizeof(T) * kRowBlock * KMAX;
     (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              row_lds);
-    (void)hipFuncSetAttribute((const void *)k_row_batch<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              row_lds);
+                              3 * (int)sizeof(T) * kRowBlock * KMAX);
 }
 
 static size_t row_lds_bytes(const gfw_graph_s *g) { return 3 * dsize(g->dtype) * kRowBlock * (size_t)g->K; }
@@ -618,7 +572,7 @@ static void spmm_any(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
     }
 }
 
-static SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm)
+SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm)
 {
     SolveParams sp;
     sp.inv_eps = std::isinf(prm->eps) ? 0.0 : 1.0 / prm->eps;
@@ -686,11 +640,8 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
 {
     gfw_status_t s = ensure_workspace(g, prm->max_iter);
     if (s != GFW_OK) return s;
-    static bool lds_set = false; // per instantiation
-    if (!lds_set) {
-        set_lds_limits<T, KMAX>();
-        lds_set = true;
-    }
+    static const bool lds_set = (set_lds_limits<T, KMAX>(), true); // once per instantiation, thread-safe
+    (void)lds_set;
     Workspace &w = g->ws;
     T *U = (T *)w.U, *P = (T *)w.P;
     Ctl c0;
@@ -792,222 +743,6 @@ static gfw_status_t objective_impl(gfw_graph_s *g, const gfw_params_t *prm, cons
     GFW_HIP_TRY(hipGetLastError());
     GFW_HIP_TRY(hipMemcpyAsync(E, g->ws.row_part, sizeof(double), hipMemcpyDeviceToHost, st));
     GFW_HIP_TRY(hipStreamSynchronize(st));
-    return GFW_OK;
-}
-
-// --------------------------------------------------------------------------------------
-// batched solves
-// --------------------------------------------------------------------------------------
-
-static int bucket_of(int kmax) { return kmax == 4 ? 0 : kmax == 8 ? 1 : 2; }
-
-// Device tables of one batch: the graph views and, per K bucket, the (graph, tile) lists of
-// the row-wise kernels and of the two label passes.
-template <typename T>
-struct BatchTables {
-    std::vector<GraphView<T>> views;
-    std::vector<TileRef> rows[3], plain[3], sorted[3], all_rows;
-    GraphView<T> *d_views = nullptr;
-    TileRef *d_rows[3] = {}, *d_plain[3] = {}, *d_sorted[3] = {}, *d_all = nullptr;
-    int32_t *d_flag = nullptr;
-    int32_t *h_flag = nullptr;
-    const T **d_U0 = nullptr;
-    int32_t **d_lab_out = nullptr;
-    Ctl *d_ctl0 = nullptr, *d_ctl_out = nullptr;
-    double *d_E = nullptr;
-    ~BatchTables()
-    {
-        dfree(d_views);
-        for (int b = 0; b < 3; ++b) {
-            dfree(d_rows[b]);
-            dfree(d_plain[b]);
-            dfree(d_sorted[b]);
-        }
-        dfree(d_all);
-        dfree(d_flag);
-        dfree((void *)d_U0);
-        dfree(d_lab_out);
-        dfree(d_ctl0);
-        dfree(d_ctl_out);
-        dfree(d_E);
-        if (h_flag) (void)hipHostFree(h_flag);
-    }
-};
-
-template <typename T>
-static gfw_status_t upload(std::vector<T> &v, T **d, hipStream_t st)
-{
-    if (v.empty()) return GFW_OK;
-    if (hipMalloc((void **)d, sizeof(T) * v.size()) != hipSuccess) return fail(GFW_E_NOMEM, "batch table allocation");
-    GFW_HIP_TRY(hipMemcpyAsync(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
-    return GFW_OK;
-}
-
-template <typename T>
-static void batch_row_launch(BatchTables<T> &bt, int apply_only, hipStream_t st)
-{
-    if (!bt.rows[0].empty())
-        k_row_batch<T, uint8_t, 4><<<bt.rows[0].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 4, st>>>(
-            bt.d_views, bt.d_rows[0], apply_only);
-    if (!bt.rows[1].empty())
-        k_row_batch<T, uint8_t, 8><<<bt.rows[1].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 8, st>>>(
-            bt.d_views, bt.d_rows[1], apply_only);
-    if (!bt.rows[2].empty())
-        k_row_batch<T, uint8_t, 16><<<bt.rows[2].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 16, st>>>(
-            bt.d_views, bt.d_rows[2], apply_only);
-}
-
-template <typename T, int KB>
-static void batch_label_bucket(BatchTables<T> &bt, int b, hipStream_t st)
-{
-    if (!bt.plain[b].empty())
-        k_label_batch<T, uint8_t, KB><<<bt.plain[b].size(), kRowBlock, sizeof(T) * kRowBlock * KB, st>>>(bt.d_views,
-                                                                                                       bt.d_plain[b]);
-    if (!bt.sorted[b].empty())
-        k_label_sorted_batch<T, uint8_t, KB><<<bt.sorted[b].size(), kSortedThreads, kSortedMaxEntries, st>>>(
-            bt.d_views, bt.d_sorted[b]);
-}
-
-template <typename T>
-static void batch_iteration(BatchTables<T> &bt, hipStream_t st)
-{
-    batch_row_launch<T>(bt, 0, st);
-    batch_label_bucket<T, 4>(bt, 0, st);
-    batch_label_bucket<T, 8>(bt, 1, st);
-    batch_label_bucket<T, 16>(bt, 2, st);
-    k_finish_batch<T><<<bt.views.size(), kFinishThreads, 0, st>>>(bt.d_views);
-}
-
-template <typename T>
-static gfw_status_t solve_batched_impl(gfw_context_s *cx, int32_t count, gfw_graph_s *const *gs,
-                                       const gfw_params_t *const *prms, void *const *U_out,
-                                       int32_t *const *labels_out, gfw_stats_t *stats, hipStream_t st)
-{
-    static bool lds_set = false;
-    if (!lds_set) {
-        set_lds_limits<T, 4>();
-        set_lds_limits<T, 8>();
-        set_lds_limits<T, 16>();
-        lds_set = true;
-    }
-    BatchTables<T> bt;
-    std::vector<Ctl> ctl0((size_t)count);
-    std::vector<const T *> u0((size_t)count, nullptr);
-    std::vector<int32_t *> lab_out((size_t)count, nullptr);
-    int32_t max_iter = 0;
-    bool any_u0 = false, watch_stop = false;
-    for (int32_t i = 0; i < count; ++i) {
-        gfw_graph_s *g = gs[i];
-        const gfw_params_t *prm = prms[i];
-        gfw_status_t s = ensure_workspace(g, prm->max_iter);
-        if (s != GFW_OK) return s;
-        bt.views.push_back(make_view<T>(g));
-        const int b = bucket_of(g->shape.kmax);
-        for (int32_t t = 0; t < g->shape.nb_row; ++t) {
-            bt.rows[b].push_back({i, t});
-            bt.all_rows.push_back({i, t});
-            if (g->label_path != 1) bt.plain[b].push_back({i, t});
-        }
-        if (g->label_path == 1)
-            for (int32_t t = 0; t < g->n_tiles; ++t) bt.sorted[b].push_back({i, t});
-        Ctl &c = ctl0[(size_t)i];
-        std::memset(&c, 0, sizeof(c));
-        c.active = prm->max_iter > 0 ? 1 : 0;
-        c.max_iter = prm->max_iter;
-        c.one_shot = prm->one_shot;
-        c.last_eval = -1;
-        c.alpha_last = std::numeric_limits<double>::quiet_NaN();
-        c.gap = std::numeric_limits<double>::quiet_NaN();
-        c.sp = solve_params(g, prm);
-        c.hist = g->ws.hist;
-        c.hist_stride = prm->max_iter + 1;
-        u0[(size_t)i] = (const T *)prm->U0;
-        any_u0 = any_u0 || prm->U0;
-        lab_out[(size_t)i] = labels_out ? labels_out[i] : nullptr;
-        max_iter = std::max(max_iter, prm->max_iter);
-        watch_stop = watch_stop || prm->tol >= 0.0 || prm->one_shot;
-    }
-    gfw_status_t s;
-    if ((s = upload(bt.views, &bt.d_views, st)) != GFW_OK) return s;
-    for (int b = 0; b < 3; ++b) {
-        if ((s = upload(bt.rows[b], &bt.d_rows[b], st)) != GFW_OK) return s;
-        if ((s = upload(bt.plain[b], &bt.d_plain[b], st)) != GFW_OK) return s;
-        if ((s = upload(bt.sorted[b], &bt.d_sorted[b], st)) != GFW_OK) return s;
-    }
-    if ((s = upload(bt.all_rows, &bt.d_all, st)) != GFW_OK) return s;
-    if ((s = upload(ctl0, &bt.d_ctl0, st)) != GFW_OK) return s;
-    if (any_u0 && (s = upload(u0, (const T ***)&bt.d_U0, st)) != GFW_OK) return s;
-    if (labels_out && (s = upload(lab_out, &bt.d_lab_out, st)) != GFW_OK) return s;
-    if (hipMalloc(&bt.d_flag, sizeof(int32_t)) != hipSuccess) return fail(GFW_E_NOMEM, "batch flag allocation");
-    GFW_HIP_TRY(hipHostMalloc((void **)&bt.h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
-
-    // U_0 and P_0 = L_s U_0 for every graph
-    k_set_ctl_batch<T><<<grid_for(count, 256), 256, 0, st>>>(bt.d_views, bt.d_ctl0, count);
-    k_init_u_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_U0);
-    if (!bt.rows[0].empty()) k_spmm_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
-    if (!bt.rows[1].empty()) k_spmm_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
-    if (!bt.rows[2].empty()) k_spmm_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
-    GFW_HIP_TRY(hipGetLastError());
-
-    // iterations: every graph advances in the same launches until its own stop; the host
-    // checks, one chunk behind, whether any graph is still running
-    constexpr int chunk = 8;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    for (int i = 0; i < 2; ++i) GFW_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
-    const int reps = (int)cdiv(max_iter, chunk);
-    for (int r = 0; r < reps; ++r) {
-        for (int c = 0; c < chunk; ++c) batch_iteration<T>(bt, st);
-        if (!watch_stop) continue;
-        k_any_active<T><<<1, 256, 0, st>>>(bt.d_views, count, bt.d_flag);
-        GFW_HIP_TRY(hipMemcpyAsync(&bt.h_flag[r & 1], bt.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        GFW_HIP_TRY(hipEventRecord(ev[r & 1], st));
-        if (r >= 1) {
-            GFW_HIP_TRY(hipEventSynchronize(ev[(r - 1) & 1]));
-            if (bt.h_flag[(r - 1) & 1] == 0) break;
-        }
-    }
-    batch_row_launch<T>(bt, 1, st); // commit the last pending updates
-    GFW_HIP_TRY(hipGetLastError());
-    for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ev[i]);
-
-    // outputs
-    if (U_out)
-        for (int32_t i = 0; i < count; ++i)
-            if (U_out[i])
-                GFW_HIP_TRY(hipMemcpyAsync(U_out[i], gs[i]->ws.U, dsize(gs[i]->dtype) * gs[i]->n * gs[i]->K,
-                                           hipMemcpyDeviceToDevice, st));
-    if (labels_out) k_labels_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_lab_out);
-    if (stats) {
-        if (!bt.rows[0].empty())
-            k_spmm_to_q_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
-        if (!bt.rows[1].empty())
-            k_spmm_to_q_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
-        if (!bt.rows[2].empty())
-            k_spmm_to_q_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
-        k_energy_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all);
-        if (hipMalloc(&bt.d_E, sizeof(double) * count) != hipSuccess ||
-            hipMalloc(&bt.d_ctl_out, sizeof(Ctl) * count) != hipSuccess)
-            return fail(GFW_E_NOMEM, "batch stats allocation");
-        k_collect_batch<T><<<count, kFinishThreads, 0, st>>>(bt.d_views, bt.d_E, bt.d_ctl_out);
-        std::vector<double> E((size_t)count);
-        std::vector<Ctl> cs((size_t)count);
-        GFW_HIP_TRY(hipMemcpyAsync(E.data(), bt.d_E, sizeof(double) * count, hipMemcpyDeviceToHost, st));
-        GFW_HIP_TRY(hipMemcpyAsync(cs.data(), bt.d_ctl_out, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st));
-        GFW_HIP_TRY(hipStreamSynchronize(st));
-        bool nan = false;
-        for (int32_t i = 0; i < count; ++i) {
-            stats[i].iters = cs[(size_t)i].iters;
-            stats[i].stop_reason = cs[(size_t)i].stop_reason;
-            stats[i].gap = cs[(size_t)i].gap;
-            stats[i].alpha_last = cs[(size_t)i].alpha_last;
-            stats[i].objective = E[(size_t)i];
-            nan = nan || cs[(size_t)i].stop_reason == GFW_STOP_NUMERIC;
-        }
-        if (nan) return fail(GFW_E_NUMERIC, "NaN met in at least one graph of the batch");
-    } else {
-        GFW_HIP_TRY(hipStreamSynchronize(st)); // the batch tables are freed on return
-    }
-    GFW_HIP_TRY(hipGetLastError());
     return GFW_OK;
 }
 
@@ -1168,37 +903,6 @@ gfw_status_t gfw_solve(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm
         if (stats->stop_reason == GFW_STOP_NUMERIC) return fail(GFW_E_NUMERIC, "NaN met during the iteration");
     }
     return GFW_OK;
-}
-
-gfw_status_t gfw_solve_batched(gfw_context_t ctx, int32_t count, const gfw_graph_t *graphs, const gfw_params_t *prm,
-                               int32_t shared_params, void *const *U_out, int32_t *const *labels_out,
-                               gfw_stats_t *stats, void *stream)
-{
-    if (!ctx || !graphs || !prm) return fail(GFW_E_INVALID_ARG, "NULL argument");
-    if (count < 0) return fail(GFW_E_INVALID_ARG, "count must be >= 0");
-    if (count == 0) return GFW_OK;
-    std::vector<gfw_graph_s *> gs((size_t)count);
-    std::vector<const gfw_params_t *> ps((size_t)count);
-    for (int32_t i = 0; i < count; ++i) {
-        gs[(size_t)i] = graphs[i];
-        if (!graphs[i]) return fail(GFW_E_INVALID_ARG, "graph %d is NULL", i);
-        if (graphs[i]->ctx != ctx) return fail(GFW_E_INVALID_ARG, "graph %d belongs to another context", i);
-        if (graphs[i]->dtype != graphs[0]->dtype) return fail(GFW_E_UNSUPPORTED, "a batch must share one dtype");
-        if (graphs[i]->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by the batched solver");
-        ps[(size_t)i] = shared_params ? prm : prm + i;
-        gfw_status_t s = check_params(ps[(size_t)i], graphs[i]->K);
-        if (s != GFW_OK) return s;
-        if (ps[(size_t)i]->p_refresh != 0) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported in batches");
-    }
-    std::vector<gfw_graph_s *> sorted_gs = gs;
-    std::sort(sorted_gs.begin(), sorted_gs.end());
-    if (std::adjacent_find(sorted_gs.begin(), sorted_gs.end()) != sorted_gs.end())
-        return fail(GFW_E_INVALID_ARG, "a graph appears twice in the batch");
-    GFW_HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)stream;
-    return graphs[0]->dtype == GFW_F32
-               ? solve_batched_impl<float>(ctx, count, gs.data(), ps.data(), U_out, labels_out, stats, st)
-               : solve_batched_impl<double>(ctx, count, gs.data(), ps.data(), U_out, labels_out, stats, st);
 }
 
 gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm, const void *U, double *E_host,

@@ -1,0 +1,667 @@
+// Batched solves and the request server of libgfw: many graphs advance in the same
+// launches.  Every kernel here runs the same device functions as the single-graph path on
+// the same tiles of each graph, so a graph's results do not depend on its companions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include <new>
+#include <string>
+
+#include "gfw_internal.h"
+
+namespace gfw {
+
+template <typename T, int KMAX>
+static void set_batch_lds_limits()
+{
+    (void)hipFuncSetAttribute((const void *)k_label_sorted_batch<T, uint8_t, KMAX>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kSortedMaxEntries);
+    (void)hipFuncSetAttribute((const void *)k_row_batch<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              3 * (int)sizeof(T) * kRowBlock * KMAX);
+}
+
+// --------------------------------------------------------------------------------------
+// batched solves
+// --------------------------------------------------------------------------------------
+
+static int bucket_of(int kmax) { return kmax == 4 ? 0 : kmax == 8 ? 1 : 2; }
+
+// Device tables of one batch: the graph views and, per K bucket, the (graph, tile) lists of
+// the row-wise kernels and of the two label passes.
+template <typename T>
+struct BatchTables {
+    std::vector<GraphView<T>> views;
+    std::vector<TileRef> rows[3], plain[3], sorted[3], all_rows;
+    GraphView<T> *d_views = nullptr;
+    TileRef *d_rows[3] = {}, *d_plain[3] = {}, *d_sorted[3] = {}, *d_all = nullptr;
+    int32_t *d_flag = nullptr;
+    int32_t *h_flag = nullptr;
+    const T **d_U0 = nullptr;
+    int32_t **d_lab_out = nullptr;
+    Ctl *d_ctl0 = nullptr, *d_ctl_out = nullptr;
+    double *d_E = nullptr;
+    ~BatchTables()
+    {
+        dfree(d_views);
+        for (int b = 0; b < 3; ++b) {
+            dfree(d_rows[b]);
+            dfree(d_plain[b]);
+            dfree(d_sorted[b]);
+        }
+        dfree(d_all);
+        dfree(d_flag);
+        dfree((void *)d_U0);
+        dfree(d_lab_out);
+        dfree(d_ctl0);
+        dfree(d_ctl_out);
+        dfree(d_E);
+        if (h_flag) (void)hipHostFree(h_flag);
+    }
+};
+
+template <typename T>
+static gfw_status_t upload(std::vector<T> &v, T **d, hipStream_t st)
+{
+    if (v.empty()) return GFW_OK;
+    if (hipMalloc((void **)d, sizeof(T) * v.size()) != hipSuccess) return fail(GFW_E_NOMEM, "batch table allocation");
+    GFW_HIP_TRY(hipMemcpyAsync(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    return GFW_OK;
+}
+
+template <typename T>
+static void batch_row_launch(BatchTables<T> &bt, int apply_only, hipStream_t st)
+{
+    if (!bt.rows[0].empty())
+        k_row_batch<T, uint8_t, 4><<<bt.rows[0].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 4, st>>>(
+            bt.d_views, bt.d_rows[0], apply_only);
+    if (!bt.rows[1].empty())
+        k_row_batch<T, uint8_t, 8><<<bt.rows[1].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 8, st>>>(
+            bt.d_views, bt.d_rows[1], apply_only);
+    if (!bt.rows[2].empty())
+        k_row_batch<T, uint8_t, 16><<<bt.rows[2].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 16, st>>>(
+            bt.d_views, bt.d_rows[2], apply_only);
+}
+
+template <typename T, int KB>
+static void batch_label_bucket(BatchTables<T> &bt, int b, hipStream_t st)
+{
+    if (!bt.plain[b].empty())
+        k_label_batch<T, uint8_t, KB><<<bt.plain[b].size(), kRowBlock, sizeof(T) * kRowBlock * KB, st>>>(bt.d_views,
+                                                                                                       bt.d_plain[b]);
+    if (!bt.sorted[b].empty())
+        k_label_sorted_batch<T, uint8_t, KB><<<bt.sorted[b].size(), kSortedThreads, kSortedMaxEntries, st>>>(
+            bt.d_views, bt.d_sorted[b]);
+}
+
+template <typename T>
+static void batch_iteration(BatchTables<T> &bt, hipStream_t st)
+{
+    batch_row_launch<T>(bt, 0, st);
+    batch_label_bucket<T, 4>(bt, 0, st);
+    batch_label_bucket<T, 8>(bt, 1, st);
+    batch_label_bucket<T, 16>(bt, 2, st);
+    k_finish_batch<T><<<bt.views.size(), kFinishThreads, 0, st>>>(bt.d_views);
+}
+
+// Builds the device tables of a batch (graphs gs with settings prms; every graph's
+// workspace must exist) and uploads the initial control blocks.
+template <typename T>
+static gfw_status_t batch_prepare(BatchTables<T> &bt, int32_t count, gfw_graph_s *const *gs,
+                                  const gfw_params_t *const *prms, int32_t *const *labels_out, hipStream_t st,
+                                  bool init_state, int32_t *max_iter_out, bool *watch_stop_out)
+{
+    static const bool lds_set = (set_batch_lds_limits<T, 4>(), set_batch_lds_limits<T, 8>(),
+                                 set_batch_lds_limits<T, 16>(), true); // once, thread-safe
+    (void)lds_set;
+    std::vector<Ctl> ctl0((size_t)count);
+    std::vector<const T *> u0((size_t)count, nullptr);
+    std::vector<int32_t *> lab_out((size_t)count, nullptr);
+    int32_t max_iter = 0;
+    bool any_u0 = false, watch_stop = false;
+    for (int32_t i = 0; i < count; ++i) {
+        gfw_graph_s *g = gs[i];
+        const gfw_params_t *prm = prms[i];
+        bt.views.push_back(make_view<T>(g));
+        const int b = bucket_of(g->shape.kmax);
+        for (int32_t t = 0; t < g->shape.nb_row; ++t) {
+            bt.rows[b].push_back({i, t});
+            bt.all_rows.push_back({i, t});
+            if (g->label_path != 1) bt.plain[b].push_back({i, t});
+        }
+        if (g->label_path == 1)
+            for (int32_t t = 0; t < g->n_tiles; ++t) bt.sorted[b].push_back({i, t});
+        if (init_state) {
+            Ctl &c = ctl0[(size_t)i];
+            std::memset(&c, 0, sizeof(c));
+            c.active = prm->max_iter > 0 ? 1 : 0;
+            c.max_iter = prm->max_iter;
+            c.one_shot = prm->one_shot;
+            c.last_eval = -1;
+            c.alpha_last = std::numeric_limits<double>::quiet_NaN();
+            c.gap = std::numeric_limits<double>::quiet_NaN();
+            c.sp = solve_params(g, prm);
+            c.hist = g->ws.hist;
+            c.hist_stride = prm->max_iter + 1;
+            u0[(size_t)i] = (const T *)prm->U0;
+            any_u0 = any_u0 || prm->U0;
+            max_iter = std::max(max_iter, prm->max_iter);
+            watch_stop = watch_stop || prm->tol >= 0.0 || prm->one_shot;
+        }
+        lab_out[(size_t)i] = labels_out ? labels_out[i] : nullptr;
+    }
+    gfw_status_t s;
+    if ((s = upload(bt.views, &bt.d_views, st)) != GFW_OK) return s;
+    for (int b = 0; b < 3; ++b) {
+        if ((s = upload(bt.rows[b], &bt.d_rows[b], st)) != GFW_OK) return s;
+        if ((s = upload(bt.plain[b], &bt.d_plain[b], st)) != GFW_OK) return s;
+        if ((s = upload(bt.sorted[b], &bt.d_sorted[b], st)) != GFW_OK) return s;
+    }
+    if ((s = upload(bt.all_rows, &bt.d_all, st)) != GFW_OK) return s;
+    if (labels_out && (s = upload(lab_out, &bt.d_lab_out, st)) != GFW_OK) return s;
+    if (hipMalloc(&bt.d_flag, sizeof(int32_t)) != hipSuccess) return fail(GFW_E_NOMEM, "batch flag allocation");
+    GFW_HIP_TRY(hipHostMalloc((void **)&bt.h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+    if (init_state) {
+        if ((s = upload(ctl0, &bt.d_ctl0, st)) != GFW_OK) return s;
+        if (any_u0 && (s = upload(u0, (const T ***)&bt.d_U0, st)) != GFW_OK) return s;
+        // U_0 and P_0 = L_s U_0 for every graph
+        k_set_ctl_batch<T><<<grid_for(count, 256), 256, 0, st>>>(bt.d_views, bt.d_ctl0, count);
+        k_init_u_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_U0);
+        if (!bt.rows[0].empty()) k_spmm_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
+        if (!bt.rows[1].empty()) k_spmm_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
+        if (!bt.rows[2].empty())
+            k_spmm_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
+        GFW_HIP_TRY(hipGetLastError());
+    }
+    if (max_iter_out) *max_iter_out = max_iter;
+    if (watch_stop_out) *watch_stop_out = watch_stop;
+    return GFW_OK;
+}
+
+// Runs up to `iters` iterations of every graph of the batch; with `watch`, returns early
+// (one chunk behind) once no graph has work left.  *any_left reports whether some graph
+// may still have work.
+template <typename T>
+static gfw_status_t batch_run(BatchTables<T> &bt, int32_t iters, bool watch, hipStream_t st, bool *any_left)
+{
+    constexpr int chunk = 8;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; ++i) GFW_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    const int count = (int)bt.views.size();
+    const int reps = (int)cdiv(iters, chunk);
+    bool left = true;
+    for (int r = 0; r < reps; ++r) {
+        const int n_it = std::min(chunk, iters - r * chunk);
+        for (int c = 0; c < n_it; ++c) batch_iteration<T>(bt, st);
+        if (!watch) continue;
+        k_any_active<T><<<1, 256, 0, st>>>(bt.d_views, count, bt.d_flag);
+        GFW_HIP_TRY(hipMemcpyAsync(&bt.h_flag[r & 1], bt.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipEventRecord(ev[r & 1], st));
+        if (r >= 1) {
+            GFW_HIP_TRY(hipEventSynchronize(ev[(r - 1) & 1]));
+            if (bt.h_flag[(r - 1) & 1] == 0) {
+                left = false;
+                break;
+            }
+        }
+    }
+    GFW_HIP_TRY(hipGetLastError());
+    for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ev[i]);
+    if (any_left) *any_left = left;
+    return GFW_OK;
+}
+
+// Commits every pending update (apply-only row pass) and clears the pending flags, so that
+// U and P of every graph are current and a later iteration starts from a clean state.
+template <typename T>
+static void batch_commit(BatchTables<T> &bt, hipStream_t st)
+{
+    batch_row_launch<T>(bt, 1, st);
+    k_clear_pending_batch<T><<<grid_for((int64_t)bt.views.size(), 256), 256, 0, st>>>(bt.d_views,
+                                                                                       (int)bt.views.size());
+}
+
+// Labels (if asked), objective and control blocks of every graph; synchronises `st`.
+template <typename T>
+static gfw_status_t batch_collect(BatchTables<T> &bt, bool labels, std::vector<double> &E, std::vector<Ctl> &cs,
+                                  hipStream_t st)
+{
+    const int count = (int)bt.views.size();
+    if (labels) k_labels_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_lab_out);
+    if (!bt.rows[0].empty()) k_spmm_to_q_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
+    if (!bt.rows[1].empty()) k_spmm_to_q_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
+    if (!bt.rows[2].empty())
+        k_spmm_to_q_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
+    k_energy_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all);
+    if (!bt.d_E && hipMalloc(&bt.d_E, sizeof(double) * count) != hipSuccess)
+        return fail(GFW_E_NOMEM, "batch stats allocation");
+    if (!bt.d_ctl_out && hipMalloc(&bt.d_ctl_out, sizeof(Ctl) * count) != hipSuccess)
+        return fail(GFW_E_NOMEM, "batch stats allocation");
+    k_collect_batch<T><<<count, kFinishThreads, 0, st>>>(bt.d_views, bt.d_E, bt.d_ctl_out);
+    E.resize((size_t)count);
+    cs.resize((size_t)count);
+    GFW_HIP_TRY(hipMemcpyAsync(E.data(), bt.d_E, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+    GFW_HIP_TRY(hipMemcpyAsync(cs.data(), bt.d_ctl_out, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st));
+    GFW_HIP_TRY(hipStreamSynchronize(st));
+    GFW_HIP_TRY(hipGetLastError());
+    return GFW_OK;
+}
+
+template <typename T>
+static gfw_status_t solve_batched_impl(gfw_context_s *cx, int32_t count, gfw_graph_s *const *gs,
+                                       const gfw_params_t *const *prms, void *const *U_out,
+                                       int32_t *const *labels_out, gfw_stats_t *stats, hipStream_t st)
+{
+    (void)cx;
+    for (int32_t i = 0; i < count; ++i) {
+        gfw_status_t s = ensure_workspace(gs[i], prms[i]->max_iter);
+        if (s != GFW_OK) return s;
+    }
+    BatchTables<T> bt;
+    int32_t max_iter = 0;
+    bool watch = false;
+    gfw_status_t s = batch_prepare<T>(bt, count, gs, prms, labels_out, st, true, &max_iter, &watch);
+    if (s != GFW_OK) return s;
+    // every graph advances in the same launches until its own stop
+    if ((s = batch_run<T>(bt, max_iter, watch, st, nullptr)) != GFW_OK) return s;
+    batch_row_launch<T>(bt, 1, st); // commit the last pending updates
+    if (U_out)
+        for (int32_t i = 0; i < count; ++i)
+            if (U_out[i])
+                GFW_HIP_TRY(hipMemcpyAsync(U_out[i], gs[i]->ws.U, dsize(gs[i]->dtype) * gs[i]->n * gs[i]->K,
+                                           hipMemcpyDeviceToDevice, st));
+    if (stats) {
+        std::vector<double> E;
+        std::vector<Ctl> cs;
+        if ((s = batch_collect<T>(bt, labels_out != nullptr, E, cs, st)) != GFW_OK) return s;
+        bool nan = false;
+        for (int32_t i = 0; i < count; ++i) {
+            stats[i].iters = cs[(size_t)i].iters;
+            stats[i].stop_reason = cs[(size_t)i].stop_reason;
+            stats[i].gap = cs[(size_t)i].gap;
+            stats[i].alpha_last = cs[(size_t)i].alpha_last;
+            stats[i].objective = E[(size_t)i];
+            nan = nan || cs[(size_t)i].stop_reason == GFW_STOP_NUMERIC;
+        }
+        if (nan) return fail(GFW_E_NUMERIC, "NaN met in at least one graph of the batch");
+    } else {
+        if (labels_out)
+            k_labels_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_lab_out);
+        GFW_HIP_TRY(hipStreamSynchronize(st)); // the batch tables are freed on return
+    }
+    GFW_HIP_TRY(hipGetLastError());
+    return GFW_OK;
+}
+
+// --------------------------------------------------------------------------------------
+// request server (continuous batching)
+// --------------------------------------------------------------------------------------
+
+// Device bytes a problem will hold while resident (graph + one solve), an upper bound of
+// gfw_graph_footprint for the same problem.
+static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter)
+{
+    const size_t v = dsize(p->dtype);
+    const size_t n = (size_t)p->n, nnz = (size_t)p->nnz, K = (size_t)p->K;
+    const size_t nb = (size_t)cdiv(p->n, kRowBlock);
+    size_t graph = 4 * (n + 1) + (4 + v) * nnz + 4 * n;
+    if (p->nnz >= ((int64_t)4 << 20)) graph += 6 * nnz + 4 * (nnz / 4096 + 2); // column-sorted copy
+    const size_t solve = 3 * v * n * K + 2 * n + 8 * ((size_t)(kRowParts + 4) * nb + 64) + sizeof(Ctl) +
+                         8 * 5 * ((size_t)max_iter + 1) + 4096;
+    return graph + solve;
+}
+
+struct ServerRequest {
+    uint64_t ticket = 0;
+    gfw_problem_t prob{};
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci, li, lb;
+    std::vector<unsigned char> vals;
+    gfw_params_t prm{};
+    size_t footprint = 0;
+    int state = 0;         // 0 queued or resident, 2 done (read and written under the server mutex)
+    bool finished = false; // set by the worker thread only; published as state 2 under the mutex
+    gfw_status_t status = GFW_OK;
+    std::string error;
+    gfw_graph_s *g = nullptr;
+    std::vector<unsigned char> U;
+    std::vector<int32_t> labels;
+    gfw_stats_t stats{};
+};
+
+} // namespace gfw
+
+struct gfw_server_s {
+    gfw_context_s *ctx = nullptr;
+    size_t budget = 0, used = 0;
+    int32_t max_slots = 0;
+    hipStream_t st = nullptr;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::deque<gfw::ServerRequest *> queue;
+    std::vector<gfw::ServerRequest *> resident;
+    std::map<uint64_t, gfw::ServerRequest *> all;
+};
+
+namespace gfw {
+
+static constexpr int kMacroIters = 16; // iterations between admissions / retirements
+
+template <typename T>
+static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &fresh,
+                                std::vector<ServerRequest *> &run)
+{
+    hipStream_t st = sv->st;
+    gfw_status_t s;
+    if (!fresh.empty()) { // U_0, P_0 and control blocks of the newly admitted requests
+        std::vector<gfw_graph_s *> gs;
+        std::vector<const gfw_params_t *> ps;
+        for (auto *r : fresh) {
+            gs.push_back(r->g);
+            ps.push_back(&r->prm);
+        }
+        BatchTables<T> bt;
+        if ((s = batch_prepare<T>(bt, (int32_t)gs.size(), gs.data(), ps.data(), nullptr, st, true, nullptr, nullptr)) !=
+            GFW_OK)
+            return s;
+        GFW_HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (run.empty()) return GFW_OK;
+    std::vector<gfw_graph_s *> gs;
+    std::vector<const gfw_params_t *> ps;
+    std::vector<int32_t *> lab_out;
+    for (auto *r : run) {
+        gs.push_back(r->g);
+        ps.push_back(&r->prm);
+    }
+    BatchTables<T> bt;
+    if ((s = batch_prepare<T>(bt, (int32_t)gs.size(), gs.data(), ps.data(), nullptr, st, false, nullptr, nullptr)) !=
+        GFW_OK)
+        return s;
+    if ((s = batch_run<T>(bt, kMacroIters, false, st, nullptr)) != GFW_OK) return s;
+    batch_commit<T>(bt, st);
+    // which requests are finished
+    const int count = (int)gs.size();
+    Ctl *d_c = nullptr;
+    if (hipMalloc(&d_c, sizeof(Ctl) * count) != hipSuccess) return fail(GFW_E_NOMEM, "server state allocation");
+    k_ctl_gather_batch<T><<<grid_for(count, 256), 256, 0, st>>>(bt.d_views, d_c, count);
+    std::vector<Ctl> cs((size_t)count);
+    GFW_HIP_TRY(hipMemcpyAsync(cs.data(), d_c, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st));
+    GFW_HIP_TRY(hipStreamSynchronize(st));
+    dfree(d_c);
+    std::vector<ServerRequest *> done;
+    for (int i = 0; i < count; ++i)
+        if (!cs[(size_t)i].active && !cs[(size_t)i].pending) done.push_back(run[(size_t)i]);
+    if (done.empty()) return GFW_OK;
+    // results of the finished requests: U, labels, objective, stats
+    std::vector<gfw_graph_s *> dg;
+    std::vector<const gfw_params_t *> dp;
+    std::vector<int32_t *> dl;
+    std::vector<int32_t *> dev_labels;
+    for (auto *r : done) {
+        dg.push_back(r->g);
+        dp.push_back(&r->prm);
+        int32_t *lab = nullptr;
+        if (hipMalloc(&lab, sizeof(int32_t) * r->g->n) != hipSuccess) return fail(GFW_E_NOMEM, "label buffer");
+        dev_labels.push_back(lab);
+        dl.push_back(lab);
+    }
+    BatchTables<T> bd;
+    if ((s = batch_prepare<T>(bd, (int32_t)dg.size(), dg.data(), dp.data(), dl.data(), st, false, nullptr, nullptr)) !=
+        GFW_OK)
+        return s;
+    std::vector<double> E;
+    std::vector<Ctl> dc;
+    if ((s = batch_collect<T>(bd, true, E, dc, st)) != GFW_OK) return s;
+    for (size_t i = 0; i < done.size(); ++i) {
+        ServerRequest *r = done[i];
+        gfw_graph_s *g = r->g;
+        r->U.resize(dsize(g->dtype) * (size_t)g->n * g->K);
+        r->labels.resize((size_t)g->n);
+        GFW_HIP_TRY(hipMemcpyAsync(r->U.data(), g->ws.U, r->U.size(), hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipMemcpyAsync(r->labels.data(), dev_labels[i], 4 * (size_t)g->n, hipMemcpyDeviceToHost, st));
+        r->stats.iters = dc[i].iters;
+        r->stats.stop_reason = dc[i].stop_reason;
+        r->stats.gap = dc[i].gap;
+        r->stats.alpha_last = dc[i].alpha_last;
+        r->stats.objective = E[i];
+        r->status = dc[i].stop_reason == GFW_STOP_NUMERIC ? GFW_E_NUMERIC : GFW_OK;
+        if (r->status != GFW_OK) r->error = "NaN met during the iteration";
+    }
+    GFW_HIP_TRY(hipStreamSynchronize(st));
+    for (int32_t *lab : dev_labels) dfree(lab);
+    for (auto *r : done) r->finished = true;
+    return GFW_OK;
+}
+
+static void server_loop(gfw_server_s *sv)
+{
+    (void)hipSetDevice(sv->ctx->device);
+    for (;;) {
+        std::vector<ServerRequest *> admit;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty() || !sv->resident.empty(); });
+            if (sv->stop) return;
+            while (!sv->queue.empty() && (int32_t)(sv->resident.size() + admit.size()) < sv->max_slots &&
+                   sv->used + sv->queue.front()->footprint <= sv->budget) {
+                ServerRequest *r = sv->queue.front();
+                sv->queue.pop_front();
+                sv->used += r->footprint;
+                admit.push_back(r);
+            }
+        }
+        std::vector<ServerRequest *> fresh, failed;
+        for (ServerRequest *r : admit) {
+            gfw_graph_s *g = nullptr;
+            gfw_status_t s = graph_create(sv->ctx, &r->prob, &g, sv->st);
+            if (s == GFW_OK) s = ensure_workspace(g, r->prm.max_iter);
+            if (s != GFW_OK) {
+                r->status = s;
+                r->error = gfw_last_error();
+                if (g) free_graph(g);
+                failed.push_back(r);
+                continue;
+            }
+            r->g = g;
+            r->rp.clear();
+            r->ci.clear();
+            r->vals.clear(); // the device copy is the reference from here on
+            fresh.push_back(r);
+        }
+        std::vector<ServerRequest *> run32, run64, fr32, fr64;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            for (ServerRequest *r : fresh) sv->resident.push_back(r);
+            for (ServerRequest *r : sv->resident) (r->g->dtype == GFW_F32 ? run32 : run64).push_back(r);
+        }
+        for (ServerRequest *r : fresh) (r->g->dtype == GFW_F32 ? fr32 : fr64).push_back(r);
+        gfw_status_t s = GFW_OK;
+        if (!run32.empty() || !fr32.empty()) s = server_step<float>(sv, fr32, run32);
+        if (s == GFW_OK && (!run64.empty() || !fr64.empty())) s = server_step<double>(sv, fr64, run64);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (s != GFW_OK) { // a device failure ends every resident request
+            for (ServerRequest *r : sv->resident) {
+                r->status = s;
+                r->error = gfw_last_error();
+                r->finished = true;
+            }
+        }
+        for (ServerRequest *r : failed) {
+            r->state = 2;
+            sv->used -= r->footprint;
+        }
+        std::vector<ServerRequest *> keep;
+        for (ServerRequest *r : sv->resident) {
+            if (r->finished) {
+                free_graph(r->g);
+                r->g = nullptr;
+                sv->used -= r->footprint;
+                r->state = 2;
+            } else {
+                keep.push_back(r);
+            }
+        }
+        sv->resident.swap(keep);
+        sv->cv_done.notify_all();
+    }
+}
+
+} // namespace gfw
+
+
+using namespace gfw;
+
+extern "C" {
+
+gfw_status_t gfw_solve_batched(gfw_context_t ctx, int32_t count, const gfw_graph_t *graphs, const gfw_params_t *prm,
+                               int32_t shared_params, void *const *U_out, int32_t *const *labels_out,
+                               gfw_stats_t *stats, void *stream)
+{
+    if (!ctx || !graphs || !prm) return fail(GFW_E_INVALID_ARG, "NULL argument");
+    if (count < 0) return fail(GFW_E_INVALID_ARG, "count must be >= 0");
+    if (count == 0) return GFW_OK;
+    std::vector<gfw_graph_s *> gs((size_t)count);
+    std::vector<const gfw_params_t *> ps((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        gs[(size_t)i] = graphs[i];
+        if (!graphs[i]) return fail(GFW_E_INVALID_ARG, "graph %d is NULL", i);
+        if (graphs[i]->ctx != ctx) return fail(GFW_E_INVALID_ARG, "graph %d belongs to another context", i);
+        if (graphs[i]->dtype != graphs[0]->dtype) return fail(GFW_E_UNSUPPORTED, "a batch must share one dtype");
+        if (graphs[i]->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by the batched solver");
+        ps[(size_t)i] = shared_params ? prm : prm + i;
+        gfw_status_t s = check_params(ps[(size_t)i], graphs[i]->K);
+        if (s != GFW_OK) return s;
+        if (ps[(size_t)i]->p_refresh != 0) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported in batches");
+    }
+    std::vector<gfw_graph_s *> sorted_gs = gs;
+    std::sort(sorted_gs.begin(), sorted_gs.end());
+    if (std::adjacent_find(sorted_gs.begin(), sorted_gs.end()) != sorted_gs.end())
+        return fail(GFW_E_INVALID_ARG, "a graph appears twice in the batch");
+    GFW_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    return graphs[0]->dtype == GFW_F32
+               ? solve_batched_impl<float>(ctx, count, gs.data(), ps.data(), U_out, labels_out, stats, st)
+               : solve_batched_impl<double>(ctx, count, gs.data(), ps.data(), U_out, labels_out, stats, st);
+}
+
+
+gfw_status_t gfw_server_create(gfw_context_t ctx, size_t hbm_budget_bytes, int32_t max_slots, gfw_server_t *out)
+{
+    if (!ctx || !out) return fail(GFW_E_INVALID_ARG, "ctx or out is NULL");
+    if (max_slots < 1) return fail(GFW_E_INVALID_ARG, "max_slots must be >= 1");
+    if (hbm_budget_bytes == 0) return fail(GFW_E_INVALID_ARG, "the HBM budget must be > 0");
+    *out = nullptr;
+    GFW_HIP_TRY(hipSetDevice(ctx->device));
+    gfw_server_s *sv = new (std::nothrow) gfw_server_s();
+    if (!sv) return fail(GFW_E_NOMEM, "host allocation failed");
+    sv->ctx = ctx;
+    sv->budget = hbm_budget_bytes;
+    sv->max_slots = max_slots;
+    if (hipStreamCreateWithFlags(&sv->st, hipStreamNonBlocking) != hipSuccess) {
+        delete sv;
+        return fail(GFW_E_HIP, "stream creation failed");
+    }
+    sv->worker = std::thread(server_loop, sv);
+    *out = sv;
+    return GFW_OK;
+}
+
+gfw_status_t gfw_server_submit(gfw_server_t sv, const gfw_problem_t *p, const gfw_params_t *prm, uint64_t *ticket)
+{
+    if (!sv || !p || !prm || !ticket) return fail(GFW_E_INVALID_ARG, "NULL argument");
+    if (p->location != GFW_HOST) return fail(GFW_E_INVALID_ARG, "server requests must be host-resident");
+    gfw_status_t s = check_problem(p);
+    if (s != GFW_OK) return s;
+    if ((s = check_params(prm, p->K)) != GFW_OK) return s;
+    if (prm->U0) return fail(GFW_E_UNSUPPORTED, "server requests start from Uhat (U0 must be NULL)");
+    if (prm->p_refresh) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported by the server");
+    if (p->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by the server");
+    const size_t fp = request_footprint(p, prm->max_iter);
+    if (fp > sv->budget) return fail(GFW_E_BUDGET, "request needs %zu bytes, budget is %zu", fp, sv->budget);
+    auto *r = new (std::nothrow) ServerRequest();
+    if (!r) return fail(GFW_E_NOMEM, "host allocation failed");
+    const size_t v = dsize(p->dtype);
+    r->rp.assign(p->row_ptr, p->row_ptr + p->n + 1);
+    r->ci.assign(p->col_idx, p->col_idx + p->nnz);
+    if (p->vals) r->vals.assign((const unsigned char *)p->vals, (const unsigned char *)p->vals + v * p->nnz);
+    r->li.assign(p->labelled_idx, p->labelled_idx + p->n_labelled);
+    r->lb.assign(p->labels, p->labels + p->n_labelled);
+    r->prob = *p;
+    r->prob.row_ptr = r->rp.data();
+    r->prob.col_idx = r->ci.data();
+    r->prob.vals = p->vals ? r->vals.data() : nullptr;
+    r->prob.labelled_idx = r->li.data();
+    r->prob.labels = r->lb.data();
+    r->prm = *prm;
+    r->footprint = fp;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        r->ticket = sv->next_ticket++;
+        sv->all[r->ticket] = r;
+        sv->queue.push_back(r);
+    }
+    sv->cv_work.notify_all();
+    *ticket = r->ticket;
+    return GFW_OK;
+}
+
+gfw_status_t gfw_server_poll(gfw_server_t sv, uint64_t ticket, int blocking, void *U_out, int32_t *labels_out,
+                             gfw_stats_t *stats)
+{
+    if (!sv) return fail(GFW_E_INVALID_ARG, "server is NULL");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->all.find(ticket);
+    if (it == sv->all.end()) return fail(GFW_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    ServerRequest *r = it->second;
+    if (r->state != 2) {
+        if (!blocking) return GFW_E_NOT_READY;
+        sv->cv_done.wait(lk, [&] { return r->state == 2; });
+    }
+    sv->all.erase(it);
+    lk.unlock();
+    gfw_status_t s = r->status;
+    if (s == GFW_OK) {
+        if (U_out) std::memcpy(U_out, r->U.data(), r->U.size());
+        if (labels_out) std::memcpy(labels_out, r->labels.data(), 4 * r->labels.size());
+        if (stats) *stats = r->stats;
+    } else {
+        fail(s, "%s", r->error.c_str());
+    }
+    delete r;
+    return s;
+}
+
+gfw_status_t gfw_server_destroy(gfw_server_t sv)
+{
+    if (!sv) return GFW_OK;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    (void)hipStreamSynchronize(sv->st);
+    for (auto &kv : sv->all) {
+        if (kv.second->g) free_graph(kv.second->g);
+        delete kv.second;
+    }
+    (void)hipStreamDestroy(sv->st);
+    delete sv;
+    return GFW_OK;
+}
+
+} // extern "C"

@@ -13,6 +13,22 @@
 namespace gfw {
 
 void set_error(const char *fmt, ...);
+gfw_status_t fail(gfw_status_t s, const char *fmt, ...);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+inline int grid_for(int64_t work, int threads, int cap = 65535)
+{
+    int64_t b = cdiv(work > 1 ? work : 1, threads);
+    return (int)(b < cap ? b : cap);
+}
+
+inline size_t dsize(gfw_dtype_t d) { return d == GFW_F32 ? 4 : 8; }
 
 #define GFW_HIP_TRY(expr)                                                                   \
     do {                                                                                    \
@@ -100,3 +116,41 @@ struct gfw_graph_s {
     gfw::Workspace ws;
     size_t graph_bytes = 0, solve_bytes = 0;
 };
+
+namespace gfw {
+gfw_status_t check_problem(const gfw_problem_t *p);
+gfw_status_t check_params(const gfw_params_t *p, int32_t K);
+gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st);
+void free_graph(gfw_graph_s *g);
+gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter);
+SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm);
+
+// view of a graph and its solve workspace for the per-iteration kernels
+template <typename T>
+GraphView<T> make_view(const gfw_graph_s *g)
+{
+    GraphView<T> v;
+    const Workspace &w = g->ws;
+    v.n = g->n;
+    v.K = g->K;
+    v.diag_one = g->diag_one;
+    v.rp = g->row_ptr;
+    v.ci = g->col;
+    v.a = (const T *)g->vals;
+    v.lab = g->lab;
+    v.U = (T *)w.U;
+    v.P = (T *)w.P;
+    v.Q = (T *)w.Q;
+    v.s0 = w.s0;
+    v.s1 = w.s1;
+    v.ctl = w.ctl;
+    v.row_part = w.row_part;
+    v.lab_part = w.lab_part;
+    v.nb_row = g->shape.nb_row;
+    v.n_tiles = g->label_path == 1 ? g->n_tiles : 0;
+    v.tile_rows = g->tile_rows;
+    v.gcol = g->gcol;
+    v.gpos = g->gpos;
+    return v;
+}
+} // namespace gfw

@@ -98,7 +98,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[N], double *out)
 
 // d_i = sum_j w_ij in FP64, dinv_i = d_i^{-1/2} (0 for an isolated node)
 template <typename T>
-__global__ void k_degrees(int64_t n, const int32_t *__restrict__ rp, const T *__restrict__ w,
+static __global__ void k_degrees(int64_t n, const int32_t *__restrict__ rp, const T *__restrict__ w,
                           double *__restrict__ dinv)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -115,7 +115,7 @@ __global__ void k_degrees(int64_t n, const int32_t *__restrict__ rp, const T *__
 // a_p = -d_i^{-1/2} w_ij d_j^{-1/2} (off-diagonal part of L_s = I - D^{-1/2} W D^{-1/2});
 // rho_i = Gershgorin radius |1 + a_ii| + sum_{j != i} |a_ij| of row i.
 template <typename T>
-__global__ void k_scale_values(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+static __global__ void k_scale_values(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                const T *__restrict__ w, const double *__restrict__ dinv, T *__restrict__ a,
                                double *__restrict__ rho)
 {
@@ -135,7 +135,7 @@ __global__ void k_scale_values(int64_t n, const int32_t *__restrict__ rp, const 
 
 // Gershgorin radius of a user-supplied operator L (kind L, diagonal stored explicitly)
 template <typename T>
-__global__ void k_rho_plain(int64_t n, const int32_t *__restrict__ rp, const T *__restrict__ a,
+static __global__ void k_rho_plain(int64_t n, const int32_t *__restrict__ rp, const T *__restrict__ a,
                             double *__restrict__ rho)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -148,7 +148,7 @@ __global__ void k_rho_plain(int64_t n, const int32_t *__restrict__ rp, const T *
 // Structural checks of a device-resident CSR (same rules as the host validator).
 // flags bit 0: graph malformed, bit 1: asymmetric, bit 2: bad weight.
 template <typename T>
-__global__ void k_validate_graph(int64_t n, int64_t nnz, const int64_t *__restrict__ rp64,
+static __global__ void k_validate_graph(int64_t n, int64_t nnz, const int64_t *__restrict__ rp64,
                                  const int32_t *__restrict__ ci, const T *__restrict__ w, int kind_L,
                                  unsigned int *flags)
 {
@@ -178,14 +178,14 @@ __global__ void k_validate_graph(int64_t n, int64_t nnz, const int64_t *__restri
     }
 }
 
-__global__ void k_rowptr_narrow(int64_t n, const int64_t *__restrict__ rp64, int32_t *__restrict__ rp32)
+static __global__ void k_rowptr_narrow(int64_t n, const int64_t *__restrict__ rp64, int32_t *__restrict__ rp32)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x)
         rp32[i] = (int32_t)rp64[i];
 }
 
 // lab[i] = class of a labelled node, -1 otherwise; flags bit 3: bad label set
-__global__ void k_scatter_labels(int64_t n, int64_t nl, int32_t K, const int32_t *__restrict__ idx,
+static __global__ void k_scatter_labels(int64_t n, int64_t nl, int32_t K, const int32_t *__restrict__ idx,
                                  const int32_t *__restrict__ labels, int32_t *__restrict__ lab, unsigned int *flags)
 {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nl; t += (int64_t)gridDim.x * blockDim.x) {
@@ -195,7 +195,7 @@ __global__ void k_scatter_labels(int64_t n, int64_t nl, int32_t K, const int32_t
     }
 }
 
-__global__ void k_fill_i32(int64_t n, int32_t *p, int32_t v)
+static __global__ void k_fill_i32(int64_t n, int32_t *p, int32_t v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -902,13 +902,13 @@ __device__ __forceinline__ void spmm_body(const GraphView<T> &gv, const T *__res
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kRowBlock) k_init_u(GraphView<T> gv, const T *__restrict__ U0)
+static __global__ void __launch_bounds__(kRowBlock) k_init_u(GraphView<T> gv, const T *__restrict__ U0)
 {
     init_body<T>(gv, U0, blockIdx.x);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kRowBlock) k_init_u_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kRowBlock) k_init_u_batch(const GraphView<T> *__restrict__ views,
                                                              const TileRef *__restrict__ refs,
                                                              const T *const *__restrict__ U0s)
 {
@@ -917,14 +917,14 @@ __global__ void __launch_bounds__(kRowBlock) k_init_u_batch(const GraphView<T> *
 }
 
 template <typename T, int KB>
-__global__ void __launch_bounds__(kRowBlock) k_spmm(GraphView<T> gv, const T *__restrict__ Uin, T *__restrict__ Pout)
+static __global__ void __launch_bounds__(kRowBlock) k_spmm(GraphView<T> gv, const T *__restrict__ Uin, T *__restrict__ Pout)
 {
     spmm_body<T, KB>(gv, Uin, Pout, blockIdx.x);
 }
 
 // batched L_s U_0 -> P at the start of a batched solve
 template <typename T, int KB>
-__global__ void __launch_bounds__(kRowBlock) k_spmm_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kRowBlock) k_spmm_batch(const GraphView<T> *__restrict__ views,
                                                            const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
@@ -936,13 +936,13 @@ __global__ void __launch_bounds__(kRowBlock) k_spmm_batch(const GraphView<T> *__
 // single-graph and batched entry points
 // ---------------------------------------------------------------------------------
 template <typename T, typename ST, int KB>
-__global__ void __launch_bounds__(kRowBlock) k_row(GraphView<T> gv, int apply_only)
+static __global__ void __launch_bounds__(kRowBlock) k_row(GraphView<T> gv, int apply_only)
 {
     row_body<T, ST, KB>(gv, blockIdx.x, apply_only);
 }
 
 template <typename T, typename ST, int KB>
-__global__ void __launch_bounds__(kRowBlock) k_row_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kRowBlock) k_row_batch(const GraphView<T> *__restrict__ views,
                                                           const TileRef *__restrict__ refs, int apply_only)
 {
     const TileRef r = refs[blockIdx.x];
@@ -950,13 +950,13 @@ __global__ void __launch_bounds__(kRowBlock) k_row_batch(const GraphView<T> *__r
 }
 
 template <typename T, typename ST, int KB>
-__global__ void __launch_bounds__(kRowBlock) k_label(GraphView<T> gv)
+static __global__ void __launch_bounds__(kRowBlock) k_label(GraphView<T> gv)
 {
     label_body<T, ST, KB>(gv, blockIdx.x);
 }
 
 template <typename T, typename ST, int KB>
-__global__ void __launch_bounds__(kRowBlock) k_label_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kRowBlock) k_label_batch(const GraphView<T> *__restrict__ views,
                                                             const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
@@ -964,20 +964,20 @@ __global__ void __launch_bounds__(kRowBlock) k_label_batch(const GraphView<T> *_
 }
 
 template <typename T, typename ST, int KB>
-__global__ void __launch_bounds__(kSortedThreads) k_label_sorted(GraphView<T> gv)
+static __global__ void __launch_bounds__(kSortedThreads) k_label_sorted(GraphView<T> gv)
 {
     label_sorted_body<T, ST, KB>(gv, blockIdx.x);
 }
 
 template <typename T, typename ST, int KB>
-__global__ void __launch_bounds__(kSortedThreads) k_label_sorted_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kSortedThreads) k_label_sorted_batch(const GraphView<T> *__restrict__ views,
                                                                         const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
     label_sorted_body<T, ST, KB>(views[r.graph], r.tile);
 }
 
-__global__ void __launch_bounds__(kFinishThreads) k_finish(const double *__restrict__ row_part, int nb_row,
+static __global__ void __launch_bounds__(kFinishThreads) k_finish(const double *__restrict__ row_part, int nb_row,
                                                            const double *__restrict__ lab_part, int nb_lab,
                                                            Ctl *__restrict__ ctl)
 {
@@ -1032,13 +1032,13 @@ __device__ __forceinline__ void energy_sum_body(const double *__restrict__ part,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kRowBlock) k_energy(GraphView<T> gv, const T *__restrict__ U, const T *__restrict__ P,
+static __global__ void __launch_bounds__(kRowBlock) k_energy(GraphView<T> gv, const T *__restrict__ U, const T *__restrict__ P,
                                                        double omega0, double *__restrict__ part)
 {
     energy_body<T>(gv, U, P, omega0, part, blockIdx.x);
 }
 
-__global__ void __launch_bounds__(kFinishThreads) k_energy_sum(const double *__restrict__ part, int nb,
+static __global__ void __launch_bounds__(kFinishThreads) k_energy_sum(const double *__restrict__ part, int nb,
                                                                double inv_eps, double *__restrict__ out)
 {
     energy_sum_body(part, nb, inv_eps, out);
@@ -1047,7 +1047,7 @@ __global__ void __launch_bounds__(kFinishThreads) k_energy_sum(const double *__r
 // batched objective of the final iterates: P = L U goes to Q (free after the solve), the
 // tile partials to row_part
 template <typename T, int KB>
-__global__ void __launch_bounds__(kRowBlock) k_spmm_to_q_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kRowBlock) k_spmm_to_q_batch(const GraphView<T> *__restrict__ views,
                                                                 const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
@@ -1056,7 +1056,7 @@ __global__ void __launch_bounds__(kRowBlock) k_spmm_to_q_batch(const GraphView<T
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kRowBlock) k_energy_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kRowBlock) k_energy_batch(const GraphView<T> *__restrict__ views,
                                                              const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
@@ -1066,7 +1066,7 @@ __global__ void __launch_bounds__(kRowBlock) k_energy_batch(const GraphView<T> *
 
 // one workgroup per graph: objective and a copy of the control block
 template <typename T>
-__global__ void __launch_bounds__(kFinishThreads) k_collect_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kFinishThreads) k_collect_batch(const GraphView<T> *__restrict__ views,
                                                                   double *__restrict__ E, Ctl *__restrict__ ctls)
 {
     const GraphView<T> &gv = views[blockIdx.x];
@@ -1076,14 +1076,14 @@ __global__ void __launch_bounds__(kFinishThreads) k_collect_batch(const GraphVie
 
 // writes the initial control blocks of a batch
 template <typename T>
-__global__ void k_set_ctl_batch(const GraphView<T> *__restrict__ views, const Ctl *__restrict__ src, int count)
+static __global__ void k_set_ctl_batch(const GraphView<T> *__restrict__ views, const Ctl *__restrict__ src, int count)
 {
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < count; g += gridDim.x * blockDim.x) *views[g].ctl = src[g];
 }
 
 // labels (lowest-index argmax of each row of U) for the rows of a tile
 template <typename T>
-__global__ void __launch_bounds__(kRowBlock) k_labels_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kRowBlock) k_labels_batch(const GraphView<T> *__restrict__ views,
                                                              const TileRef *__restrict__ refs,
                                                              int32_t *const *__restrict__ outs)
 {
@@ -1105,7 +1105,7 @@ __global__ void __launch_bounds__(kRowBlock) k_labels_batch(const GraphView<T> *
 
 // 1 while some graph of the batch still has an iteration to evaluate or an update to commit
 template <typename T>
-__global__ void k_any_active(const GraphView<T> *__restrict__ views, int count, int32_t *__restrict__ flag)
+static __global__ void k_any_active(const GraphView<T> *__restrict__ views, int count, int32_t *__restrict__ flag)
 {
     int a = 0;
     for (int g = threadIdx.x; g < count; g += blockDim.x) a |= views[g].ctl->active | views[g].ctl->pending;
@@ -1113,9 +1113,22 @@ __global__ void k_any_active(const GraphView<T> *__restrict__ views, int count, 
     if (threadIdx.x == 0) *flag = a;
 }
 
+template <typename T>
+static __global__ void k_clear_pending_batch(const GraphView<T> *__restrict__ views, int count)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < count; g += gridDim.x * blockDim.x)
+        views[g].ctl->pending = 0;
+}
+
+template <typename T>
+static __global__ void k_ctl_gather_batch(const GraphView<T> *__restrict__ views, Ctl *__restrict__ out, int count)
+{
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < count; g += gridDim.x * blockDim.x) out[g] = *views[g].ctl;
+}
+
 // one workgroup per graph of the batch
 template <typename T>
-__global__ void __launch_bounds__(kFinishThreads) k_finish_batch(const GraphView<T> *__restrict__ views)
+static __global__ void __launch_bounds__(kFinishThreads) k_finish_batch(const GraphView<T> *__restrict__ views)
 {
     const GraphView<T> &gv = views[blockIdx.x];
     finish_body(gv.row_part, gv.nb_row, gv.lab_part, gv.n_tiles > 0 ? gv.n_tiles : gv.nb_row, gv.ctl);
@@ -1124,7 +1137,7 @@ __global__ void __launch_bounds__(kFinishThreads) k_finish_batch(const GraphView
 // labels_i = lowest-index argmax_c U_ic; s_out = vertex indices of the last GLMO output
 // (-1 when no iteration was evaluated).
 template <typename T, typename ST>
-__global__ void k_outputs(int64_t n, int32_t K, const T *__restrict__ U, const ST *__restrict__ s0,
+static __global__ void k_outputs(int64_t n, int32_t K, const T *__restrict__ U, const ST *__restrict__ s0,
                           const ST *__restrict__ s1, const Ctl *__restrict__ ctl, int32_t *__restrict__ labels,
                           int32_t *__restrict__ s_out)
 {
@@ -1143,12 +1156,12 @@ __global__ void k_outputs(int64_t n, int32_t K, const T *__restrict__ U, const S
     }
 }
 
-__global__ void k_clear_pending(Ctl *ctl)
+static __global__ void k_clear_pending(Ctl *ctl)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) ctl->pending = 0;
 }
 
-__global__ void k_max_reduce(const double *__restrict__ v, int64_t n, double *__restrict__ out)
+static __global__ void k_max_reduce(const double *__restrict__ v, int64_t n, double *__restrict__ out)
 {
     __shared__ double red[kFinishThreads / 64];
     double m = 0.0;

@@ -290,6 +290,49 @@ def solve_batched(ctx: Context, graphs: list, prms, want_U: bool = True, want_la
     return out
 
 
+class Server:
+    """gfw_server_*: continuous-batching request server on one context."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int):
+        self.ctx = ctx
+        self.handle = C.c_void_p()
+        check(lib().gfw_server_create(ctx.handle, int(hbm_budget_bytes), int(max_slots), C.byref(self.handle)))
+        self._meta = {}
+
+    def submit(self, n, K, indptr, indices, data, labelled_idx, labels, prm: Params, dtype: int = F32,
+               kind: int = GRAPH_W) -> int:
+        pb, keep = host_problem(n, K, indptr, indices, data, labelled_idx, labels, dtype, kind)
+        t = C.c_uint64()
+        check(lib().gfw_server_submit(self.handle, C.byref(pb), C.byref(prm), C.byref(t)))
+        self._meta[t.value] = (n, K, dtype)
+        return t.value
+
+    def poll(self, ticket: int, blocking: bool = True):
+        """The result dict, or None when not ready (non-blocking)."""
+        n, K, dtype = self._meta[ticket]
+        U = np.empty((n, K), np.float32 if dtype == F32 else np.float64)
+        lab = np.empty(n, np.int32)
+        st = Stats()
+        rc = lib().gfw_server_poll(self.handle, ticket, int(blocking), U.ctypes.data, lab.ctypes.data, C.byref(st))
+        if rc == -8:
+            return None
+        del self._meta[ticket]
+        check(rc)
+        return dict(U=U, labels=lab, iters=st.iters, stop_reason=st.stop_reason, gap=st.gap, objective=st.objective,
+                    alpha_last=st.alpha_last)
+
+    def close(self):
+        if self.handle:
+            lib().gfw_server_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def objective(ctx: Context, g: Graph, prm: Params, U, stream=None) -> float:
     E = C.c_double()
     check(lib().gfw_objective(ctx.handle, g.handle, C.byref(prm), U.data_ptr(), C.byref(E), _stream(stream)))
