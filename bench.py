@@ -86,6 +86,144 @@ def cpu_baseline(prob, iters: int) -> dict:
                       f"FP64, serial C, including the final objective evaluation; {dt:.1f} s"}
 
 
+def bench_batched(gfw, ctx, count: int, seed: int = 3) -> dict:
+    """The batch workload: `count` graphs (SBMs and 4-neighbour image grids, n log-uniform
+    in [2e3, 2e5], K in 3..10), 300 iterations / gap 1e-6 each: one gfw_solve_batched call
+    against one gfw_solve per graph on the same resident graphs."""
+    import numpy as np
+    import torch
+
+    from synth import configs
+
+    t0 = time.time()
+    probs = configs.batch_mix(seed=seed, count=count)
+    Gs = [gfw.Graph.from_host(ctx, p.n, p.K, p.graph.indptr, p.graph.indices, p.graph.data, p.labelled_idx,
+                              p.labels, gfw.F32) for p in probs]
+    log(f"[bench] batch: {count} graphs ready in {time.time() - t0:.1f}s "
+        f"(sum n={sum(p.n for p in probs)}, sum nnz={sum(p.graph.nnz for p in probs)})")
+    prm = gfw.params(eps=50.0, omega0=1000.0, max_iter=300, tol=1e-6)
+    gfw.solve_batched(ctx, Gs[:8], prm, want_stats=False)  # warm-up (kernel loading)
+    gfw.solve(ctx, Gs[0], prm, want_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = gfw.solve_batched(ctx, Gs, prm, want_stats=False)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rs = [gfw.solve(ctx, G, prm, want_stats=False) for G in Gs]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    same = sum(int(torch.equal(a["labels"], b["labels"]) and torch.equal(a["U"], b["U"])) for a, b in zip(rb, rs))
+    acc = float(np.mean([np.mean(b["labels"].cpu().numpy() == p.graph.truth) for b, p in zip(rb, probs)]))
+    for G in Gs:
+        G.close()
+    return {"graphs": count, "batched_solves_per_s": round(count / t_batch, 1),
+            "sequential_solves_per_s": round(count / t_seq, 1), "speedup": round(t_seq / t_batch, 2),
+            "batched_s": round(t_batch, 3), "sequential_s": round(t_seq, 3),
+            "identical_results": f"{same}/{count}", "mean_accuracy": round(acc, 4)}
+
+
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def bench_serving(gfw, ctx, n_sat: int, n_load: int, n_fifo: int, seed: int = 4) -> dict:
+    """The serving workload: 8-neighbour image grids (sides 128..1024, K in {3,4,6}, 2%
+    scribbles), 300 iterations / gap 1e-6.  Saturation throughput with everything submitted
+    at once, then Poisson arrivals at 80% of it, served by the continuous-batching server and,
+    at the same rate, by a FIFO one-at-a-time loop (graph set-up + gfw_solve per request)."""
+    import random
+    import threading
+
+    import numpy as np
+    import torch
+
+    from synth import configs
+
+    t0 = time.time()
+    pool = configs.serve_pool(seed)
+    log(f"[bench] serve: pool of {len(pool)} requests in {time.time() - t0:.1f}s")
+    prm = gfw.params(eps=50.0, omega0=1000.0, max_iter=300, tol=1e-6)
+
+    def submit(sv, p):
+        g = p.graph
+        return sv.submit(g.n, p.K, g.indptr, g.indices, g.data, p.labelled_idx, p.labels, prm)
+
+    def run_server(arrivals):
+        """arrivals: list of (time offset, problem); returns latencies and wall time."""
+        sv = gfw.Server(ctx, 96 << 30, 64)
+        lat, pend = [], {}
+        lock = threading.Lock()
+        t_start = time.perf_counter()
+
+        def feeder():
+            for off, p in arrivals:
+                d = t_start + off - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                t_sub = time.perf_counter()
+                tk = submit(sv, p)
+                with lock:
+                    pend[tk] = t_sub
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        done = 0
+        while done < len(arrivals):
+            with lock:
+                items = list(pend.items())
+            for tk, ts in items:
+                r = sv.poll(tk, blocking=False)
+                if r is not None:
+                    lat.append(time.perf_counter() - ts)
+                    with lock:
+                        del pend[tk]
+                    done += 1
+            time.sleep(0.0005)
+        th.join()
+        wall = time.perf_counter() - t_start
+        sv.close()
+        return lat, wall
+
+    # warm-up
+    run_server([(0.0, pool[i]) for i in range(4)])
+    lat, wall = run_server([(0.0, pool[i % len(pool)]) for i in range(n_sat)])
+    mu = n_sat / wall
+    lam = 0.8 * mu
+    rng = random.Random(7)
+    offs, t = [], 0.0
+    for i in range(max(n_load, n_fifo)):
+        t += rng.expovariate(lam)
+        offs.append(t)
+    order = [rng.randrange(len(pool)) for _ in offs]
+    lat_b, wall_b = run_server([(offs[i], pool[order[i]]) for i in range(n_load)])
+
+    # FIFO one-at-a-time at the same arrival times
+    lat_f = []
+    t_start = time.perf_counter()
+    for i in range(n_fifo):
+        d = t_start + offs[i] - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        t_arr = t_start + offs[i]
+        p = pool[order[i]]
+        G = gfw.Graph.from_host(ctx, p.n, p.K, p.graph.indptr, p.graph.indices, p.graph.data, p.labelled_idx,
+                                p.labels, gfw.F32)
+        r = gfw.solve(ctx, G, prm, want_stats=False)
+        r["labels"].cpu()
+        G.close()
+        lat_f.append(time.perf_counter() - t_arr)
+    wall_f = time.perf_counter() - t_start
+    return {"requests_saturation": n_sat, "saturation_solves_per_s": round(mu, 1),
+            "arrival_rate_per_s": round(lam, 1),
+            "served": {"requests": n_load, "solves_per_s": round(n_load / wall_b, 1),
+                       "p50_ms": round(1e3 * _pct(lat_b, 50), 1), "p99_ms": round(1e3 * _pct(lat_b, 99), 1)},
+            "fifo_one_at_a_time": {"requests": n_fifo, "solves_per_s": round(n_fifo / wall_f, 1),
+                                   "p50_ms": round(1e3 * _pct(lat_f, 50), 1),
+                                   "p99_ms": round(1e3 * _pct(lat_f, 99), 1)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +233,8 @@ def main() -> int:
     ap.add_argument("--iters", type=int, default=1000)
     ap.add_argument("--cpu-iters", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch", type=int, default=256, help="graphs in the batch measurement (0: skip)")
+    ap.add_argument("--serve", type=int, default=160, help="requests under load in the serving measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design, "
@@ -177,6 +317,16 @@ def main() -> int:
     lab = last["labels"].cpu().numpy()
     acc = float(np.mean(lab == g.truth))
 
+    G.close()
+    extra = {}
+    if args.batch > 0:
+        extra["batched"] = bench_batched(gfw, ctx, args.batch)
+        log("[bench] batched: " + json.dumps(extra["batched"]))
+    if args.serve > 0:
+        extra["serving"] = bench_serving(gfw, ctx, n_sat=max(48, args.serve // 2), n_load=args.serve,
+                                         n_fifo=max(24, args.serve // 4))
+        log("[bench] serving: " + json.dumps(extra["serving"]))
+
     cpu = None
     if not args.no_cpu:
         log(f"[bench] cpu baseline: {args.cpu_iters} oracle iterations")
@@ -209,6 +359,7 @@ def main() -> int:
         "objective": last["objective"],
         "source_hash": src_hash,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -351,24 +351,37 @@ static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const 
 
 // Chooses and prepares the label path: the column-sorted pass for large graphs whose
 // neighbour labels are scattered, the plain pass otherwise.  mode: 0 auto, 1 plain, 2 sorted.
-static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st)
+// host_col: the column indices in host memory when the caller has them (else they are
+// copied back from the device when needed).
+static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st, const int32_t *host_col = nullptr)
 {
     if (mode == 1) {
         g->label_path = 0;
         return GFW_OK;
     }
-    std::vector<int32_t> rp((size_t)g->n + 1), col((size_t)std::max<int64_t>(g->nnz, 1));
-    GFW_HIP_TRY(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToHost, st));
-    if (g->nnz) GFW_HIP_TRY(hipMemcpyAsync(col.data(), g->col, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToHost, st));
-    GFW_HIP_TRY(hipStreamSynchronize(st));
-    g->locality = label_locality(g->nnz, col.data());
-    const bool want = mode == 2 || (g->nnz >= (int64_t)4 << 20 && g->locality > 16.0);
+    const bool big = g->nnz >= ((int64_t)4 << 20);
+    if (mode == 0 && !big) { // small graphs keep the plain pass whatever their locality
+        g->label_path = 0;
+        return GFW_OK;
+    }
+    std::vector<int32_t> col;
+    if (!host_col) {
+        col.resize((size_t)std::max<int64_t>(g->nnz, 1));
+        if (g->nnz) GFW_HIP_TRY(hipMemcpyAsync(col.data(), g->col, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipStreamSynchronize(st));
+        host_col = col.data();
+    }
+    g->locality = label_locality(g->nnz, host_col);
+    const bool want = mode == 2 || g->locality > 16.0;
     if (!want) {
         g->label_path = 0;
         return GFW_OK;
     }
     if (!g->gcol) {
-        gfw_status_t s = build_sorted_tiles(g, rp.data(), col.data(), st);
+        std::vector<int32_t> rp((size_t)g->n + 1);
+        GFW_HIP_TRY(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipStreamSynchronize(st));
+        gfw_status_t s = build_sorted_tiles(g, rp.data(), host_col, st);
         if (s != GFW_OK) {
             if (mode == 2) return s;
             g->label_path = 0; // a row too long for the sorted tiles: keep the plain pass
@@ -383,9 +396,10 @@ static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st)
     return GFW_OK;
 }
 
-gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st)
+gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st,
+                          bool validated)
 {
-    gfw_status_t s = check_problem(p);
+    gfw_status_t s = validated ? GFW_OK : check_problem(p);
     if (s != GFW_OK) return s;
     GFW_HIP_TRY(hipSetDevice(ctx->device));
     gfw_graph_s *g = new (std::nothrow) gfw_graph_s();
@@ -487,7 +501,7 @@ gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_
     dfree(wraw);
     if (s != GFW_OK) return s;
     g->shape = shape_for(n, nnz, p->K);
-    if ((s = choose_label_path(g, 0, st)) != GFW_OK) return s;
+    if ((s = choose_label_path(g, 0, st, p->location == GFW_HOST ? p->col_idx : nullptr)) != GFW_OK) return s;
     g->graph_bytes += 4 * (n + 1) + (4 + vs) * nnz + 4 * n;
     g->solve_bytes = 3 * vs * n * p->K + 2 * n + sizeof(double) * ((kRowParts + 4) * g->shape.nb_row + 64) +
                      sizeof(Ctl);

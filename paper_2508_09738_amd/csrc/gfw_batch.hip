@@ -37,45 +37,81 @@ static void set_batch_lds_limits()
 
 static int bucket_of(int kmax) { return kmax == 4 ? 0 : kmax == 8 ? 1 : 2; }
 
+// A grow-only device array (kept across macro-steps of the server).
+template <typename E>
+struct DevArr {
+    E *p = nullptr;
+    size_t cap = 0;
+    ~DevArr() { dfree(p); }
+    gfw_status_t reserve(size_t n)
+    {
+        if (n <= cap) return GFW_OK;
+        dfree(p);
+        p = nullptr;
+        cap = 0;
+        const size_t c = n + n / 2 + 16;
+        if (hipMalloc((void **)&p, sizeof(E) * c) != hipSuccess) return fail(GFW_E_NOMEM, "batch table allocation");
+        cap = c;
+        return GFW_OK;
+    }
+};
+
 // Device tables of one batch: the graph views and, per K bucket, the (graph, tile) lists of
-// the row-wise kernels and of the two label passes.
+// the row-wise kernels and of the two label passes.  Reusable: prepare() refills them.
 template <typename T>
 struct BatchTables {
     std::vector<GraphView<T>> views;
     std::vector<TileRef> rows[3], plain[3], sorted[3], all_rows;
+    // host staging of the per-graph control blocks, U_0 pointers and label destinations; kept
+    // here so that they outlive the asynchronous copies that read them
+    std::vector<Ctl> ctl0;
+    std::vector<const T *> u0;
+    std::vector<int32_t *> lab_out;
+    DevArr<GraphView<T>> dv;
+    DevArr<TileRef> drows[3], dplain[3], dsorted[3], dall;
+    DevArr<int32_t> dflag;
+    DevArr<const T *> dU0;
+    DevArr<int32_t *> dlab;
+    DevArr<Ctl> dctl0, dctl_out;
+    DevArr<double> dE;
+    int32_t *h_flag = nullptr;
+    // device pointers of the current contents
     GraphView<T> *d_views = nullptr;
     TileRef *d_rows[3] = {}, *d_plain[3] = {}, *d_sorted[3] = {}, *d_all = nullptr;
     int32_t *d_flag = nullptr;
-    int32_t *h_flag = nullptr;
     const T **d_U0 = nullptr;
     int32_t **d_lab_out = nullptr;
     Ctl *d_ctl0 = nullptr, *d_ctl_out = nullptr;
     double *d_E = nullptr;
+    void reset()
+    {
+        views.clear();
+        for (int b = 0; b < 3; ++b) {
+            rows[b].clear();
+            plain[b].clear();
+            sorted[b].clear();
+        }
+        all_rows.clear();
+        d_U0 = nullptr;
+        d_lab_out = nullptr;
+    }
     ~BatchTables()
     {
-        dfree(d_views);
-        for (int b = 0; b < 3; ++b) {
-            dfree(d_rows[b]);
-            dfree(d_plain[b]);
-            dfree(d_sorted[b]);
-        }
-        dfree(d_all);
-        dfree(d_flag);
-        dfree((void *)d_U0);
-        dfree(d_lab_out);
-        dfree(d_ctl0);
-        dfree(d_ctl_out);
-        dfree(d_E);
         if (h_flag) (void)hipHostFree(h_flag);
     }
 };
 
-template <typename T>
-static gfw_status_t upload(std::vector<T> &v, T **d, hipStream_t st)
+template <typename E>
+static gfw_status_t upload(std::vector<E> &v, DevArr<E> &arr, E **d, hipStream_t st)
 {
-    if (v.empty()) return GFW_OK;
-    if (hipMalloc((void **)d, sizeof(T) * v.size()) != hipSuccess) return fail(GFW_E_NOMEM, "batch table allocation");
-    GFW_HIP_TRY(hipMemcpyAsync(*d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    if (v.empty()) {
+        *d = nullptr;
+        return GFW_OK;
+    }
+    gfw_status_t s = arr.reserve(v.size());
+    if (s != GFW_OK) return s;
+    *d = arr.p;
+    GFW_HIP_TRY(hipMemcpyAsync(*d, v.data(), sizeof(E) * v.size(), hipMemcpyHostToDevice, st));
     return GFW_OK;
 }
 
@@ -124,9 +160,13 @@ static gfw_status_t batch_prepare(BatchTables<T> &bt, int32_t count, gfw_graph_s
     static const bool lds_set = (set_batch_lds_limits<T, 4>(), set_batch_lds_limits<T, 8>(),
                                  set_batch_lds_limits<T, 16>(), true); // once, thread-safe
     (void)lds_set;
-    std::vector<Ctl> ctl0((size_t)count);
-    std::vector<const T *> u0((size_t)count, nullptr);
-    std::vector<int32_t *> lab_out((size_t)count, nullptr);
+    bt.reset();
+    std::vector<Ctl> &ctl0 = bt.ctl0;
+    std::vector<const T *> &u0 = bt.u0;
+    std::vector<int32_t *> &lab_out = bt.lab_out;
+    ctl0.assign((size_t)count, Ctl{});
+    u0.assign((size_t)count, nullptr);
+    lab_out.assign((size_t)count, nullptr);
     int32_t max_iter = 0;
     bool any_u0 = false, watch_stop = false;
     for (int32_t i = 0; i < count; ++i) {
@@ -161,19 +201,20 @@ static gfw_status_t batch_prepare(BatchTables<T> &bt, int32_t count, gfw_graph_s
         lab_out[(size_t)i] = labels_out ? labels_out[i] : nullptr;
     }
     gfw_status_t s;
-    if ((s = upload(bt.views, &bt.d_views, st)) != GFW_OK) return s;
+    if ((s = upload(bt.views, bt.dv, &bt.d_views, st)) != GFW_OK) return s;
     for (int b = 0; b < 3; ++b) {
-        if ((s = upload(bt.rows[b], &bt.d_rows[b], st)) != GFW_OK) return s;
-        if ((s = upload(bt.plain[b], &bt.d_plain[b], st)) != GFW_OK) return s;
-        if ((s = upload(bt.sorted[b], &bt.d_sorted[b], st)) != GFW_OK) return s;
+        if ((s = upload(bt.rows[b], bt.drows[b], &bt.d_rows[b], st)) != GFW_OK) return s;
+        if ((s = upload(bt.plain[b], bt.dplain[b], &bt.d_plain[b], st)) != GFW_OK) return s;
+        if ((s = upload(bt.sorted[b], bt.dsorted[b], &bt.d_sorted[b], st)) != GFW_OK) return s;
     }
-    if ((s = upload(bt.all_rows, &bt.d_all, st)) != GFW_OK) return s;
-    if (labels_out && (s = upload(lab_out, &bt.d_lab_out, st)) != GFW_OK) return s;
-    if (hipMalloc(&bt.d_flag, sizeof(int32_t)) != hipSuccess) return fail(GFW_E_NOMEM, "batch flag allocation");
-    GFW_HIP_TRY(hipHostMalloc((void **)&bt.h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
+    if ((s = upload(bt.all_rows, bt.dall, &bt.d_all, st)) != GFW_OK) return s;
+    if (labels_out && (s = upload(lab_out, bt.dlab, &bt.d_lab_out, st)) != GFW_OK) return s;
+    if ((s = bt.dflag.reserve(1)) != GFW_OK) return s;
+    bt.d_flag = bt.dflag.p;
+    if (!bt.h_flag) GFW_HIP_TRY(hipHostMalloc((void **)&bt.h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
     if (init_state) {
-        if ((s = upload(ctl0, &bt.d_ctl0, st)) != GFW_OK) return s;
-        if (any_u0 && (s = upload(u0, (const T ***)&bt.d_U0, st)) != GFW_OK) return s;
+        if ((s = upload(ctl0, bt.dctl0, &bt.d_ctl0, st)) != GFW_OK) return s;
+        if (any_u0 && (s = upload(u0, bt.dU0, &bt.d_U0, st)) != GFW_OK) return s;
         // U_0 and P_0 = L_s U_0 for every graph
         k_set_ctl_batch<T><<<grid_for(count, 256), 256, 0, st>>>(bt.d_views, bt.d_ctl0, count);
         k_init_u_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_U0);
@@ -243,10 +284,10 @@ static gfw_status_t batch_collect(BatchTables<T> &bt, bool labels, std::vector<d
     if (!bt.rows[2].empty())
         k_spmm_to_q_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
     k_energy_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all);
-    if (!bt.d_E && hipMalloc(&bt.d_E, sizeof(double) * count) != hipSuccess)
-        return fail(GFW_E_NOMEM, "batch stats allocation");
-    if (!bt.d_ctl_out && hipMalloc(&bt.d_ctl_out, sizeof(Ctl) * count) != hipSuccess)
-        return fail(GFW_E_NOMEM, "batch stats allocation");
+    gfw_status_t s;
+    if ((s = bt.dE.reserve(count)) != GFW_OK || (s = bt.dctl_out.reserve(count)) != GFW_OK) return s;
+    bt.d_E = bt.dE.p;
+    bt.d_ctl_out = bt.dctl_out.p;
     k_collect_batch<T><<<count, kFinishThreads, 0, st>>>(bt.d_views, bt.d_E, bt.d_ctl_out);
     E.resize((size_t)count);
     cs.resize((size_t)count);
@@ -354,11 +395,18 @@ struct gfw_server_s {
     std::deque<gfw::ServerRequest *> queue;
     std::vector<gfw::ServerRequest *> resident;
     std::map<uint64_t, gfw::ServerRequest *> all;
+    // device tables reused by every macro-step (grow-only): admission, iteration, retirement
+    gfw::BatchTables<float> bt32[3];
+    gfw::BatchTables<double> bt64[3];
+    gfw::DevArr<int32_t> lab_pool; // labels of the requests retired in one macro-step
 };
 
 namespace gfw {
 
-static constexpr int kMacroIters = 16; // iterations between admissions / retirements
+static constexpr int kMacroIters = 32; // iterations between admissions / retirements
+
+static BatchTables<float> *server_tables(gfw_server_s *sv, float *) { return sv->bt32; }
+static BatchTables<double> *server_tables(gfw_server_s *sv, double *) { return sv->bt64; }
 
 template <typename T>
 static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &fresh,
@@ -366,6 +414,7 @@ static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &
 {
     hipStream_t st = sv->st;
     gfw_status_t s;
+    BatchTables<T> *tabs = server_tables(sv, (T *)nullptr);
     if (!fresh.empty()) { // U_0, P_0 and control blocks of the newly admitted requests
         std::vector<gfw_graph_s *> gs;
         std::vector<const gfw_params_t *> ps;
@@ -373,11 +422,9 @@ static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &
             gs.push_back(r->g);
             ps.push_back(&r->prm);
         }
-        BatchTables<T> bt;
-        if ((s = batch_prepare<T>(bt, (int32_t)gs.size(), gs.data(), ps.data(), nullptr, st, true, nullptr, nullptr)) !=
-            GFW_OK)
+        if ((s = batch_prepare<T>(tabs[0], (int32_t)gs.size(), gs.data(), ps.data(), nullptr, st, true, nullptr,
+                                  nullptr)) != GFW_OK)
             return s;
-        GFW_HIP_TRY(hipStreamSynchronize(st));
     }
     if (run.empty()) return GFW_OK;
     std::vector<gfw_graph_s *> gs;
@@ -387,7 +434,7 @@ static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &
         gs.push_back(r->g);
         ps.push_back(&r->prm);
     }
-    BatchTables<T> bt;
+    BatchTables<T> &bt = tabs[1];
     if ((s = batch_prepare<T>(bt, (int32_t)gs.size(), gs.data(), ps.data(), nullptr, st, false, nullptr, nullptr)) !=
         GFW_OK)
         return s;
@@ -395,13 +442,12 @@ static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &
     batch_commit<T>(bt, st);
     // which requests are finished
     const int count = (int)gs.size();
-    Ctl *d_c = nullptr;
-    if (hipMalloc(&d_c, sizeof(Ctl) * count) != hipSuccess) return fail(GFW_E_NOMEM, "server state allocation");
+    if ((s = bt.dctl_out.reserve(count)) != GFW_OK) return s;
+    Ctl *d_c = bt.dctl_out.p;
     k_ctl_gather_batch<T><<<grid_for(count, 256), 256, 0, st>>>(bt.d_views, d_c, count);
     std::vector<Ctl> cs((size_t)count);
     GFW_HIP_TRY(hipMemcpyAsync(cs.data(), d_c, sizeof(Ctl) * count, hipMemcpyDeviceToHost, st));
     GFW_HIP_TRY(hipStreamSynchronize(st));
-    dfree(d_c);
     std::vector<ServerRequest *> done;
     for (int i = 0; i < count; ++i)
         if (!cs[(size_t)i].active && !cs[(size_t)i].pending) done.push_back(run[(size_t)i]);
@@ -410,16 +456,17 @@ static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &
     std::vector<gfw_graph_s *> dg;
     std::vector<const gfw_params_t *> dp;
     std::vector<int32_t *> dl;
-    std::vector<int32_t *> dev_labels;
+    size_t lab_total = 0;
+    for (auto *r : done) lab_total += (size_t)r->g->n;
+    if ((s = sv->lab_pool.reserve(lab_total)) != GFW_OK) return s;
+    lab_total = 0;
     for (auto *r : done) {
         dg.push_back(r->g);
         dp.push_back(&r->prm);
-        int32_t *lab = nullptr;
-        if (hipMalloc(&lab, sizeof(int32_t) * r->g->n) != hipSuccess) return fail(GFW_E_NOMEM, "label buffer");
-        dev_labels.push_back(lab);
-        dl.push_back(lab);
+        dl.push_back(sv->lab_pool.p + lab_total);
+        lab_total += (size_t)r->g->n;
     }
-    BatchTables<T> bd;
+    BatchTables<T> &bd = tabs[2];
     if ((s = batch_prepare<T>(bd, (int32_t)dg.size(), dg.data(), dp.data(), dl.data(), st, false, nullptr, nullptr)) !=
         GFW_OK)
         return s;
@@ -432,7 +479,7 @@ static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &
         r->U.resize(dsize(g->dtype) * (size_t)g->n * g->K);
         r->labels.resize((size_t)g->n);
         GFW_HIP_TRY(hipMemcpyAsync(r->U.data(), g->ws.U, r->U.size(), hipMemcpyDeviceToHost, st));
-        GFW_HIP_TRY(hipMemcpyAsync(r->labels.data(), dev_labels[i], 4 * (size_t)g->n, hipMemcpyDeviceToHost, st));
+        GFW_HIP_TRY(hipMemcpyAsync(r->labels.data(), dl[i], 4 * (size_t)g->n, hipMemcpyDeviceToHost, st));
         r->stats.iters = dc[i].iters;
         r->stats.stop_reason = dc[i].stop_reason;
         r->stats.gap = dc[i].gap;
@@ -442,7 +489,6 @@ static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &
         if (r->status != GFW_OK) r->error = "NaN met during the iteration";
     }
     GFW_HIP_TRY(hipStreamSynchronize(st));
-    for (int32_t *lab : dev_labels) dfree(lab);
     for (auto *r : done) r->finished = true;
     return GFW_OK;
 }
@@ -467,7 +513,7 @@ static void server_loop(gfw_server_s *sv)
         std::vector<ServerRequest *> fresh, failed;
         for (ServerRequest *r : admit) {
             gfw_graph_s *g = nullptr;
-            gfw_status_t s = graph_create(sv->ctx, &r->prob, &g, sv->st);
+            gfw_status_t s = graph_create(sv->ctx, &r->prob, &g, sv->st, true); // validated at submit
             if (s == GFW_OK) s = ensure_workspace(g, r->prm.max_iter);
             if (s != GFW_OK) {
                 r->status = s;

@@ -120,7 +120,10 @@ struct gfw_graph_s {
 namespace gfw {
 gfw_status_t check_problem(const gfw_problem_t *p);
 gfw_status_t check_params(const gfw_params_t *p, int32_t K);
-gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st);
+// validated = true skips the host validation of a host-resident problem that the caller has
+// already checked with check_problem (the server does so at submit).
+gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st,
+                          bool validated = false);
 void free_graph(gfw_graph_s *g);
 gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter);
 SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm);

@@ -88,11 +88,20 @@ def batch_mix(seed: int = 3, count: int = 256, n_lo: float = 2e3, n_hi: float = 
     return [batch_member(seed, i, n_lo, n_hi) for i in range(count)]
 
 
-def serve_request(seed: int, i: int, sides=(128, 256, 512, 1024), Ks=(3, 4, 6)) -> Problem:
+def serve_request(seed: int, i: int, sides=(128, 256, 512, 1024), Ks=(3, 4, 6), side=None, K=None) -> Problem:
     rg = graphs.rng_for(seed, 200 + i)
-    side = int(sides[int(rg.integers(len(sides)))])
-    K = int(Ks[int(rg.integers(len(Ks)))])
+    s_draw = int(sides[int(rg.integers(len(sides)))])
+    k_draw = int(Ks[int(rg.integers(len(Ks)))])
+    side = s_draw if side is None else int(side)
+    K = k_draw if K is None else int(K)
     sub = seed * 100003 + i
     g = graphs.image_grid(side * side, K, sub, neighbours=8, side=side)
     idx, lab = graphs.scribble_labels(g.truth, side, side, K, 0.02, sub)
     return Problem(g, idx, lab, K, "f32", 50.0, 1000.0, 300, 1e-6, f"serve[{i}]")
+
+
+def serve_pool(seed: int, sides=(128, 256, 512, 1024), Ks=(3, 4, 6)) -> list:
+    """One request of every (side, K) pair: drawing uniformly from this pool is drawing side
+    and K uniformly and independently, as the serving mix asks."""
+    return [serve_request(seed, j * len(sides) + i, side=sd, K=k)
+            for j, k in enumerate(Ks) for i, sd in enumerate(sides)]
