@@ -226,6 +226,7 @@ void free_graph(gfw_graph_s *g)
     dfree(w.Q);
     dfree(w.s0);
     dfree(w.s1);
+    dfree(w.s4);
     dfree(w.row_part);
     dfree(w.lab_part);
     dfree(w.scratch);
@@ -288,8 +289,7 @@ static double label_locality(int64_t nnz, const int32_t *col)
 static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const int32_t *col, hipStream_t st)
 {
     const int64_t n = g->n;
-    const size_t vs = g->dtype == GFW_F32 ? 4 : 8;
-    const int64_t rcap = std::min<int64_t>(4 * kSortedThreads, kSortedMaxEntries / (g->K * (int64_t)vs));
+    const int64_t rcap = 16 * kSortedThreads; // rows per tile (a thread sums at most 16)
     std::vector<int32_t> tr;
     tr.push_back(0);
     int64_t cr = 0, ce = 0;
@@ -527,6 +527,7 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
     if ((s = dalloc(&w.Q, vs * nK)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.s0, g->n)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.s1, g->n)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.s4, (size_t)(g->n + 1) / 2)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.row_part, sizeof(double) * kRowParts * g->shape.nb_row)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.lab_part, sizeof(double) * std::max<int64_t>(g->shape.nb_row, g->n_tiles)))
         != GFW_OK) return s;

@@ -356,7 +356,7 @@ static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter)
     const size_t n = (size_t)p->n, nnz = (size_t)p->nnz, K = (size_t)p->K;
     const size_t nb = (size_t)cdiv(p->n, kRowBlock);
     size_t graph = 4 * (n + 1) + (4 + v) * nnz + 4 * n;
-    if (p->nnz >= ((int64_t)4 << 20)) graph += 6 * nnz + 4 * (nnz / 4096 + 2); // column-sorted copy
+    if (p->nnz >= ((int64_t)4 << 20)) graph += 6 * nnz + 4 * (n + 2); // column-sorted copy and its tiles
     const size_t solve = 3 * v * n * K + 2 * n + 8 * ((size_t)(kRowParts + 4) * nb + 64) + sizeof(Ctl) +
                          8 * 5 * ((size_t)max_iter + 1) + 4096;
     return graph + solve;

@@ -44,6 +44,7 @@ inline size_t dsize(gfw_dtype_t d) { return d == GFW_F32 ? 4 : 8; }
 struct Workspace {
     void *U = nullptr, *P = nullptr, *Q = nullptr; // n x K of the graph dtype
     uint8_t *s0 = nullptr, *s1 = nullptr;          // vertex indices (ping-pong)
+    uint8_t *s4 = nullptr;                         // the current vertices packed two per byte (K <= 16)
     double *row_part = nullptr, *lab_part = nullptr, *scratch = nullptr;
     Ctl *ctl = nullptr;
     double *hist = nullptr;
@@ -146,6 +147,7 @@ GraphView<T> make_view(const gfw_graph_s *g)
     v.Q = (T *)w.Q;
     v.s0 = w.s0;
     v.s1 = w.s1;
+    v.s4 = w.s4;
     v.ctl = w.ctl;
     v.row_part = w.row_part;
     v.lab_part = w.lab_part;

@@ -241,6 +241,7 @@ struct GraphView {
     const int32_t *lab;
     T *U, *P, *Q;
     uint8_t *s0, *s1;
+    uint8_t *s4;      // vertices of the current iteration, two per byte (written for the sorted pass)
     Ctl *ctl;
     double *row_part, *lab_part;
     int32_t nb_row;   // 256-row tiles (row kernel, plain label pass, SpMM)
@@ -330,6 +331,7 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
     double acc[kRowParts];
 #pragma unroll
     for (int j = 0; j < kRowParts; ++j) acc[j] = 0.0;
+    int32_t s_row = 0;
     if (tid < rows) {
         const int64_t i = r0 + tid;
         T *ur = lu + tid * K;
@@ -410,6 +412,7 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
                 s = bi < 0 ? 0 : bi;
             }
             s_cur[i] = (ST)s;
+            s_row = s;
             double gap = 0.0, up = 0.0, dd = 0.0, pen = 0.0, fid = 0.0, ps = 0.0;
 #pragma unroll
             for (int c = 0; c < KB; ++c) {
@@ -432,6 +435,13 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
             acc[PART_DD] = dd;
             acc[PART_NB] = binary ? 0.0 : 1.0;
         }
+    }
+    // graphs on the column-sorted label pass also get the vertices packed two per byte
+    // (rows 2m and 2m+1 in the low and high nibble; r0 is even, so pairs are lane pairs)
+    if (KB <= 16 && gv.n_tiles > 0 && active) {
+        const int32_t s_next = __shfl_down(s_row, 1);
+        if (tid < rows && !(tid & 1))
+            gv.s4[(r0 + tid) >> 1] = (uint8_t)(s_row | ((tid + 1 < rows ? s_next : 0) << 4));
     }
     __syncthreads();
     if (pending) {
@@ -572,19 +582,20 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
 // entries are stored twice: in CSR order (values) and sorted by column (gcol, with gpos the
 // entry's offset inside the tile's CSR range).
 //  1. gather: consecutive threads take consecutive column-sorted entries, so the labels they
-//     load lie close together and share cache lines; each label is written into an LDS
+//     load lie close together and share cache lines; labels are read from the packed
+//     two-per-byte copy (half the lines of the byte array) and each is written into an LDS
 //     array at the entry's CSR offset.
-//  2. rows: each thread sums the histogram of its rows in CSR order, values read from
-//     global memory (a row's values are contiguous) and labels from LDS (the same order,
-//     hence the same result, as label_body).
-//  3. Q rows are staged in LDS (reusing the label array) and written coalesced.
-// Dynamic LDS: kSortedMaxEntries bytes (labels, later Q staging).
-// On a randomly ordered graph the gathers of phase 1 bound this kernel (the L1 address
-// path stalls on scattered lines); sorting within a tile halves the L2 requests of the
-// gathers compared with label_body.
+//  2. rows: each thread sums the histogram of one row at a time in CSR order, values read
+//     from global memory (a row's values are contiguous) and labels from LDS (the same
+//     order, hence the same result, as label_body), and writes the row of Q directly.
+// Dynamic LDS: kSortedMaxEntries bytes.
+// On a randomly ordered graph the gathers of phase 1 bound this kernel: the cost follows the
+// number of distinct cache lines each gather instruction touches, which the column order
+// and the packed labels both reduce.
 template <typename T, typename ST, int KB>
 __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const int tile)
 {
+    static_assert(KB <= 16, "packed labels hold K <= 16");
     const int32_t K = gv.K;
     const int32_t *__restrict__ rp = gv.rp;
     const int32_t *__restrict__ tile_rows = gv.tile_rows;
@@ -592,15 +603,14 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
     const uint16_t *__restrict__ gpos = gv.gpos;
     const T *__restrict__ a = gv.a;
     const int diag_one = gv.diag_one;
-    const ST *__restrict__ s0 = gv.s0;
-    const ST *__restrict__ s1 = gv.s1;
+    const uint8_t *__restrict__ s4 = gv.s4;
     T *__restrict__ Q = gv.Q;
     const Ctl *__restrict__ ctl = gv.ctl;
     double *__restrict__ part = gv.lab_part;
     if (!ctl->active) return;
-    const ST *__restrict__ s = (ctl->k & 1) ? s1 : s0;
+    const ST *__restrict__ s = (ctl->k & 1) ? gv.s1 : gv.s0;
     extern __shared__ unsigned char lds_raw[];
-    uint8_t *llab = lds_raw;                                                  // [kSortedMaxEntries]
+    uint8_t *llab = lds_raw; // [kSortedMaxEntries]
     const int tid = threadIdx.x;
     const int32_t r0 = tile_rows[tile], r1 = tile_rows[tile + 1];
     const int32_t e0 = rp[r0], e1 = rp[r1];
@@ -618,35 +628,24 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
             cc[m] = __builtin_nontemporal_load(gcol + e0 + e);
             pp[m] = (int)__builtin_nontemporal_load(gpos + e0 + e);
         }
-        ST ss[G];
+        uint32_t ss[G];
 #pragma unroll
-        for (int m = 0; m < G; ++m) ss[m] = s[cc[m]];
+        for (int m = 0; m < G; ++m) ss[m] = (uint32_t)s4[cc[m] >> 1];
 #pragma unroll
         for (int m = 0; m < G; ++m)
-            if (b + tid + m * kSortedThreads < E) llab[pp[m]] = (uint8_t)ss[m];
+            if (b + tid + m * kSortedThreads < E) llab[pp[m]] = (uint8_t)((ss[m] >> ((cc[m] & 1) << 2)) & 15u);
     }
     __syncthreads();
 
-    // 2. each thread owns rows r0 + tid + j * kSortedThreads (j < 4)
-    constexpr int RPT = 4;
-    T acc[RPT][KB];
+    // 2. one row at a time per thread: rows r0 + tid + j * kSortedThreads
+    double own = 0.0;
+    for (int r = tid; r < rows; r += kSortedThreads) {
+        const int rb = rp[r0 + r] - e0, re = rp[r0 + r + 1] - e0;
+        T acc[KB];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j)
-#pragma unroll
-        for (int c = 0; c < KB; ++c) acc[j][c] = (T)0;
-    int rb[RPT], re[RPT];
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = tid + j * kSortedThreads;
-        rb[j] = r < rows ? rp[r0 + r] - e0 : 0;
-        re[j] = r < rows ? rp[r0 + r + 1] - e0 : 0;
-    }
-    // the values of a row are contiguous; each thread reads its rows' values directly
-    // (four at a time) and the labels from LDS
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        int p = rb[j];
-        for (; p + 4 <= re[j]; p += 4) {
+        for (int c = 0; c < KB; ++c) acc[c] = (T)0;
+        int p = rb;
+        for (; p + 4 <= re; p += 4) {
             T v[4];
             int32_t sj[4];
 #pragma unroll
@@ -657,39 +656,25 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int c = 0; c < KB; ++c) acc[j][c] += (c == sj[u]) ? v[u] : (T)0;
+                for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? v[u] : (T)0;
         }
-        for (; p < re[j]; ++p) {
+        for (; p < re; ++p) {
             const T v = a[e0 + p];
             const int32_t sj = (int32_t)llab[p];
 #pragma unroll
-            for (int c = 0; c < KB; ++c) acc[j][c] += (c == sj) ? v : (T)0;
+            for (int c = 0; c < KB; ++c) acc[c] += (c == sj) ? v : (T)0;
         }
-    }
-    __syncthreads(); // all label reads done: the label array becomes the Q staging area
-
-    // 3. Q rows (rows * K * sizeof(T) <= kSortedMaxEntries by construction of the tiles)
-    T *lq = reinterpret_cast<T *>(llab);
-    double own = 0.0;
+        const int32_t si = (int32_t)s[r0 + r];
+        T *__restrict__ qr = Q + (int64_t)(r0 + r) * K;
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int r = tid + j * kSortedThreads;
-        if (r < rows) {
-            const int32_t si = (int32_t)s[r0 + r];
-#pragma unroll
-            for (int c = 0; c < KB; ++c) {
-                if (c < K) {
-                    const T v = acc[j][c] + ((diag_one && c == si) ? (T)1 : (T)0);
-                    lq[r * K + c] = v;
-                    if (c == si) own += (double)v;
-                }
+        for (int c = 0; c < KB; ++c) {
+            if (c < K) {
+                const T v = acc[c] + ((diag_one && c == si) ? (T)1 : (T)0);
+                qr[c] = v;
+                if (c == si) own += (double)v;
             }
         }
     }
-    __syncthreads();
-    const int cntq = rows * K;
-    const int64_t base = (int64_t)r0 * K;
-    for (int q = tid; q < cntq; q += kSortedThreads) Q[base + q] = lq[q];
     // fixed-order block sum (16 waves)
     __shared__ double red[kSortedThreads / 64];
     own = wave_sum(own);

@@ -2,7 +2,7 @@
 
 Both passes sum every row's label histogram in CSR order, so Q = L_s S is the same; only the
 order of the per-tile partial sums differs.  Graphs here are forced onto the sorted path with
-gfw_graph_tune; they cover FP32/FP64, K = 2..16 (tile limits from the Q staging area),
+gfw_graph_tune; they cover FP32/FP64, K = 2..16 (labels packed two per byte),
 rows without entries and a ragged last tile."""
 import numpy as np
 import pytest
