@@ -73,6 +73,87 @@ def traffic_from_profile(kernel: str, src_hash: str):
     return e.get("bytes_per_launch")
 
 
+def copy_peak_gbs(torch, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Achievable HBM bandwidth: a plain device-to-device copy of `nbytes` (read + write)."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def calibrate_copy() -> int:
+    """Copy kernel of known size for scaling the FETCH_SIZE / WRITE_SIZE counters: five
+    copies of 1 GiB (each reads 1 GiB and writes 1 GiB)."""
+    import torch
+
+    src = torch.ones((1 << 30) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copies": 5, "bytes_read_per_copy": 1 << 30, "bytes_written_per_copy": 1 << 30}))
+    return 0
+
+
+def _pmc_rows(d: str, counter: str):
+    """(kernel name, value) per dispatch from the counter_collection CSV files under d."""
+    import csv
+    import glob
+
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def derive_traffic(d: str) -> int:
+    """Writes profiles/traffic.json from four rocprofv3 --pmc runs under d: label_fetch and
+    label_write (the benchmark, FETCH_SIZE and WRITE_SIZE), copy_fetch and copy_write (the
+    calibration copy).  Counter values are KiB per dispatch; each is scaled by the ratio of
+    the copy's known bytes to what the same counter reads for it."""
+    def mean_for(sub, counter, pick):
+        vals = [v for k, v in _pmc_rows(os.path.join(d, sub), counter) if pick(k)]
+        if not vals:
+            raise SystemExit(f"no {counter} rows for the kernel under {os.path.join(d, sub)}")
+        # launches of an iteration graph replayed past the stop exit at once: leave them out
+        vals = [v for v in vals if v >= 0.01 * max(vals)]
+        return sum(vals) / len(vals), len(vals)
+
+    def is_copy(k):
+        return "copy" in k.lower()
+
+    copy_fetch, nf = mean_for("copy_fetch", "FETCH_SIZE", is_copy)
+    copy_write, nw = mean_for("copy_write", "WRITE_SIZE", is_copy)
+    fetch_scale = (1 << 30) / (copy_fetch * 1024.0)
+    write_scale = (1 << 30) / (copy_write * 1024.0)
+    src_hash = kernel_sources_hash()
+    out = {"calibration": {"copy_bytes": 1 << 30, "fetch_kib_per_copy": copy_fetch, "write_kib_per_copy": copy_write,
+                           "fetch_scale": fetch_scale, "write_scale": write_scale, "dispatches": [nf, nw]}}
+    for key, pat in (("label", "k_label_sorted<"), ("row", "k_row<"), ("finish", "k_finish")):
+        f, nfd = mean_for("label_fetch", "FETCH_SIZE", lambda k: pat in k)
+        w, nwd = mean_for("label_write", "WRITE_SIZE", lambda k: pat in k)
+        out[key] = {"source_hash": src_hash, "fetch_kib_raw": f, "write_kib_raw": w,
+                    "bytes_per_launch": int(round(f * 1024.0 * fetch_scale + w * 1024.0 * write_scale)),
+                    "fetch_bytes": int(round(f * 1024.0 * fetch_scale)),
+                    "write_bytes": int(round(w * 1024.0 * write_scale)), "dispatches": [nfd, nwd]}
+    with open(os.path.join(PROFILES, "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+    return 0
+
+
 def cpu_baseline(prob, iters: int) -> dict:
     from oracle import oracle as O
 
@@ -235,7 +316,13 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="graphs in the batch measurement (0: skip)")
     ap.add_argument("--serve", type=int, default=160, help="requests under load in the serving measurement (0: skip)")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run only the 1 GiB calibration copies")
+    ap.add_argument("--derive-traffic", metavar="DIR", help="write profiles/traffic.json from counter runs in DIR")
     args = ap.parse_args()
+    if args.derive_traffic:
+        return derive_traffic(args.derive_traffic)
+    if args.calibrate_copy:
+        return calibrate_copy()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design, "
               "not part of this build.", file=sys.stderr)
@@ -313,6 +400,9 @@ def main() -> int:
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb, "kernel": "k_label (L_s S label pass)",
                 "algorithmic_bytes_per_launch": abytes, "avg_launch_us": round(per[dom]["avg_us"], 2)}
+    copy_gbs = copy_peak_gbs(torch)
+    roofline["achievable_copy_gbs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
     it_bytes = iteration_bytes(g.n, g.nnz, prob.K, 4, 4)
     lab = last["labels"].cpu().numpy()
     acc = float(np.mean(lab == g.truth))
