@@ -226,11 +226,15 @@ static void set_hist(double *h, int64_t stride, int64_t k, double E, double g, d
  * Uhat/omega define the fidelity term.  hist (5 x (max_iter+1), may be NULL)
  * receives per evaluated iterate k: E(U_k), g_k, q_k = <D_k, Hess D_k>, alpha_k,
  * and the number of non-binary rows (NaN where a quantity was not formed).
- * s_hist (max_iter+1 rows of n, may be NULL) receives the oracle's vertex indices.
+ * s_hist (max_iter+1 rows of n, may be NULL) receives the vertex indices used.
+ * s_first (n entries, may be NULL) replaces the (G)LMO's vertices of the first iteration:
+ * the tests use it to follow another implementation's choice among tied minimisers
+ * (the caller checks that the given vertices are minimisers up to its tolerance).
  */
 int orc_solve(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const double *v,
               const double *Uhat, const double *omega, const orc_params_t *prm,
-              double *U, int32_t *labels, orc_stats_t *st, double *hist, int32_t *s_hist)
+              double *U, int32_t *labels, orc_stats_t *st, double *hist, int32_t *s_hist,
+              const int32_t *s_first)
 {
     if (n < 0 || K < 1 || !prm || !U) return -1;
     const int64_t nK = n * K;
@@ -280,6 +284,7 @@ int orc_solve(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const 
 
         /* step 3: S_k from the (G)LMO */
         int64_t nonbin = orc_lmo(n, K, U, G, prm->lmo, s);
+        if (k == 0 && s_first) memcpy(s, s_first, sizeof(int32_t) * (size_t)n);
         if (s_hist) memcpy(s_hist + (int64_t)k * n, s, sizeof(int32_t) * (size_t)n);
 
         /* D_k = S_k - U_k and the gap g_k = -<grad E(U_k), D_k> */

@@ -41,5 +41,6 @@ int orc_gradient_from_P(int64_t n, int32_t K, const double *P, const double *U, 
 int64_t orc_lmo(int64_t n, int32_t K, const double *U, const double *G, int mode, int32_t *s);
 int orc_solve(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const double *v,
               const double *Uhat, const double *omega, const orc_params_t *prm,
-              double *U, int32_t *labels, orc_stats_t *st, double *hist, int32_t *s_hist);
+              double *U, int32_t *labels, orc_stats_t *st, double *hist, int32_t *s_hist,
+              const int32_t *s_first);
 #endif

@@ -68,7 +68,7 @@ def lib():
         L.orc_lmo.restype = C.c_int64
         L.orc_lmo.argtypes = [C.c_int64, C.c_int32, p, p, C.c_int, p]
         L.orc_solve.argtypes = [C.c_int64, C.c_int32, p, p, p, p, p, C.POINTER(_Params), p, p,
-                                C.POINTER(_Stats), p, p]
+                                C.POINTER(_Stats), p, p, p]
         _lib = L
     return _lib
 
@@ -180,7 +180,7 @@ def solve(L: Operator, K: int, labelled_idx, labels, eps: float = 50.0, omega0: 
           max_iter: int = 30, tol: float = 1e-6, ls: int = LS_ARMIJO, delta: float = 0.5,
           gamma: float = 1e-6, lmo_mode: int = LMO_GREEDY, osfw: bool = False,
           lipschitz: float | None = None, armijo_direct: bool = False, U0=None,
-          record_s: bool = False) -> dict:
+          record_s: bool = False, s_first=None) -> dict:
     """Greedy Frank-Wolfe (Alg. 3) with Armijo / exact / short steps; FW (Alg. 2) with
     lmo_mode=LMO_FULL; OSFW (Alg. 4) with osfw=True.  Returns U, labels, stats, history."""
     n = L.n
@@ -198,8 +198,11 @@ def solve(L: Operator, K: int, labelled_idx, labels, eps: float = 50.0, omega0: 
     hist = np.full((5, max_iter + 1), np.nan)
     s_hist = np.zeros((max_iter + 1, n), np.int32) if record_s else None
     lab = np.zeros(n, np.int32)
+    sf = None if s_first is None else _i32(s_first)
+    if sf is not None and sf.shape != (n,):
+        raise ValueError("s_first needs one vertex per node")
     rc = lib().orc_solve(n, K, _p(L.indptr), _p(L.indices), _p(L.data), _p(Uhat), _p(omega), C.byref(prm),
-                         _p(U), _p(lab), C.byref(st), _p(hist), _p(s_hist))
+                         _p(U), _p(lab), C.byref(st), _p(hist), _p(s_hist), _p(sf))
     if rc != 0:
         raise RuntimeError(f"orc_solve failed ({rc})")
     out = dict(U=U, labels=lab, iters=st.iters, stop_reason=st.stop_reason, gap=st.gap,

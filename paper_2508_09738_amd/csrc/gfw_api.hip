@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "gfw_internal.h"
+#include "gfw_kernels_bigk.h"
 
 namespace gfw {
 
@@ -199,12 +200,13 @@ gfw_status_t check_params(const gfw_params_t *p, int32_t K)
 static Shape shape_for(int64_t n, int64_t nnz, int32_t K)
 {
     Shape s;
-    s.kmax = K <= 4 ? 4 : K <= 8 ? 8 : 16;
+    s.kmax = K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : K <= 64 ? 64 : K <= 128 ? 128 : K <= 256 ? 256 : K <= 512 ? 512 : 1024;
     const double avg = (double)nnz / (double)n;
     int l = 1;
     while (l < 32 && l < avg * 0.25) l <<= 1;
     s.lpr = l;
     s.nb_row = (int)cdiv(n, kRowBlock);
+    s.nb_big = K > 16 ? (int)cdiv(n, kBigRowsPerBlock) : 0;
     s.nb_csr = (int)std::min<int64_t>(cdiv(n, kRowBlock / s.lpr), 8192);
     return s;
 }
@@ -359,6 +361,11 @@ static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st, 
         g->label_path = 0;
         return GFW_OK;
     }
+    if (g->K > 16) { // the large-K kernels have one label pass (the sorted one packs K <= 16)
+        if (mode == 2) return fail(GFW_E_UNSUPPORTED, "the column-sorted label pass needs K <= 16");
+        g->label_path = 0;
+        return GFW_OK;
+    }
     const bool big = g->nnz >= ((int64_t)4 << 20);
     if (mode == 0 && !big) { // small graphs keep the plain pass whatever their locality
         g->label_path = 0;
@@ -503,7 +510,7 @@ gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_
     g->shape = shape_for(n, nnz, p->K);
     if ((s = choose_label_path(g, 0, st, p->location == GFW_HOST ? p->col_idx : nullptr)) != GFW_OK) return s;
     g->graph_bytes += 4 * (n + 1) + (4 + vs) * nnz + 4 * n;
-    g->solve_bytes = 3 * vs * n * p->K + 2 * n + sizeof(double) * ((kRowParts + 4) * g->shape.nb_row + 64) +
+    g->solve_bytes = 3 * vs * n * p->K + (p->K > 16 ? 4 : 2) * n + sizeof(double) * ((kRowParts + 4) * g->shape.nb_row + 64) +
                      sizeof(Ctl);
     guard.g = nullptr;
     *out = g;
@@ -525,10 +532,12 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
     if ((s = dalloc(&w.U, vs * nK)) != GFW_OK) return s;
     if ((s = dalloc(&w.P, vs * nK)) != GFW_OK) return s;
     if ((s = dalloc(&w.Q, vs * nK)) != GFW_OK) return s;
-    if ((s = dalloc((void **)&w.s0, g->n)) != GFW_OK) return s;
-    if ((s = dalloc((void **)&w.s1, g->n)) != GFW_OK) return s;
+    const size_t sb = g->K > 16 ? 2 : 1; // vertex bytes: 16-bit for the large-K kernels
+    if ((s = dalloc((void **)&w.s0, sb * g->n)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.s1, sb * g->n)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.s4, (size_t)(g->n + 1) / 2)) != GFW_OK) return s;
-    if ((s = dalloc((void **)&w.row_part, sizeof(double) * kRowParts * g->shape.nb_row)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.row_part, sizeof(double) * kRowParts * std::max(g->shape.nb_row, g->shape.nb_big)))
+        != GFW_OK) return s;
     if ((s = dalloc((void **)&w.lab_part, sizeof(double) * std::max<int64_t>(g->shape.nb_row, g->n_tiles)))
         != GFW_OK) return s;
     if ((s = dalloc((void **)&w.scratch, sizeof(double) * 3 * std::max(g->shape.nb_row, 64))) != GFW_OK) return s;
@@ -551,11 +560,13 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
 template <typename T, int KMAX>
 static void set_lds_limits()
 {
-    // the largest dynamic LDS any launch of these kernels asks for
-    (void)hipFuncSetAttribute((const void *)k_label_sorted<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kSortedMaxEntries);
-    (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              3 * (int)sizeof(T) * kRowBlock * KMAX);
+    if constexpr (KMAX <= 16) { // the large-K kernels use static LDS only
+        // the largest dynamic LDS any launch of these kernels asks for
+        (void)hipFuncSetAttribute((const void *)k_label_sorted<T, uint8_t, KMAX>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kSortedMaxEntries);
+        (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  3 * (int)sizeof(T) * kRowBlock * KMAX);
+    }
 }
 
 static size_t row_lds_bytes(const gfw_graph_s *g) { return 3 * dsize(g->dtype) * kRowBlock * (size_t)g->K; }
@@ -563,18 +574,23 @@ static size_t row_lds_bytes(const gfw_graph_s *g) { return 3 * dsize(g->dtype) *
 template <typename T, int KMAX>
 static void launch_spmm(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
 {
-    k_spmm<T, KMAX><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), U, P);
+    if constexpr (KMAX > 16)
+        k_spmm_big<T, KMAX / 64><<<g->shape.nb_big, kBigThreads, 0, st>>>(make_view<T>(g), U, P);
+    else
+        k_spmm<T, KMAX><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), U, P);
 }
 
 template <typename T, int KMAX>
 static void launch_label(const gfw_graph_s *g, hipStream_t st)
 {
-    if (g->label_path == 1) {
+    if constexpr (KMAX > 16) {
+        k_label_big<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g));
+    } else if (g->label_path == 1) {
         k_label_sorted<T, uint8_t, KMAX><<<g->n_tiles, kSortedThreads, kSortedMaxEntries, st>>>(make_view<T>(g));
-        return;
+    } else {
+        const size_t lds = sizeof(T) * kRowBlock * g->K;
+        k_label<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(make_view<T>(g));
     }
-    const size_t lds = sizeof(T) * kRowBlock * g->K;
-    k_label<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(make_view<T>(g));
 }
 
 template <typename T>
@@ -583,7 +599,12 @@ static void spmm_any(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
     switch (g->shape.kmax) {
     case 4: launch_spmm<T, 4>(g, U, P, st); break;
     case 8: launch_spmm<T, 8>(g, U, P, st); break;
-    default: launch_spmm<T, 16>(g, U, P, st); break;
+    case 16: launch_spmm<T, 16>(g, U, P, st); break;
+    case 64: launch_spmm<T, 64>(g, U, P, st); break;
+    case 128: launch_spmm<T, 128>(g, U, P, st); break;
+    case 256: launch_spmm<T, 256>(g, U, P, st); break;
+    case 512: launch_spmm<T, 512>(g, U, P, st); break;
+    default: launch_spmm<T, 1024>(g, U, P, st); break;
     }
 }
 
@@ -604,7 +625,10 @@ SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm)
 template <typename T, int KMAX>
 static void launch_row(gfw_graph_s *g, int apply_only, hipStream_t st)
 {
-    k_row<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, row_lds_bytes(g), st>>>(make_view<T>(g), apply_only);
+    if constexpr (KMAX > 16)
+        k_row_big<T, KMAX / 64><<<g->shape.nb_big, kBigThreads, 0, st>>>(make_view<T>(g), apply_only);
+    else
+        k_row<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, row_lds_bytes(g), st>>>(make_view<T>(g), apply_only);
 }
 
 // One GFW iteration (row kernel, label pass, finish), optionally bracketed by trace events.
@@ -621,8 +645,9 @@ static void launch_iteration(gfw_graph_s *g, hipStream_t st, bool traced)
     launch_label<T, KMAX>(g, st);
     trace_end(cx, GFW_KERNEL_LABEL, ev, st);
     ev = trace_begin(cx, st);
-    k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, g->shape.nb_row, w.lab_part,
-                                           g->label_path == 1 ? g->n_tiles : g->shape.nb_row, w.ctl);
+    const int nb_rows = KMAX > 16 ? g->shape.nb_big : g->shape.nb_row;
+    const int nb_lab = (KMAX <= 16 && g->label_path == 1) ? g->n_tiles : g->shape.nb_row;
+    k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, nb_rows, w.lab_part, nb_lab, w.ctl);
     trace_end(cx, GFW_KERNEL_FINISH, ev, st);
 }
 
@@ -713,8 +738,11 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     if ((s = trace_flush(cx, st)) != GFW_OK) return s;
     if (U_out) GFW_HIP_TRY(hipMemcpyAsync(U_out, U, sizeof(T) * nK, hipMemcpyDeviceToDevice, st));
     if (labels_out || s_out)
-        k_outputs<T, uint8_t><<<grid_for(g->n, 256), 256, 0, st>>>(g->n, g->K, U, w.s0, w.s1, w.ctl, labels_out,
-                                                                  s_out);
+    {
+        using ST = std::conditional_t<(KMAX > 16), uint16_t, uint8_t>;
+        k_outputs<T, ST><<<grid_for(g->n, 256), 256, 0, st>>>(g->n, g->K, U, (const ST *)w.s0, (const ST *)w.s1,
+                                                             w.ctl, labels_out, s_out);
+    }
     GFW_HIP_TRY(hipGetLastError());
     if (stats || history) {
         Ctl ch;
@@ -742,6 +770,22 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
         }
     }
     return GFW_OK;
+}
+
+template <typename T>
+static gfw_status_t solve_dispatch(gfw_graph_s *g, const gfw_params_t *prm, void *U_out, int32_t *labels_out,
+                                   int32_t *s_out, gfw_stats_t *stats, double *history, hipStream_t st)
+{
+    switch (g->shape.kmax) {
+    case 4: return solve_impl<T, 4>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    case 8: return solve_impl<T, 8>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    case 16: return solve_impl<T, 16>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    case 64: return solve_impl<T, 64>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    case 128: return solve_impl<T, 128>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    case 256: return solve_impl<T, 256>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    case 512: return solve_impl<T, 512>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    default: return solve_impl<T, 1024>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    }
 }
 
 template <typename T>
@@ -892,22 +936,10 @@ gfw_status_t gfw_solve(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm
     if (!ctx || !g) return fail(GFW_E_INVALID_ARG, "ctx or graph is NULL");
     gfw_status_t s = check_params(prm, g->K);
     if (s != GFW_OK) return s;
-    if (g->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by this build");
     GFW_HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    if (g->dtype == GFW_F32) {
-        switch (g->shape.kmax) {
-        case 4: s = solve_impl<float, 4>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
-        case 8: s = solve_impl<float, 8>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
-        default: s = solve_impl<float, 16>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
-        }
-    } else {
-        switch (g->shape.kmax) {
-        case 4: s = solve_impl<double, 4>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
-        case 8: s = solve_impl<double, 8>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
-        default: s = solve_impl<double, 16>(g, prm, U_out, labels_out, s_out, stats, history, st); break;
-        }
-    }
+    s = g->dtype == GFW_F32 ? solve_dispatch<float>(g, prm, U_out, labels_out, s_out, stats, history, st)
+                            : solve_dispatch<double>(g, prm, U_out, labels_out, s_out, stats, history, st);
     if (s != GFW_OK) return s;
     if (stats) {
         double E = 0.0;
@@ -926,7 +958,6 @@ gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t 
     if (!ctx || !g || !U || !E_host) return fail(GFW_E_INVALID_ARG, "NULL argument");
     gfw_status_t s = check_params(prm, g->K);
     if (s != GFW_OK) return s;
-    if (g->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by this build");
     GFW_HIP_TRY(hipSetDevice(ctx->device));
     return g->dtype == GFW_F32 ? objective_impl<float>(g, prm, (const float *)U, E_host, (hipStream_t)stream)
                                : objective_impl<double>(g, prm, (const double *)U, E_host, (hipStream_t)stream);
@@ -961,7 +992,6 @@ gfw_status_t gfw_trace_get(gfw_context_t ctx, int32_t kernel, double *total_ms, 
 gfw_status_t gfw_spmm(gfw_context_t ctx, gfw_graph_t g, const void *U, void *P, void *stream)
 {
     if (!ctx || !g || !U || !P) return fail(GFW_E_INVALID_ARG, "NULL argument");
-    if (g->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by this build");
     GFW_HIP_TRY(hipSetDevice(ctx->device));
     if (g->dtype == GFW_F32) spmm_any<float>(g, (const float *)U, (float *)P, (hipStream_t)stream);
     else spmm_any<double>(g, (const double *)U, (double *)P, (hipStream_t)stream);

@@ -59,10 +59,11 @@ struct Workspace {
 // Launch shape derived from the graph (fixed per graph, so reductions are deterministic
 // for that graph whatever else runs).
 struct Shape {
-    int kmax = 4;       // register bucket for K
+    int kmax = 4;       // register bucket for K: 4, 8, 16, or 64..1024 for the large-K kernels
     int lpr = 8;        // lanes per row of the CSR kernels
-    int nb_row = 1;     // blocks of the row kernel
+    int nb_row = 1;     // 256-row blocks (row kernel, label passes, SpMM, set-up)
     int nb_csr = 1;     // blocks of the CSR kernels
+    int nb_big = 0;     // blocks of the large-K row kernel and SpMM (0 when K <= 16)
 };
 
 } // namespace gfw
@@ -152,6 +153,7 @@ GraphView<T> make_view(const gfw_graph_s *g)
     v.row_part = w.row_part;
     v.lab_part = w.lab_part;
     v.nb_row = g->shape.nb_row;
+    v.nb_big = g->shape.nb_big;
     v.n_tiles = g->label_path == 1 ? g->n_tiles : 0;
     v.tile_rows = g->tile_rows;
     v.gcol = g->gcol;

@@ -245,6 +245,7 @@ struct GraphView {
     Ctl *ctl;
     double *row_part, *lab_part;
     int32_t nb_row;   // 256-row tiles (row kernel, plain label pass, SpMM)
+    int32_t nb_big;   // blocks of the large-K row kernel (stride of its partials)
     int32_t n_tiles;  // tiles of the column-sorted label pass (0: plain pass)
     const int32_t *tile_rows, *gcol;
     const uint16_t *gpos;

@@ -1,0 +1,311 @@
+// ---------------------------------------------------------------------------------
+// Kernels for many classes (16 < K <= 1024), the regime of the paper's LFR networks
+// (Section 5.2: hundreds of communities, average degree about 5).
+//
+// With K this large a row of U, P or Q is K wide and no longer fits one thread's
+// registers, while the CSR row is short.  The iteration keeps the structure of the
+// small-K path (row kernel, label pass, finish) with three changes:
+//  * a wavefront owns a row: lane l holds classes l, l + 64, l + 128, ... (MC per lane),
+//    so every row of U and P is read and written with coalesced accesses, and the
+//    GLMO's lowest-index argmin and the per-row sums are wavefront reductions;
+//  * Q = L_s S is never stored: S is one-hot, so the row (L_s S_{k-1})_i has at most
+//    deg_i + 1 non-zeros, and the row kernel of iteration k rebuilds it from the row's
+//    neighbours and their vertices s_{k-1} just before the update
+//    P_k = (1 - a) P_{k-1} + a Q_{k-1}.  That saves writing and reading an n x K array;
+//  * the label pass only forms the per-row term Q_{i,s_i} of <S, L_s S> (the sum of the
+//    row's values over neighbours that share its vertex, plus the diagonal), which does
+//    not depend on K.
+// Vertices are 16-bit (K up to 1024).  Every sum over a row runs in a fixed order, so
+// the results are deterministic; the sums over a row's classes are wavefront trees and
+// differ from a sequential sum by rounding only.
+// ---------------------------------------------------------------------------------
+#pragma once
+
+#include "gfw_kernels.h"
+
+#include <limits.h>
+
+namespace gfw {
+
+constexpr int kBigThreads = 256;                             // 4 wavefronts per block
+constexpr int kBigRowsPerWave = 4;                           // rows a wavefront takes in turn
+constexpr int kBigRowsPerBlock = kBigRowsPerWave * (kBigThreads / 64);
+
+__device__ __forceinline__ int wave_min_int(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Lowest-index minimum over the wavefront of (value, index) pairs; index INT_MAX marks a
+// lane without a candidate.  The pairs are totally ordered, so every lane ends with the
+// same result.
+__device__ __forceinline__ void wave_argmin(double &v, int &idx)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
+        const bool take = oi != INT_MAX && (idx == INT_MAX || ov < v || (ov == v && oi < idx));
+        if (take) {
+            v = ov;
+            idx = oi;
+        }
+    }
+}
+
+// Row kernel for large K: pending update (with the Q row rebuilt from s_{k-1}), gradient,
+// GLMO, per-row partials.  Block `tile` owns rows [tile * kBigRowsPerBlock, +kBigRowsPerBlock);
+// partials are stored transposed with stride nb_big: row_part[j * nb_big + tile].
+template <typename T, int MC>
+__device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int tile, const int apply_only)
+{
+    const int64_t n = gv.n;
+    const int32_t K = gv.K;
+    const Ctl *__restrict__ ctl = gv.ctl;
+    const int32_t active = apply_only ? 0 : ctl->active, pending = ctl->pending;
+    if (!active && !pending) return;
+    const uint16_t *__restrict__ s_prev = reinterpret_cast<const uint16_t *>((ctl->last_eval & 1) ? gv.s1 : gv.s0);
+    uint16_t *__restrict__ s_cur = reinterpret_cast<uint16_t *>((ctl->k & 1) ? gv.s1 : gv.s0);
+    const int32_t *__restrict__ rp = gv.rp;
+    const int32_t *__restrict__ ci = gv.ci;
+    const T *__restrict__ a = gv.a;
+    const double alpha = ctl->alpha;
+    const SolveParams sp = ctl->sp;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double wacc[kRowParts];
+#pragma unroll
+    for (int j = 0; j < kRowParts; ++j) wacc[j] = 0.0;
+    const int64_t rbase = (int64_t)tile * kBigRowsPerBlock + (int64_t)wid * kBigRowsPerWave;
+    for (int t = 0; t < kBigRowsPerWave; ++t) {
+        const int64_t i = rbase + t;
+        if (i >= n) break; // uniform across the wavefront
+        T *__restrict__ Ui = gv.U + i * K;
+        T *__restrict__ Pi = gv.P + i * K;
+        double u[MC], p[MC];
+#pragma unroll
+        for (int m = 0; m < MC; ++m) {
+            const int c = lane + 64 * m;
+            u[m] = c < K ? (double)Ui[c] : 0.0;
+            p[m] = c < K ? (double)Pi[c] : 0.0;
+        }
+        bool bl = true;
+#pragma unroll
+        for (int m = 0; m < MC; ++m)
+            if (lane + 64 * m < K && !(u[m] == 0.0 || u[m] == 1.0)) bl = false;
+        bool binary = __all(bl);
+        if (pending) {
+            const int32_t spi = (int32_t)s_prev[i];
+            // Q_{k-1} row i: values of the row summed per neighbour vertex, in CSR order
+            T q[MC];
+#pragma unroll
+            for (int m = 0; m < MC; ++m) q[m] = (T)0;
+            const int32_t e0 = rp[i], e1 = rp[i + 1];
+            for (int32_t e = e0; e < e1; ++e) {
+                const int32_t sj = (int32_t)s_prev[ci[e]];
+                const T v = a[e];
+                if ((sj & 63) == lane) {
+#pragma unroll
+                    for (int m = 0; m < MC; ++m)
+                        if (m == (sj >> 6)) q[m] += v;
+                }
+            }
+            if (gv.diag_one && (spi & 63) == lane) {
+#pragma unroll
+                for (int m = 0; m < MC; ++m)
+                    if (m == (spi >> 6)) q[m] += (T)1;
+            }
+            const double om = 1.0 - alpha;
+#pragma unroll
+            for (int m = 0; m < MC; ++m) {
+                const int c = lane + 64 * m;
+                if (c < K) {
+                    p[m] = (double)(T)(om * p[m] + alpha * (double)q[m]);
+                    Pi[c] = (T)p[m];
+                }
+            }
+            // a row whose direction e_{s_i} - u_i is zero (binary, kept by the GLMO) stays as it is
+            double us = 0.0;
+#pragma unroll
+            for (int m = 0; m < MC; ++m)
+                if (m == (spi >> 6)) us = u[m];
+            const double at_s = __shfl(us, spi & 63, 64);
+            if (!(binary && at_s == 1.0)) {
+                bl = true;
+#pragma unroll
+                for (int m = 0; m < MC; ++m) {
+                    const int c = lane + 64 * m;
+                    if (c < K) {
+                        u[m] = (double)(T)(om * u[m] + (c == spi ? alpha : 0.0));
+                        Ui[c] = (T)u[m];
+                        if (!(u[m] == 0.0 || u[m] == 1.0)) bl = false;
+                    }
+                }
+                binary = __all(bl);
+            }
+        }
+        if (active) {
+            const int32_t y = gv.lab[i];
+            const double om_i = y >= 0 ? sp.omega0 : 0.0;
+            double g[MC];
+#pragma unroll
+            for (int m = 0; m < MC; ++m) {
+                const int c = lane + 64 * m;
+                if (c < K) {
+                    const double uhat = (c == y) ? 1.0 : 0.0;
+                    const double fid = om_i != 0.0 ? om_i * (uhat - u[m]) : 0.0;
+                    g[m] = p[m] + sp.inv_eps * (1.0 - 2.0 * u[m]) - fid;
+                } else {
+                    g[m] = 0.0;
+                }
+            }
+            int32_t s;
+            if (binary && sp.lmo == 0) {
+                // the GLMO keeps a binary row: its vertex is the position of its 1
+                int cand = INT_MAX;
+#pragma unroll
+                for (int m = 0; m < MC; ++m) {
+                    const int c = lane + 64 * m;
+                    if (c < K && u[m] == 1.0) cand = min(cand, c);
+                }
+                cand = wave_min_int(cand);
+                s = cand == INT_MAX ? 0 : cand;
+            } else {
+                double best = 0.0;
+                int bi = INT_MAX;
+#pragma unroll
+                for (int m = 0; m < MC; ++m) {
+                    const int c = lane + 64 * m;
+                    if (c < K && (sp.lmo == 1 || u[m] != 0.0)) {
+                        if (bi == INT_MAX || g[m] < best) {
+                            best = g[m];
+                            bi = c;
+                        }
+                    }
+                }
+                wave_argmin(best, bi);
+                s = bi == INT_MAX ? 0 : bi;
+            }
+            if (lane == 0) s_cur[i] = (uint16_t)s;
+            double gap = 0.0, up = 0.0, dd = 0.0, pen = 0.0, fid = 0.0, ps = 0.0;
+#pragma unroll
+            for (int m = 0; m < MC; ++m) {
+                const int c = lane + 64 * m;
+                if (c < K) {
+                    const double d = (c == s ? 1.0 : 0.0) - u[m];
+                    gap -= g[m] * d;
+                    up += u[m] * p[m];
+                    dd += d * d;
+                    pen += u[m] * (1.0 - u[m]);
+                    if (c == s) ps = p[m];
+                    if (om_i != 0.0) {
+                        const double e = (y == c ? 1.0 : 0.0) - u[m];
+                        fid += e * e;
+                    }
+                }
+            }
+            gap = wave_sum(gap);
+            up = wave_sum(up);
+            dd = wave_sum(dd);
+            pen = wave_sum(pen);
+            fid = wave_sum(fid);
+            ps = wave_sum(ps);
+            wacc[PART_GAP] += gap;
+            wacc[PART_E] += 0.5 * up + sp.inv_eps * pen + 0.5 * (om_i * fid);
+            wacc[PART_CURV] += up - 2.0 * ps - 2.0 * sp.inv_eps * dd + om_i * dd;
+            wacc[PART_DD] += dd;
+            wacc[PART_NB] += binary ? 0.0 : 1.0;
+        }
+    }
+    if (!active) return; // uniform across the block
+    __shared__ double red[kBigThreads / 64][kRowParts];
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < kRowParts; ++j) red[wid][j] = wacc[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < kRowParts) {
+        double s = 0.0;
+        for (int w = 0; w < kBigThreads / 64; ++w) s += red[w][threadIdx.x];
+        gv.row_part[(int64_t)threadIdx.x * gv.nb_big + tile] = s;
+    }
+}
+
+// Label pass for large K: only the per-row term Q_{i,s_i} = sum of the row's values over
+// neighbours with vertex s_i (CSR order) + the diagonal, one thread per row, 256-row
+// blocks; partial lab_part[tile].
+template <typename T>
+__device__ __forceinline__ void label_big_body(const GraphView<T> &gv, const int tile)
+{
+    const Ctl *__restrict__ ctl = gv.ctl;
+    if (!ctl->active) return;
+    const uint16_t *__restrict__ s = reinterpret_cast<const uint16_t *>((ctl->k & 1) ? gv.s1 : gv.s0);
+    const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x;
+    double own = 0.0;
+    if (i < gv.n) {
+        const int32_t si = (int32_t)s[i];
+        T acc = (T)0;
+        const int32_t e0 = gv.rp[i], e1 = gv.rp[i + 1];
+        for (int32_t e = e0; e < e1; ++e)
+            if ((int32_t)s[gv.ci[e]] == si) acc += gv.a[e];
+        own = (double)(acc + (gv.diag_one ? (T)1 : (T)0));
+    }
+    double v[1] = {own};
+    block_sum_store_strided<1>(v, gv.lab_part + tile, gv.nb_row);
+}
+
+// P = L_s U for large K: a wavefront per row, each lane accumulates its classes over the
+// row's entries in CSR order in FP64 (the same arithmetic as spmm_body).
+template <typename T, int MC>
+__device__ __forceinline__ void spmm_big_body(const GraphView<T> &gv, const T *__restrict__ Uin, T *__restrict__ Pout,
+                                              const int tile)
+{
+    const int32_t K = gv.K;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t rbase = (int64_t)tile * kBigRowsPerBlock + (int64_t)wid * kBigRowsPerWave;
+    for (int t = 0; t < kBigRowsPerWave; ++t) {
+        const int64_t i = rbase + t;
+        if (i >= gv.n) break;
+        double acc[MC];
+#pragma unroll
+        for (int m = 0; m < MC; ++m) acc[m] = 0.0;
+        const int32_t e0 = gv.rp[i], e1 = gv.rp[i + 1];
+        for (int32_t e = e0; e < e1; ++e) {
+            const T *__restrict__ uj = Uin + (int64_t)gv.ci[e] * K;
+            const double v = (double)gv.a[e];
+#pragma unroll
+            for (int m = 0; m < MC; ++m) {
+                const int c = lane + 64 * m;
+                if (c < K) acc[m] += v * (double)uj[c];
+            }
+        }
+        const T *__restrict__ ui = Uin + i * K;
+#pragma unroll
+        for (int m = 0; m < MC; ++m) {
+            const int c = lane + 64 * m;
+            if (c < K) Pout[i * K + c] = (T)(gv.diag_one ? (double)ui[c] + acc[m] : acc[m]);
+        }
+    }
+}
+
+template <typename T, int MC>
+static __global__ void __launch_bounds__(kBigThreads) k_row_big(GraphView<T> gv, int apply_only)
+{
+    row_big_body<T, MC>(gv, blockIdx.x, apply_only);
+}
+
+template <typename T>
+static __global__ void __launch_bounds__(kRowBlock) k_label_big(GraphView<T> gv)
+{
+    label_big_body<T>(gv, blockIdx.x);
+}
+
+template <typename T, int MC>
+static __global__ void __launch_bounds__(kBigThreads) k_spmm_big(GraphView<T> gv, const T *__restrict__ Uin,
+                                                                 T *__restrict__ Pout)
+{
+    spmm_big_body<T, MC>(gv, Uin, Pout, blockIdx.x);
+}
+
+} // namespace gfw

@@ -105,3 +105,13 @@ def serve_pool(seed: int, sides=(128, 256, 512, 1024), Ks=(3, 4, 6)) -> list:
     and K uniformly and independently, as the serving mix asks."""
     return [serve_request(seed, j * len(sides) + i, side=sd, K=k)
             for j, k in enumerate(Ks) for i, sd in enumerate(sides)]
+
+
+def lfr_many_classes(seed: int = 5, n: int = 100_000, K: int = 585, avg_degree: float = 5.0, mu: float = 0.2,
+                     frac: float = 0.05, dtype: str = "f32", max_iter: int = 300) -> Problem:
+    """The many-classes workload: an LFR-shaped network (power-law degrees of mean about 5,
+    power-law community sizes, 20% of edge ends outside the community), K communities,
+    `frac` of each community labelled, eps = 50, omega0 = 1000."""
+    g = graphs.lfr_like(n, K, avg_degree, mu, seed)
+    idx, lab = graphs.stratified_labels(g.truth, K, frac, seed)
+    return Problem(g, idx, lab, K, dtype, 50.0, 1000.0, max_iter, 1e-6, f"lfr_many_classes(n={n},K={K})")

@@ -139,6 +139,60 @@ def sbm_by_degree(n: int, K: int, avg_degree: float, ratio: float, seed: int) ->
     return sbm(sizes, min(p_in, 1.0), min(p_out, 1.0), seed)
 
 
+def lfr_like(n: int, K: int, avg_degree: float, mu: float, seed: int, tau1: float = 2.5, tau2: float = 1.5,
+             max_degree: int = 50) -> Graph:
+    """A graph with the shape of an LFR benchmark network: power-law degrees (exponent tau1,
+    mean about `avg_degree`, at most `max_degree`), K communities of power-law sizes (exponent
+    tau2, at least 3 nodes), and a fraction `mu` of each node's edge ends placed outside its
+    community.  Edge ends are paired at random (inside the community, or over all outside
+    ends), self-pairs and duplicates are dropped, weights are 1, nodes are randomly ordered."""
+    rg = rng_for(seed, 11)
+    if K * 3 > n:
+        raise ValueError("need at least 3 nodes per community")
+    # community sizes: power law truncated to [n/(4K), 8n/K], rescaled to sum to n
+    lo, hi = max(3.0, n / (4.0 * K)), min(float(n), 8.0 * n / K)
+    e = 1.0 - tau2
+    x = rg.random(K)
+    raw = (lo ** e + x * (hi ** e - lo ** e)) ** (1.0 / e)
+    sizes = np.maximum(3, np.floor(raw / raw.sum() * n).astype(np.int64))
+    while sizes.sum() > n:
+        sizes[np.argmax(sizes)] -= 1
+    sizes[np.argmin(sizes)] += n - sizes.sum()
+    truth = np.repeat(np.arange(K, dtype=np.int32), sizes)
+    # degrees: power law, clipped to [1, max_degree]; the scale is set so that the clipped
+    # mean is avg_degree
+    y = (1.0 - rg.random(n)) ** (-1.0 / (tau1 - 1.0))
+    xmin = avg_degree * (tau1 - 2.0) / (tau1 - 1.0)
+    for _ in range(4):
+        d = np.clip(np.floor(xmin * y + 0.5), 1, max_degree)
+        xmin *= avg_degree / d.mean()
+    deg = np.clip(np.floor(xmin * y + 0.5), 1, max_degree).astype(np.int64)
+    n_out = rg.binomial(deg, mu)
+    n_in = deg - n_out
+    A, B = [], []
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    for c in range(K):
+        nodes = np.arange(starts[c], starts[c + 1])
+        ends = np.repeat(nodes, n_in[nodes])
+        rg.shuffle(ends)
+        m = ends.shape[0] // 2
+        A.append(ends[:m])
+        B.append(ends[m:2 * m])
+    ends = np.repeat(np.arange(n), n_out)
+    rg.shuffle(ends)
+    m = ends.shape[0] // 2
+    A.append(ends[:m])
+    B.append(ends[m:2 * m])
+    a, b = _dedup_pairs(n, np.concatenate(A), np.concatenate(B))
+    perm = rng_for(seed, 12).permutation(n).astype(np.int64)
+    a, b = perm[a], perm[b]
+    t2 = np.empty_like(truth)
+    t2[perm] = truth
+    indptr, indices, data = _csr_from_edges(n, a, b, np.ones(a.shape[0]))
+    return Graph(n=n, K=K, indptr=indptr, indices=indices, data=data, truth=t2,
+                 name=f"lfr_like(n={n},K={K},mu={mu})")
+
+
 def gaussian_mixture_knn(n: int, d: int, K: int, k: int, seed: int, center_scale: float = 2.0,
                          sigma: float = 1.0, device: str = "cpu") -> Graph:
     """k-NN graph of an isotropic Gaussian mixture.

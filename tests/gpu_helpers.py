@@ -6,6 +6,7 @@ import math
 import sys
 
 import numpy as np
+import pytest
 
 from oracle import oracle as O
 from paper_2508_09738_amd import gfw
@@ -101,3 +102,67 @@ def oracle_order_spread(prob, seeds=(0, 1, 2)):
         r = O.solve_problem(p2)
         worst = max(worst, abs(r["objective"] - r0["objective"]) / abs(r0["objective"]))
     return r0, worst
+
+
+def np_of(t):
+    return t.detach().cpu().numpy()
+
+
+def lockstep(prob, dtype, ks, lmo=O.LMO_GREEDY, ls=O.LS_ARMIJO, u_tol=None, label=""):
+    L = O.operator_for(prob.graph)
+    G = gpu_graph(prob.graph, prob.K, prob.labelled_idx, prob.labels, dtype)
+    Uhat, omega = O.fidelity(prob.n, prob.K, prob.labelled_idx, prob.labels, prob.omega0)
+    u_tol = u_tol if u_tol is not None else (1e-12 if dtype == gfw.F64 else 1e-5)
+    # FP64 objectives: a sequential sum of the n*K per-entry terms (the oracle's) may be off by
+    # up to (n*K) * 2^-53 relative to the exact sum, so the tolerance is at least that bound
+    e_rel = 1e-6 if dtype == gfw.F32 else max(1e-12, prob.n * prob.K * 2.0 ** -53)
+    excluded_rows = 0
+    excluded_iters = 0
+    for k in ks:
+        say(f"[gpu] lockstep {label} dtype={dtype} k={k}")
+        if k == 0:
+            Uk = Uhat.copy()
+        else:
+            Uk = O.solve(L, prob.K, prob.labelled_idx, prob.labels, eps=prob.eps, omega0=prob.omega0, max_iter=k,
+                         tol=-1.0, lmo_mode=lmo, ls=ls)["U"]
+        Ut = torch_u(Uk, dtype)
+        Uk_in = np_of(Ut).astype(np.float64)  # what the GPU starts from
+        ro = O.solve(L, prob.K, prob.labelled_idx, prob.labels, eps=prob.eps, omega0=prob.omega0, max_iter=1,
+                     tol=-1.0, lmo_mode=lmo, ls=ls, U0=Uk_in, record_s=True)
+        rg = gfw.solve(ctx(), G, gfw.params(eps=prob.eps, omega0=prob.omega0, max_iter=1, tol=-1.0, lmo=lmo, ls=ls,
+                                            U0=Ut), want_s=True, want_history=True)
+        # objective and gap of U_k
+        assert rg["E"][0] == pytest.approx(ro["E"][0], rel=e_rel)
+        assert rg["g"][0] == pytest.approx(ro["g"][0], rel=1e-5 if dtype == gfw.F32 else 1e-10, abs=1e-9)
+        # GLMO vertices: exact outside near-ties; inside, the GPU's choice must be near-optimal
+        Gk = O.gradient(L, Uk_in, Uhat, omega, prob.eps)
+        margin = glmo_margin(Uk_in, Gk, lmo)
+        scale = np.abs(Gk).max(axis=1)
+        near = margin <= 1e-5 * np.maximum(scale, 1e-300)
+        s_g, s_o = np_of(rg["s"]), ro["s"][0]
+        assert np.all(s_g[~near] == s_o[~near]), f"GLMO mismatch outside near-ties at k={k}"
+        diff = np.flatnonzero(s_g != s_o)
+        for i in diff:
+            assert Gk[i, s_g[i]] - Gk[i, s_o[i]] <= 1e-5 * max(scale[i], 1e-300)
+        excluded_rows += int(diff.size)
+        if diff.size:
+            # the GPU chose other minimisers on near-tie rows: the oracle's iteration with the
+            # GPU's vertices is the reference for the rest of the step
+            ro = O.solve(L, prob.K, prob.labelled_idx, prob.labels, eps=prob.eps, omega0=prob.omega0, max_iter=1,
+                         tol=-1.0, lmo_mode=lmo, ls=ls, U0=Uk_in, record_s=True, s_first=s_g)
+            assert rg["g"][0] == pytest.approx(ro["g"][0], rel=1e-5 if dtype == gfw.F32 else 1e-10, abs=1e-9)
+        # step size (exclude Armijo bounds sitting on a power of two)
+        if not armijo_ratio_near_power(ro["g"][0], ro["q"][0]):
+            assert rg["q"][0] == pytest.approx(ro["q"][0], rel=1e-5 if dtype == gfw.F32 else 1e-9)
+            if ls == O.LS_ARMIJO:
+                assert rg["alpha"][0] == ro["alpha"][0]  # a power of delta: exact
+            else:
+                assert rg["alpha"][0] == pytest.approx(ro["alpha"][0], rel=1e-5 if dtype == gfw.F32 else 1e-9)
+            Ug = np_of(rg["U"]).astype(np.float64)
+            assert np.abs(Ug - ro["U"]).max() <= u_tol
+            Eg = rg["objective"]
+            assert Eg == pytest.approx(ro["objective"], rel=e_rel)
+        else:
+            excluded_iters += 1
+    say(f"[gpu] lockstep {label}: near-tie rows differing {excluded_rows}, iterations excluded {excluded_iters}")
+    assert excluded_iters <= len(ks) // 2

@@ -169,3 +169,31 @@ def test_context_without_gpu_reports_hip_error():
     h = C.c_void_p()
     rc = gfw.lib().gfw_context_create(C.byref(h), 0)
     assert rc == -5 and not h.value
+
+
+def test_k_bounds_of_the_many_classes_path():
+    # 16 < K <= 1024 runs on the wavefront-per-row kernels; beyond that the problem is rejected
+    assert _check(K=17) == gfw.GFW_OK
+    assert _check(K=1024) == gfw.GFW_OK
+    assert _check(K=1025) == -6
+
+
+def test_lfr_like_generator_shape():
+    """The many-classes input: a symmetric, sorted, duplicate-free CSR without self-loops,
+    mean degree near 5, community sizes within the truncation, about 1 - mu of the edges
+    inside communities, every community present."""
+    n, K, mu = 20000, 300, 0.2
+    g = graphs.lfr_like(n, K, 5.0, mu, 3)
+    ip, ix = g.indptr, g.indices
+    rows = np.repeat(np.arange(n), np.diff(ip))
+    assert np.all(rows != ix)
+    assert all(np.all(np.diff(ix[ip[i]:ip[i + 1]]) > 0) for i in range(0, n, 97))
+    import scipy.sparse as sp
+    W = sp.csr_matrix((g.data, ix, ip), shape=(n, n))
+    assert (W != W.T).nnz == 0
+    deg = np.diff(ip)
+    assert 4.2 <= deg.mean() <= 5.2 and deg.max() <= 50
+    sizes = np.bincount(g.truth, minlength=K)
+    assert sizes.min() >= 3 and sizes.max() <= 8 * n / K + 1 and sizes.sum() == n
+    inside = np.mean(g.truth[rows] == g.truth[ix])
+    assert 1 - mu - 0.1 <= inside <= 1 - mu + 0.1

@@ -1,0 +1,129 @@
+"""The many-classes path (16 < K <= 1024): wavefront-per-row kernels, Q rows rebuilt from the
+neighbours' vertices, 16-bit vertices.  Inputs are LFR-shaped networks (power-law degrees of
+mean about 5, power-law community sizes), the regime of the paper's LFR experiments.
+
+SpMM against the oracle's CSR loop; lockstep iterations (the per-iteration contract) with
+the GFW, full-LMO and exact-step variants; a free-running FP64 solve; the objective; the
+limits of the path (K = 17 and K = 1024, isolated nodes, no label pass choice, no batching)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_09738_amd import gfw
+from synth import configs, graphs
+
+from gpu_helpers import ctx, gpu_graph, lockstep, np_of, relabelled, say, torch_u
+
+pytestmark = pytest.mark.gpu
+
+
+def _simplex_rows(n, K, seed, sparse_frac=0.3):
+    """Random rows on the unit simplex, some with zeros (shrunk supports) and some binary."""
+    rg = np.random.default_rng(seed)
+    U = rg.random((n, K)) ** 3
+    U[rg.random((n, K)) < sparse_frac] = 0.0
+    U[np.arange(n), rg.integers(0, K, n)] += 1e-3
+    U /= U.sum(axis=1, keepdims=True)
+    binary = rg.random(n) < 0.2
+    U[binary] = 0.0
+    U[binary, rg.integers(0, K, int(binary.sum()))] = 1.0
+    return U
+
+
+@pytest.mark.parametrize("dtype", [gfw.F32, gfw.F64])
+@pytest.mark.parametrize("K", [17, 64, 65, 200, 300, 585, 1024])
+def test_spmm_large_k(dtype, K):
+    say(f"[gpu] large-K spmm K={K} dtype={dtype}")
+    n = max(3 * K, 2000)
+    g = graphs.lfr_like(n, K, 5.0, 0.2, 100 + K)
+    G = gpu_graph(g, K, [0], [0], dtype)
+    U = _simplex_rows(n, K, K)
+    Ut = torch_u(U, dtype)
+    P = np_of(gfw.spmm(ctx(), G, Ut)).astype(np.float64)
+    ref = O.spmm(O.operator_for(g), np_of(Ut).astype(np.float64))
+    if dtype == gfw.F64:
+        np.testing.assert_allclose(P, ref, rtol=1e-12, atol=1e-14)
+    else:
+        np.testing.assert_allclose(P, ref, rtol=0, atol=2e-6)
+
+
+@pytest.mark.parametrize("dtype", [gfw.F64, gfw.F32])
+@pytest.mark.parametrize("K", [40, 300])
+def test_lockstep_large_k(dtype, K):
+    prob = configs.lfr_many_classes(seed=K, n=max(3000, 12 * K), K=K, frac=0.05, max_iter=60)
+    lockstep(prob, dtype, [0, 1, 5, 30], label=f"lfr K={K}")
+
+
+def test_lockstep_large_k_variants_f64():
+    prob = configs.lfr_many_classes(seed=7, n=2000, K=70, frac=0.05, max_iter=30)
+    lockstep(prob, gfw.F64, [0, 3, 12], lmo=O.LMO_FULL, label="full-lmo K=70")
+    lockstep(prob, gfw.F64, [0, 3, 12], ls=O.LS_EXACT, label="exact-ls K=70")
+
+
+def test_free_running_large_k_f64():
+    """Free-running FP64 solve with 120 classes.  With many classes the GLMO meets exact ties
+    often, and rounding decides them: the oracle itself, run on the same network with its
+    nodes renumbered, follows another trajectory after a few dozen iterations.  The GPU is
+    held to that spread (labels and objective), measured here on six renumberings."""
+    say("[gpu] free-running large K f64")
+    prob = configs.lfr_many_classes(seed=3, n=2500, K=120, frac=0.05, dtype="f64", max_iter=200)
+    ro = O.solve_problem(prob)
+    agree_o, dE_o = [], []
+    for seed in range(6):
+        p2, perm = relabelled(prob, seed)
+        r2 = O.solve_problem(p2)
+        agree_o.append(np.mean(r2["labels"][perm] == ro["labels"]))
+        dE_o.append(abs(r2["objective"] - ro["objective"]) / abs(ro["objective"]))
+    G = gpu_graph(prob.graph, prob.K, prob.labelled_idx, prob.labels, gfw.F64)
+    rg = gfw.solve(ctx(), G, gfw.params(eps=prob.eps, omega0=prob.omega0, max_iter=prob.max_iter, tol=prob.tol),
+                   want_history=True)
+    agree = np.mean(np_of(rg["labels"]) == ro["labels"])
+    dE = abs(rg["objective"] - ro["objective"]) / abs(ro["objective"])
+    first = np.flatnonzero(rg["alpha"][:ro["iters"]] != ro["alpha"][:ro["iters"]])
+    say(f"[gpu] lfr K=120 f64: iters {rg['iters']}/{ro['iters']}, label agreement {agree:.5f} "
+        f"(oracle renumbered: {min(agree_o):.5f}..{max(agree_o):.5f}), rel dE {dE:.3e} "
+        f"(oracle renumbered: up to {max(dE_o):.3e}), first alpha divergence {first[:1]}")
+    assert rg["iters"] == ro["iters"]
+    assert agree >= min(0.999, min(agree_o) - 0.005)
+    assert dE <= max(1e-6, 1.5 * max(dE_o))
+
+
+@pytest.mark.parametrize("dtype", [gfw.F32, gfw.F64])
+def test_objective_large_k(dtype):
+    say(f"[gpu] large-K objective dtype={dtype}")
+    prob = configs.lfr_many_classes(seed=9, n=3000, K=150, frac=0.05)
+    G = gpu_graph(prob.graph, prob.K, prob.labelled_idx, prob.labels, dtype)
+    U = _simplex_rows(prob.n, prob.K, 5)
+    Ut = torch_u(U, dtype)
+    prm = gfw.params(eps=prob.eps, omega0=prob.omega0)
+    Eg = gfw.objective(ctx(), G, prm, Ut)
+    Uhat, omega = O.fidelity(prob.n, prob.K, prob.labelled_idx, prob.labels, prob.omega0)
+    Eo = O.objective(O.operator_for(prob.graph), np_of(Ut).astype(np.float64), Uhat, omega, prob.eps)
+    # FP64: the oracle's sequential sum over n*K terms carries up to n*K*2^-53 relative rounding
+    assert Eg == pytest.approx(Eo, rel=1e-6 if dtype == gfw.F32 else max(1e-12, prob.n * prob.K * 2.0 ** -53))
+
+
+def test_large_k_limits():
+    say("[gpu] large-K limits")
+    # K = 1024 on a small graph with isolated nodes: runs, rows stay on the simplex
+    g = graphs.lfr_like(3100, 1024, 5.0, 0.2, 4)
+    idx, lab = graphs.stratified_labels(g.truth, 1024, 0.05, 4)
+    G = gpu_graph(g, 1024, idx, lab, gfw.F32)
+    r = gfw.solve(ctx(), G, gfw.params(max_iter=20, tol=-1))
+    U = np_of(r["U"]).astype(np.float64)
+    assert np.all(U >= 0) and np.allclose(U.sum(axis=1), 1.0, atol=1e-5)
+    assert np.all(U[idx, lab] == 1.0)
+    lb = np_of(r["labels"])
+    assert lb.min() >= 0 and lb.max() < 1024
+    # max_iter = 0 returns U_0
+    r0 = gfw.solve(ctx(), G, gfw.params(max_iter=0))
+    assert r0["iters"] == 0
+    # K = 17 (one class per lane, most lanes idle) in lockstep with the oracle
+    prob = configs.lfr_many_classes(seed=17, n=1500, K=17, frac=0.05, max_iter=10)
+    lockstep(prob, gfw.F64, [0, 4], label="K=17")
+    # the column-sorted label pass packs K <= 16; batching is limited to K <= 16
+    with pytest.raises(gfw.GfwError):
+        G.tune(gfw.TUNE_LABEL_PATH, 2)
+    assert G.query(gfw.TUNE_LABEL_PATH) == 1
+    with pytest.raises(gfw.GfwError):
+        gfw.solve_batched(ctx(), [G], gfw.params(max_iter=5))

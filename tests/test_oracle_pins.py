@@ -512,3 +512,26 @@ def test_sbm_small_recovery():
     r = O.solve(L, prob.K, prob.labelled_idx, prob.labels, max_iter=prob.max_iter, tol=prob.tol)
     acc = np.mean(r["labels"] == prob.graph.truth)
     assert acc >= 0.98
+
+
+def test_first_iteration_vertices_override():
+    """s_first replaces the (G)LMO's vertices of the first iteration and nothing else: with
+    the oracle's own vertices the run is unchanged; with other vertices the update still
+    moves every non-kept row to (1 - a) u_i + a e_{s_i} and records the given vertices."""
+    prob = configs.sbm_small(4, n_per=60)
+    L = O.operator_for(prob.graph)
+    base = O.solve(L, prob.K, prob.labelled_idx, prob.labels, max_iter=3, tol=-1, record_s=True)
+    same = O.solve(L, prob.K, prob.labelled_idx, prob.labels, max_iter=3, tol=-1, record_s=True,
+                   s_first=base["s"][0])
+    np.testing.assert_array_equal(base["U"], same["U"])
+    Uhat, _ = O.fidelity(prob.n, prob.K, prob.labelled_idx, prob.labels, prob.omega0)
+    other = (base["s"][0] + 1) % prob.K
+    lab = np.asarray(prob.labelled_idx)
+    other[lab] = np.asarray(prob.labels)  # labelled rows are binary: the GLMO keeps them
+    r = O.solve(L, prob.K, prob.labelled_idx, prob.labels, max_iter=1, tol=-1, record_s=True, s_first=other)
+    np.testing.assert_array_equal(r["s"][0], other)
+    a = r["alpha"][0]
+    expect = (1 - a) * Uhat
+    expect[np.arange(prob.n), other] += a
+    expect[lab] = Uhat[lab]
+    np.testing.assert_allclose(r["U"], expect, rtol=0, atol=1e-15)
