@@ -167,6 +167,61 @@ def cpu_baseline(prob, iters: int) -> dict:
                       f"FP64, serial C, including the final objective evaluation; {dt:.1f} s"}
 
 
+def bench_many_classes(gfw, ctx, steps: int = 3, n: int = 100_000, K: int = 585) -> dict:
+    """The many-classes workload: an LFR-shaped network (n = 100,000, mean degree about 5,
+    K = 585 power-law communities, 5% labelled), FP32, 300 iterations per solve.  Reports
+    FW iterations/s and the roofline of the dominant kernel (the wavefront-per-row row
+    kernel, which reads and writes U and P and rebuilds the Q rows from the CSR)."""
+    import numpy as np
+    import torch
+
+    from synth import configs
+
+    prob = configs.lfr_many_classes(n=n, K=K)
+    g = prob.graph
+    G = gfw.Graph.from_host(ctx, g.n, K, g.indptr, g.indices, g.data, prob.labelled_idx, prob.labels, gfw.F32)
+    prm = gfw.params(eps=prob.eps, omega0=prob.omega0, max_iter=prob.max_iter, tol=-1.0)
+    stream = torch.cuda.current_stream()
+    gfw.solve(ctx, G, prm, want_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    for _ in range(steps):
+        its += gfw.solve(ctx, G, prm, want_stats=True, stream=stream)["iters"]
+    torch.cuda.synchronize()
+    untraced = its / (time.perf_counter() - t0)
+    gfw.trace_reset(ctx)
+    gfw.trace_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = 0
+    last = None
+    for _ in range(steps):
+        last = gfw.solve(ctx, G, prm, want_stats=True, stream=stream)
+        its += last["iters"]
+    torch.cuda.synchronize()
+    traced = its / (time.perf_counter() - t0)
+    gfw.trace_enable(ctx, False)
+    per = {}
+    for name, kid in (("row", gfw.KERNEL_ROW), ("label", gfw.KERNEL_LABEL), ("finish", gfw.KERNEL_FINISH)):
+        ms, cnt = gfw.trace_get(ctx, kid)
+        if cnt:
+            per[name] = round(1e3 * ms / cnt, 2)
+    # row kernel: U and P read and written (16 n K); for the Q rows the row pointers 4(n+1),
+    # values 4 nnz and neighbour vertices 2 nnz; own vertex read and written (4n); labels (4n)
+    row_bytes = 16 * g.n * K + 4 * (g.n + 1) + 6 * g.nnz + 8 * g.n
+    achieved = row_bytes / (per["row"] * 1e-6) / 1e9
+    acc = float(np.mean(last["labels"].cpu().numpy() == g.truth))
+    G.close()
+    return {"workload": f"lfr_many_classes: LFR-shaped network n={g.n}, nnz={g.nnz}, K={K}, 5% labelled, FP32, "
+                        f"{prob.max_iter} iterations", "fw_iters_per_s": round(traced, 1),
+            "untraced_fw_iters_per_s": round(untraced, 1), "kernels_us": per,
+            "roofline": {"bound": "hbm", "kernel": "k_row_big", "algorithmic_bytes_per_launch": row_bytes,
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4)},
+            "accuracy": round(acc, 4)}
+
+
 def bench_batched(gfw, ctx, count: int, seed: int = 3) -> dict:
     """The batch workload: `count` graphs (SBMs and 4-neighbour image grids, n log-uniform
     in [2e3, 2e5], K in 3..10), 300 iterations / gap 1e-6 each: one gfw_solve_batched call
@@ -316,6 +371,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="graphs in the batch measurement (0: skip)")
     ap.add_argument("--serve", type=int, default=160, help="requests under load in the serving measurement (0: skip)")
+    ap.add_argument("--many-classes", type=int, default=1, help="run the many-classes measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run only the 1 GiB calibration copies")
     ap.add_argument("--derive-traffic", metavar="DIR", help="write profiles/traffic.json from counter runs in DIR")
     args = ap.parse_args()
@@ -409,6 +465,9 @@ def main() -> int:
 
     G.close()
     extra = {}
+    if args.many_classes:
+        extra["many_classes"] = bench_many_classes(gfw, ctx)
+        log("[bench] many classes: " + json.dumps(extra["many_classes"]))
     if args.batch > 0:
         extra["batched"] = bench_batched(gfw, ctx, args.batch)
         log("[bench] batched: " + json.dumps(extra["batched"]))

@@ -200,7 +200,8 @@ gfw_status_t check_params(const gfw_params_t *p, int32_t K)
 static Shape shape_for(int64_t n, int64_t nnz, int32_t K)
 {
     Shape s;
-    s.kmax = K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : K <= 64 ? 64 : K <= 128 ? 128 : K <= 256 ? 256 : K <= 512 ? 512 : 1024;
+    // K <= 16: register buckets of the row-per-thread kernels; above: 64 * (classes per lane)
+    s.kmax = K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : 64 * (int)cdiv(K, 64);
     const double avg = (double)nnz / (double)n;
     int l = 1;
     while (l < 32 && l < avg * 0.25) l <<= 1;
@@ -229,6 +230,7 @@ void free_graph(gfw_graph_s *g)
     dfree(w.s0);
     dfree(w.s1);
     dfree(w.s4);
+    dfree(w.nv);
     dfree(w.row_part);
     dfree(w.lab_part);
     dfree(w.scratch);
@@ -510,7 +512,7 @@ gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_
     g->shape = shape_for(n, nnz, p->K);
     if ((s = choose_label_path(g, 0, st, p->location == GFW_HOST ? p->col_idx : nullptr)) != GFW_OK) return s;
     g->graph_bytes += 4 * (n + 1) + (4 + vs) * nnz + 4 * n;
-    g->solve_bytes = 3 * vs * n * p->K + (p->K > 16 ? 4 : 2) * n + sizeof(double) * ((kRowParts + 4) * g->shape.nb_row + 64) +
+    g->solve_bytes = 3 * vs * n * p->K + (p->K > 16 ? 4 * n + 2 * nnz : 2 * n) + sizeof(double) * ((kRowParts + 4) * g->shape.nb_row + 64) +
                      sizeof(Ctl);
     guard.g = nullptr;
     *out = g;
@@ -536,6 +538,7 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
     if ((s = dalloc((void **)&w.s0, sb * g->n)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.s1, sb * g->n)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.s4, (size_t)(g->n + 1) / 2)) != GFW_OK) return s;
+    if (g->K > 16 && (s = dalloc((void **)&w.nv, sizeof(uint16_t) * (size_t)g->nnz)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.row_part, sizeof(double) * kRowParts * std::max(g->shape.nb_row, g->shape.nb_big)))
         != GFW_OK) return s;
     if ((s = dalloc((void **)&w.lab_part, sizeof(double) * std::max<int64_t>(g->shape.nb_row, g->n_tiles)))
@@ -556,6 +559,11 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
 // kernel dispatch
 // --------------------------------------------------------------------------------------
 
+
+// every register bucket with kernels: the row-per-thread buckets and 64 * (1..16)
+#define GFW_FOR_EACH_KMAX(X) \
+    X(4) X(8) X(16) X(64) X(128) X(192) X(256) X(320) X(384) X(448) X(512) X(576) X(640) X(704) X(768) X(832) \
+    X(896) X(960) X(1024)
 
 template <typename T, int KMAX>
 static void set_lds_limits()
@@ -597,14 +605,11 @@ template <typename T>
 static void spmm_any(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
 {
     switch (g->shape.kmax) {
-    case 4: launch_spmm<T, 4>(g, U, P, st); break;
-    case 8: launch_spmm<T, 8>(g, U, P, st); break;
-    case 16: launch_spmm<T, 16>(g, U, P, st); break;
-    case 64: launch_spmm<T, 64>(g, U, P, st); break;
-    case 128: launch_spmm<T, 128>(g, U, P, st); break;
-    case 256: launch_spmm<T, 256>(g, U, P, st); break;
-    case 512: launch_spmm<T, 512>(g, U, P, st); break;
-    default: launch_spmm<T, 1024>(g, U, P, st); break;
+#define GFW_SPMM_CASE(KM) \
+    case KM: launch_spmm<T, KM>(g, U, P, st); break;
+        GFW_FOR_EACH_KMAX(GFW_SPMM_CASE)
+#undef GFW_SPMM_CASE
+    default: break;
     }
 }
 
@@ -777,14 +782,11 @@ static gfw_status_t solve_dispatch(gfw_graph_s *g, const gfw_params_t *prm, void
                                    int32_t *s_out, gfw_stats_t *stats, double *history, hipStream_t st)
 {
     switch (g->shape.kmax) {
-    case 4: return solve_impl<T, 4>(g, prm, U_out, labels_out, s_out, stats, history, st);
-    case 8: return solve_impl<T, 8>(g, prm, U_out, labels_out, s_out, stats, history, st);
-    case 16: return solve_impl<T, 16>(g, prm, U_out, labels_out, s_out, stats, history, st);
-    case 64: return solve_impl<T, 64>(g, prm, U_out, labels_out, s_out, stats, history, st);
-    case 128: return solve_impl<T, 128>(g, prm, U_out, labels_out, s_out, stats, history, st);
-    case 256: return solve_impl<T, 256>(g, prm, U_out, labels_out, s_out, stats, history, st);
-    case 512: return solve_impl<T, 512>(g, prm, U_out, labels_out, s_out, stats, history, st);
-    default: return solve_impl<T, 1024>(g, prm, U_out, labels_out, s_out, stats, history, st);
+#define GFW_SOLVE_CASE(KM) \
+    case KM: return solve_impl<T, KM>(g, prm, U_out, labels_out, s_out, stats, history, st);
+        GFW_FOR_EACH_KMAX(GFW_SOLVE_CASE)
+#undef GFW_SOLVE_CASE
+    default: return fail(GFW_E_UNSUPPORTED, "no kernels for K = %d", g->K);
     }
 }
 

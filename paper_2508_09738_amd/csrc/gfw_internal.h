@@ -45,6 +45,7 @@ struct Workspace {
     void *U = nullptr, *P = nullptr, *Q = nullptr; // n x K of the graph dtype
     uint8_t *s0 = nullptr, *s1 = nullptr;          // vertex indices (ping-pong)
     uint8_t *s4 = nullptr;                         // the current vertices packed two per byte (K <= 16)
+    uint16_t *nv = nullptr;                        // per CSR entry, the vertex of its column (K > 16)
     double *row_part = nullptr, *lab_part = nullptr, *scratch = nullptr;
     Ctl *ctl = nullptr;
     double *hist = nullptr;
@@ -149,6 +150,7 @@ GraphView<T> make_view(const gfw_graph_s *g)
     v.s0 = w.s0;
     v.s1 = w.s1;
     v.s4 = w.s4;
+    v.nv = w.nv;
     v.ctl = w.ctl;
     v.row_part = w.row_part;
     v.lab_part = w.lab_part;

@@ -242,6 +242,7 @@ struct GraphView {
     T *U, *P, *Q;
     uint8_t *s0, *s1;
     uint8_t *s4;      // vertices of the current iteration, two per byte (written for the sorted pass)
+    uint16_t *nv;     // per CSR entry, the last evaluated vertex of its column (large-K kernels)
     Ctl *ctl;
     double *row_part, *lab_part;
     int32_t nb_row;   // 256-row tiles (row kernel, plain label pass, SpMM)

@@ -10,11 +10,13 @@
 //    GLMO's lowest-index argmin and the per-row sums are wavefront reductions;
 //  * Q = L_s S is never stored: S is one-hot, so the row (L_s S_{k-1})_i has at most
 //    deg_i + 1 non-zeros, and the row kernel of iteration k rebuilds it from the row's
-//    neighbours and their vertices s_{k-1} just before the update
+//    values and its neighbours' vertices s_{k-1} just before the update
 //    P_k = (1 - a) P_{k-1} + a Q_{k-1}.  That saves writing and reading an n x K array;
-//  * the label pass only forms the per-row term Q_{i,s_i} of <S, L_s S> (the sum of the
-//    row's values over neighbours that share its vertex, plus the diagonal), which does
-//    not depend on K.
+//  * the label pass forms the per-row term Q_{i,s_i} of <S, L_s S> (the sum of the row's
+//    values over neighbours that share its vertex, plus the diagonal), which does not
+//    depend on K, and stores each entry's neighbour vertex (nv, 2 bytes per entry), so
+//    that the row kernel reads the vertices it needs with plain loads instead of a
+//    dependent gather.
 // Vertices are 16-bit (K up to 1024).  Every sum over a row runs in a fixed order, so
 // the results are deterministic; the sums over a row's classes are wavefront trees and
 // differ from a sequential sum by rounding only.
@@ -69,46 +71,67 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
     const uint16_t *__restrict__ s_prev = reinterpret_cast<const uint16_t *>((ctl->last_eval & 1) ? gv.s1 : gv.s0);
     uint16_t *__restrict__ s_cur = reinterpret_cast<uint16_t *>((ctl->k & 1) ? gv.s1 : gv.s0);
     const int32_t *__restrict__ rp = gv.rp;
-    const int32_t *__restrict__ ci = gv.ci;
     const T *__restrict__ a = gv.a;
     const double alpha = ctl->alpha;
     const SolveParams sp = ctl->sp;
+    const uint16_t *__restrict__ nv = gv.nv;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     double wacc[kRowParts];
 #pragma unroll
     for (int j = 0; j < kRowParts; ++j) wacc[j] = 0.0;
     const int64_t rbase = (int64_t)tile * kBigRowsPerBlock + (int64_t)wid * kBigRowsPerWave;
+    // row pointers, label and previous vertex of the wavefront's rows, one row per lane
+    int32_t md_b = 0, md_e = 0, md_y = -1, md_sp = 0;
+    if (lane < kBigRowsPerWave && rbase + lane < n) {
+        md_b = rp[rbase + lane];
+        md_e = rp[rbase + lane + 1];
+        md_y = gv.lab[rbase + lane];
+        md_sp = pending ? (int32_t)s_prev[rbase + lane] : 0;
+    }
     for (int t = 0; t < kBigRowsPerWave; ++t) {
         const int64_t i = rbase + t;
         if (i >= n) break; // uniform across the wavefront
         T *__restrict__ Ui = gv.U + i * K;
         T *__restrict__ Pi = gv.P + i * K;
-        double u[MC], p[MC];
+        // u and p are held at storage precision (every value is rounded to T anyway) and
+        // widened to FP64 where they are used
+        T u[MC], p[MC];
 #pragma unroll
         for (int m = 0; m < MC; ++m) {
             const int c = lane + 64 * m;
-            u[m] = c < K ? (double)Ui[c] : 0.0;
-            p[m] = c < K ? (double)Pi[c] : 0.0;
+            u[m] = c < K ? Ui[c] : (T)0;
+            p[m] = c < K ? Pi[c] : (T)0;
         }
         bool bl = true;
 #pragma unroll
         for (int m = 0; m < MC; ++m)
-            if (lane + 64 * m < K && !(u[m] == 0.0 || u[m] == 1.0)) bl = false;
+            if (lane + 64 * m < K && !(u[m] == (T)0 || u[m] == (T)1)) bl = false;
         bool binary = __all(bl);
         if (pending) {
-            const int32_t spi = (int32_t)s_prev[i];
-            // Q_{k-1} row i: values of the row summed per neighbour vertex, in CSR order
+            const int32_t spi = __shfl(md_sp, t, 64);
+            // Q_{k-1} row i: values of the row summed per neighbour vertex, in CSR order.  The
+            // row's entries are loaded one per lane (64 at a time) with their vertices, then
+            // taken in order from the lanes that hold them.
             T q[MC];
 #pragma unroll
             for (int m = 0; m < MC; ++m) q[m] = (T)0;
-            const int32_t e0 = rp[i], e1 = rp[i + 1];
-            for (int32_t e = e0; e < e1; ++e) {
-                const int32_t sj = (int32_t)s_prev[ci[e]];
-                const T v = a[e];
-                if ((sj & 63) == lane) {
+            const int32_t e0 = __shfl(md_b, t, 64), e1 = __shfl(md_e, t, 64);
+            for (int32_t c0 = e0; c0 < e1; c0 += 64) {
+                const int cnt = min(64, e1 - c0);
+                int32_t sj_l = 0;
+                T v_l = (T)0;
+                if (lane < cnt) {
+                    sj_l = (int32_t)nv[c0 + lane];
+                    v_l = a[c0 + lane];
+                }
+                for (int x = 0; x < cnt; ++x) {
+                    const int32_t sj = __shfl(sj_l, x, 64);
+                    const T v = __shfl(v_l, x, 64);
+                    if ((sj & 63) == lane) {
 #pragma unroll
-                    for (int m = 0; m < MC; ++m)
-                        if (m == (sj >> 6)) q[m] += v;
+                        for (int m = 0; m < MC; ++m)
+                            if (m == (sj >> 6)) q[m] += v;
+                    }
                 }
             }
             if (gv.diag_one && (spi & 63) == lane) {
@@ -121,15 +144,15 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
             for (int m = 0; m < MC; ++m) {
                 const int c = lane + 64 * m;
                 if (c < K) {
-                    p[m] = (double)(T)(om * p[m] + alpha * (double)q[m]);
-                    Pi[c] = (T)p[m];
+                    p[m] = (T)(om * (double)p[m] + alpha * (double)q[m]);
+                    Pi[c] = p[m];
                 }
             }
             // a row whose direction e_{s_i} - u_i is zero (binary, kept by the GLMO) stays as it is
             double us = 0.0;
 #pragma unroll
             for (int m = 0; m < MC; ++m)
-                if (m == (spi >> 6)) us = u[m];
+                if (m == (spi >> 6)) us = (double)u[m];
             const double at_s = __shfl(us, spi & 63, 64);
             if (!(binary && at_s == 1.0)) {
                 bl = true;
@@ -137,29 +160,23 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
                 for (int m = 0; m < MC; ++m) {
                     const int c = lane + 64 * m;
                     if (c < K) {
-                        u[m] = (double)(T)(om * u[m] + (c == spi ? alpha : 0.0));
-                        Ui[c] = (T)u[m];
-                        if (!(u[m] == 0.0 || u[m] == 1.0)) bl = false;
+                        u[m] = (T)(om * (double)u[m] + (c == spi ? alpha : 0.0));
+                        Ui[c] = u[m];
+                        if (!(u[m] == (T)0 || u[m] == (T)1)) bl = false;
                     }
                 }
                 binary = __all(bl);
             }
         }
         if (active) {
-            const int32_t y = gv.lab[i];
+            const int32_t y = __shfl(md_y, t, 64);
             const double om_i = y >= 0 ? sp.omega0 : 0.0;
-            double g[MC];
-#pragma unroll
-            for (int m = 0; m < MC; ++m) {
-                const int c = lane + 64 * m;
-                if (c < K) {
-                    const double uhat = (c == y) ? 1.0 : 0.0;
-                    const double fid = om_i != 0.0 ? om_i * (uhat - u[m]) : 0.0;
-                    g[m] = p[m] + sp.inv_eps * (1.0 - 2.0 * u[m]) - fid;
-                } else {
-                    g[m] = 0.0;
-                }
-            }
+            // gradient entry of class c (eq. gradgl_vv2g), formed where it is used
+            auto grad = [&](const int m, const int c) -> double {
+                const double uc = (double)u[m];
+                const double fid = om_i != 0.0 ? om_i * (((c == y) ? 1.0 : 0.0) - uc) : 0.0;
+                return (double)p[m] + sp.inv_eps * (1.0 - 2.0 * uc) - fid;
+            };
             int32_t s;
             if (binary && sp.lmo == 0) {
                 // the GLMO keeps a binary row: its vertex is the position of its 1
@@ -167,7 +184,7 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
 #pragma unroll
                 for (int m = 0; m < MC; ++m) {
                     const int c = lane + 64 * m;
-                    if (c < K && u[m] == 1.0) cand = min(cand, c);
+                    if (c < K && u[m] == (T)1) cand = min(cand, c);
                 }
                 cand = wave_min_int(cand);
                 s = cand == INT_MAX ? 0 : cand;
@@ -177,9 +194,10 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
 #pragma unroll
                 for (int m = 0; m < MC; ++m) {
                     const int c = lane + 64 * m;
-                    if (c < K && (sp.lmo == 1 || u[m] != 0.0)) {
-                        if (bi == INT_MAX || g[m] < best) {
-                            best = g[m];
+                    if (c < K && (sp.lmo == 1 || u[m] != (T)0)) {
+                        const double gm = grad(m, c);
+                        if (bi == INT_MAX || gm < best) {
+                            best = gm;
                             bi = c;
                         }
                     }
@@ -193,14 +211,15 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
             for (int m = 0; m < MC; ++m) {
                 const int c = lane + 64 * m;
                 if (c < K) {
-                    const double d = (c == s ? 1.0 : 0.0) - u[m];
-                    gap -= g[m] * d;
-                    up += u[m] * p[m];
+                    const double uc = (double)u[m], pc = (double)p[m];
+                    const double d = (c == s ? 1.0 : 0.0) - uc;
+                    gap -= grad(m, c) * d;
+                    up += uc * pc;
                     dd += d * d;
-                    pen += u[m] * (1.0 - u[m]);
-                    if (c == s) ps = p[m];
+                    pen += uc * (1.0 - uc);
+                    if (c == s) ps = pc;
                     if (om_i != 0.0) {
-                        const double e = (y == c ? 1.0 : 0.0) - u[m];
+                        const double e = (y == c ? 1.0 : 0.0) - uc;
                         fid += e * e;
                     }
                 }
@@ -232,9 +251,10 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
     }
 }
 
-// Label pass for large K: only the per-row term Q_{i,s_i} = sum of the row's values over
-// neighbours with vertex s_i (CSR order) + the diagonal, one thread per row, 256-row
-// blocks; partial lab_part[tile].
+// Label pass for large K: the per-row term Q_{i,s_i} = sum of the row's values over
+// neighbours with vertex s_i (CSR order) + the diagonal, and each entry's neighbour vertex
+// nv[e] = s_{ci[e]} for the next row kernel; one thread per row, 256-row blocks; partial
+// lab_part[tile].
 template <typename T>
 __device__ __forceinline__ void label_big_body(const GraphView<T> &gv, const int tile)
 {
@@ -247,8 +267,11 @@ __device__ __forceinline__ void label_big_body(const GraphView<T> &gv, const int
         const int32_t si = (int32_t)s[i];
         T acc = (T)0;
         const int32_t e0 = gv.rp[i], e1 = gv.rp[i + 1];
-        for (int32_t e = e0; e < e1; ++e)
-            if ((int32_t)s[gv.ci[e]] == si) acc += gv.a[e];
+        for (int32_t e = e0; e < e1; ++e) {
+            const uint16_t sj = s[gv.ci[e]];
+            gv.nv[e] = sj;
+            if ((int32_t)sj == si) acc += gv.a[e];
+        }
         own = (double)(acc + (gv.diag_one ? (T)1 : (T)0));
     }
     double v[1] = {own};
