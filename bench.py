@@ -441,7 +441,7 @@ def main() -> int:
 
     per = {}
     for name, kid in (("row", gfw.KERNEL_ROW), ("label", gfw.KERNEL_LABEL), ("finish", gfw.KERNEL_FINISH),
-                      ("spmm", gfw.KERNEL_SPMM), ("fused", gfw.KERNEL_FUSED)):
+                      ("spmm", gfw.KERNEL_SPMM)):
         ms, cnt = gfw.trace_get(ctx, kid)
         if cnt:
             per[name] = {"avg_us": 1e3 * ms / cnt, "launches": cnt, "total_ms": ms}

@@ -115,8 +115,13 @@ typedef struct {
     gfw_lmo_t lmo;
     int32_t one_shot;    /* 1: Alg. 4 (OSFW), U_1 = S_0                                      */
     double lipschitz;    /* Lbar for GFW_LS_SHORT; <= 0 selects rho_max + 2/eps + omega0    */
-    const void *U0;      /* DEVICE n x K of the graph's dtype, rows in Sigma; NULL = U_0 = Uhat
-                            with unlabelled rows 1/K (Section 5.1)                          */
+    const void *U0;      /* n x K of the graph's dtype, rows in Sigma (not checked); NULL =
+                            U_0 = Uhat with unlabelled rows 1/K (Section 5.1).  A DEVICE
+                            array for gfw_solve / gfw_solve_batched, a HOST array (copied at
+                            submit) for gfw_server_submit.  Warm start for new nodes
+                            (Section 4, closing remarks): rows of already segmented nodes
+                            one-hot, new rows anywhere in Sigma; the GLMO keeps binary rows,
+                            so only the new rows move.                                       */
     int32_t p_refresh;   /* recompute L_s U by a full SpMM every p_refresh iterations
                             (0 = only at the start); see gfw_solve                          */
 } gfw_params_t;
@@ -216,8 +221,7 @@ typedef enum {
     GFW_KERNEL_LABEL = 1,  /* L_s S with one-hot S (label pass)                            */
     GFW_KERNEL_FINISH = 2, /* reductions, step size, stop test                             */
     GFW_KERNEL_SPMM = 3,   /* L_s U                                                          */
-    GFW_KERNEL_FUSED = 4,  /* persistent single-launch iteration kernel                      */
-    GFW_KERNEL_COUNT = 5
+    GFW_KERNEL_COUNT = 4
 } gfw_kernel_t;
 /* When enabled, every hot-path launch made through ctx is bracketed by HIP events on the
  * launch stream; durations are accumulated when the owning call completes (tracing makes

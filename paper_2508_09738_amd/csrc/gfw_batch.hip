@@ -350,7 +350,7 @@ static gfw_status_t solve_batched_impl(gfw_context_s *cx, int32_t count, gfw_gra
 
 // Device bytes a problem will hold while resident (graph + one solve), an upper bound of
 // gfw_graph_footprint for the same problem.
-static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter)
+static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter, bool warm)
 {
     const size_t v = dsize(p->dtype);
     const size_t n = (size_t)p->n, nnz = (size_t)p->nnz, K = (size_t)p->K;
@@ -359,7 +359,7 @@ static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter)
     if (p->nnz >= ((int64_t)4 << 20)) graph += 6 * nnz + 4 * (n + 2); // column-sorted copy and its tiles
     const size_t solve = 3 * v * n * K + 2 * n + 8 * ((size_t)(kRowParts + 4) * nb + 64) + sizeof(Ctl) +
                          8 * 5 * ((size_t)max_iter + 1) + 4096;
-    return graph + solve;
+    return graph + solve + (warm ? v * n * K : 0); // a warm start holds its U_0 until retirement
 }
 
 struct ServerRequest {
@@ -368,6 +368,8 @@ struct ServerRequest {
     std::vector<int64_t> rp;
     std::vector<int32_t> ci, li, lb;
     std::vector<unsigned char> vals;
+    std::vector<unsigned char> u0h; // warm start: U_0 copied at submit
+    void *u0d = nullptr;            // its device copy while resident
     gfw_params_t prm{};
     size_t footprint = 0;
     int state = 0;         // 0 queued or resident, 2 done (read and written under the server mutex)
@@ -522,6 +524,19 @@ static void server_loop(gfw_server_s *sv)
                 failed.push_back(r);
                 continue;
             }
+            if (!r->u0h.empty()) { // warm start: U_0 goes to the device with the graph
+                if (hipMalloc(&r->u0d, r->u0h.size()) != hipSuccess ||
+                    hipMemcpyAsync(r->u0d, r->u0h.data(), r->u0h.size(), hipMemcpyHostToDevice, sv->st) != hipSuccess) {
+                    r->status = fail(GFW_E_NOMEM, "warm-start U_0 allocation");
+                    r->error = gfw_last_error();
+                    dfree(r->u0d);
+                    r->u0d = nullptr;
+                    free_graph(g);
+                    failed.push_back(r);
+                    continue;
+                }
+                r->prm.U0 = r->u0d;
+            }
             r->g = g;
             r->rp.clear();
             r->ci.clear();
@@ -555,6 +570,9 @@ static void server_loop(gfw_server_s *sv)
             if (r->finished) {
                 free_graph(r->g);
                 r->g = nullptr;
+                dfree(r->u0d);
+                r->u0d = nullptr;
+                r->u0h.clear();
                 sv->used -= r->footprint;
                 r->state = 2;
             } else {
@@ -633,10 +651,9 @@ gfw_status_t gfw_server_submit(gfw_server_t sv, const gfw_problem_t *p, const gf
     gfw_status_t s = check_problem(p);
     if (s != GFW_OK) return s;
     if ((s = check_params(prm, p->K)) != GFW_OK) return s;
-    if (prm->U0) return fail(GFW_E_UNSUPPORTED, "server requests start from Uhat (U0 must be NULL)");
     if (prm->p_refresh) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported by the server");
     if (p->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by the server");
-    const size_t fp = request_footprint(p, prm->max_iter);
+    const size_t fp = request_footprint(p, prm->max_iter, prm->U0 != nullptr);
     if (fp > sv->budget) return fail(GFW_E_BUDGET, "request needs %zu bytes, budget is %zu", fp, sv->budget);
     auto *r = new (std::nothrow) ServerRequest();
     if (!r) return fail(GFW_E_NOMEM, "host allocation failed");
@@ -653,6 +670,11 @@ gfw_status_t gfw_server_submit(gfw_server_t sv, const gfw_problem_t *p, const gf
     r->prob.labelled_idx = r->li.data();
     r->prob.labels = r->lb.data();
     r->prm = *prm;
+    if (prm->U0) { // a HOST array for server requests; copied like the graph
+        const size_t ub = v * (size_t)p->n * (size_t)p->K;
+        r->u0h.assign((const unsigned char *)prm->U0, (const unsigned char *)prm->U0 + ub);
+        r->prm.U0 = nullptr; // set to the device copy at admission
+    }
     r->footprint = fp;
     {
         std::lock_guard<std::mutex> lk(sv->mu);
@@ -703,6 +725,7 @@ gfw_status_t gfw_server_destroy(gfw_server_t sv)
     (void)hipStreamSynchronize(sv->st);
     for (auto &kv : sv->all) {
         if (kv.second->g) free_graph(kv.second->g);
+        dfree(kv.second->u0d);
         delete kv.second;
     }
     (void)hipStreamDestroy(sv->st);

@@ -34,7 +34,7 @@ EXPORTED = [
     "gfw_graph_tune", "gfw_graph_query",
 ]
 TUNE_LABEL_PATH = 0
-KERNEL_ROW, KERNEL_LABEL, KERNEL_FINISH, KERNEL_SPMM, KERNEL_FUSED = 0, 1, 2, 3, 4
+KERNEL_ROW, KERNEL_LABEL, KERNEL_FINISH, KERNEL_SPMM = 0, 1, 2, 3
 
 
 class GfwError(RuntimeError):
@@ -300,10 +300,18 @@ class Server:
         self._meta = {}
 
     def submit(self, n, K, indptr, indices, data, labelled_idx, labels, prm: Params, dtype: int = F32,
-               kind: int = GRAPH_W) -> int:
+               kind: int = GRAPH_W, U0=None) -> int:
+        """U0: optional host n x K array (warm start); it is copied at submit."""
         pb, keep = host_problem(n, K, indptr, indices, data, labelled_idx, labels, dtype, kind)
+        p2 = Params.from_buffer_copy(prm)
+        u0 = None
+        if U0 is not None:
+            u0 = np.ascontiguousarray(U0, dtype=np.float32 if dtype == F32 else np.float64)
+            if u0.shape != (n, K):
+                raise ValueError("U0 must be n x K")
+            p2.U0 = u0.ctypes.data
         t = C.c_uint64()
-        check(lib().gfw_server_submit(self.handle, C.byref(pb), C.byref(prm), C.byref(t)))
+        check(lib().gfw_server_submit(self.handle, C.byref(pb), C.byref(p2), C.byref(t)))
         self._meta[t.value] = (n, K, dtype)
         return t.value
 

@@ -115,3 +115,22 @@ def lfr_many_classes(seed: int = 5, n: int = 100_000, K: int = 585, avg_degree: 
     g = graphs.lfr_like(n, K, avg_degree, mu, seed)
     idx, lab = graphs.stratified_labels(g.truth, K, frac, seed)
     return Problem(g, idx, lab, K, dtype, 50.0, 1000.0, max_iter, 1e-6, f"lfr_many_classes(n={n},K={K})")
+
+
+def grown_sbm(seed: int = 6, n_old: int = 3000, n_new: int = 150, K: int = 3, avg_degree: float = 24.0,
+              frac: float = 0.05):
+    """A network that grows: an SBM on n_old + n_new nodes whose first n_old nodes (in the
+    randomly permuted order) are the network seen first.  Returns (old problem, grown
+    problem); both label the same nodes, all of them old."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    g = graphs.sbm_by_degree(n_old + n_new, K, avg_degree, 8.0, seed)
+    W = sp.csr_matrix((g.data, g.indices, g.indptr), shape=(g.n, g.n))
+    Wo = W[:n_old, :n_old].tocsr()
+    Wo.sort_indices()
+    go = graphs.Graph(n_old, K, Wo.indptr.astype(np.int64), Wo.indices.astype(np.int32), Wo.data, g.truth[:n_old])
+    idx, lab = graphs.stratified_labels(go.truth, K, frac, seed)
+    old = Problem(go, idx, lab, K, "f64", 50.0, 1000.0, 300, 1e-6, "grown_sbm(old)")
+    full = Problem(g, idx, lab, K, "f64", 50.0, 1000.0, 300, 1e-6, "grown_sbm(full)")
+    return old, full

@@ -535,3 +535,21 @@ def test_first_iteration_vertices_override():
     expect[np.arange(prob.n), other] += a
     expect[lab] = Uhat[lab]
     np.testing.assert_allclose(r["U"], expect, rtol=0, atol=1e-15)
+
+
+def test_warm_start_moves_only_new_rows():
+    """Section 4, closing remarks: warm-started from a point whose old rows are the binary
+    solution of the old network, GFW keeps those rows (the GLMO returns a binary row's own
+    vertex, so its direction is zero) and only the new rows change."""
+    old, full = configs.grown_sbm(n_old=600, n_new=40)
+    r_old = O.solve_problem(old, max_iter=200)
+    n_old, K = old.n, old.K
+    U0 = np.full((full.n, K), 1.0 / K)
+    U0[:n_old] = 0.0
+    U0[np.arange(n_old), r_old["labels"]] = 1.0
+    L = O.operator_for(full.graph)
+    r = O.solve(L, K, full.labelled_idx, full.labels, max_iter=60, tol=-1, U0=U0, record_s=True)
+    np.testing.assert_array_equal(r["U"][:n_old], U0[:n_old])
+    np.testing.assert_array_equal(r["s"][:r["iters"], :n_old],
+                                  np.broadcast_to(r_old["labels"], (r["iters"], n_old)))
+    assert np.all(r["U"][n_old:] != U0[n_old:])  # every new row moved
