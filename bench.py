@@ -265,8 +265,8 @@ def _pct(xs, q):
 
 
 def bench_serving(gfw, ctx, n_sat: int, n_load: int, n_fifo: int, seed: int = 4) -> dict:
-    """The serving workload: 8-neighbour image grids (sides 128..1024, K in {3,4,6}, 2%
-    scribbles), 300 iterations / gap 1e-6.  Saturation throughput with everything submitted
+    """The serving workload: 8-neighbour image grids (sides 128..1024, K in {3,4,6}, 2% of
+    pixels labelled by short scribble strokes), 300 iterations / gap 1e-6.  Saturation throughput with everything submitted
     at once, then Poisson arrivals at 80% of it, served by the continuous-batching server and,
     at the same rate, by a FIFO one-at-a-time loop (graph set-up + gfw_solve per request)."""
     import random
@@ -279,6 +279,13 @@ def bench_serving(gfw, ctx, n_sat: int, n_load: int, n_fifo: int, seed: int = 4)
 
     t0 = time.time()
     pool = configs.serve_pool(seed)
+    for p in pool:  # the arrays a client would hold: already in the submitted types
+        g = p.graph
+        g.indptr = np.ascontiguousarray(g.indptr, np.int64)
+        g.indices = np.ascontiguousarray(g.indices, np.int32)
+        g.data = np.ascontiguousarray(g.data, np.float32)
+        p.labelled_idx = np.ascontiguousarray(p.labelled_idx, np.int32)
+        p.labels = np.ascontiguousarray(p.labels, np.int32)
     log(f"[bench] serve: pool of {len(pool)} requests in {time.time() - t0:.1f}s")
     prm = gfw.params(eps=50.0, omega0=1000.0, max_iter=300, tol=1e-6)
 
@@ -287,9 +294,10 @@ def bench_serving(gfw, ctx, n_sat: int, n_load: int, n_fifo: int, seed: int = 4)
         return sv.submit(g.n, p.K, g.indptr, g.indices, g.data, p.labelled_idx, p.labels, prm)
 
     def run_server(arrivals):
-        """arrivals: list of (time offset, problem); returns latencies and wall time."""
+        """arrivals: list of (time offset, problem); returns latencies, wall time, executed
+        iterations and label accuracies of the results."""
         sv = gfw.Server(ctx, 96 << 30, 64)
-        lat, pend = [], {}
+        lat, its, accs, pend = [], [], [], {}
         lock = threading.Lock()
         t_start = time.perf_counter()
 
@@ -301,7 +309,7 @@ def bench_serving(gfw, ctx, n_sat: int, n_load: int, n_fifo: int, seed: int = 4)
                 t_sub = time.perf_counter()
                 tk = submit(sv, p)
                 with lock:
-                    pend[tk] = t_sub
+                    pend[tk] = (t_sub, p)
 
         th = threading.Thread(target=feeder)
         th.start()
@@ -309,10 +317,12 @@ def bench_serving(gfw, ctx, n_sat: int, n_load: int, n_fifo: int, seed: int = 4)
         while done < len(arrivals):
             with lock:
                 items = list(pend.items())
-            for tk, ts in items:
+            for tk, (ts, p) in items:
                 r = sv.poll(tk, blocking=False)
                 if r is not None:
                     lat.append(time.perf_counter() - ts)
+                    its.append(r["iters"])
+                    accs.append(float(np.mean(r["labels"] == p.graph.truth)))
                     with lock:
                         del pend[tk]
                     done += 1
@@ -320,11 +330,11 @@ def bench_serving(gfw, ctx, n_sat: int, n_load: int, n_fifo: int, seed: int = 4)
         th.join()
         wall = time.perf_counter() - t_start
         sv.close()
-        return lat, wall
+        return lat, wall, its, accs
 
     # warm-up
     run_server([(0.0, pool[i]) for i in range(4)])
-    lat, wall = run_server([(0.0, pool[i % len(pool)]) for i in range(n_sat)])
+    lat, wall, its_s, acc_s = run_server([(0.0, pool[i % len(pool)]) for i in range(n_sat)])
     mu = n_sat / wall
     lam = 0.8 * mu
     rng = random.Random(7)
@@ -333,7 +343,7 @@ def bench_serving(gfw, ctx, n_sat: int, n_load: int, n_fifo: int, seed: int = 4)
         t += rng.expovariate(lam)
         offs.append(t)
     order = [rng.randrange(len(pool)) for _ in offs]
-    lat_b, wall_b = run_server([(offs[i], pool[order[i]]) for i in range(n_load)])
+    lat_b, wall_b, its_b, acc_b = run_server([(offs[i], pool[order[i]]) for i in range(n_load)])
 
     # FIFO one-at-a-time at the same arrival times
     lat_f = []
@@ -352,6 +362,8 @@ def bench_serving(gfw, ctx, n_sat: int, n_load: int, n_fifo: int, seed: int = 4)
         lat_f.append(time.perf_counter() - t_arr)
     wall_f = time.perf_counter() - t_start
     return {"requests_saturation": n_sat, "saturation_solves_per_s": round(mu, 1),
+            "mean_iterations": round(float(np.mean(its_s + its_b)), 1),
+            "mean_accuracy": round(float(np.mean(acc_s + acc_b)), 4),
             "arrival_rate_per_s": round(lam, 1),
             "served": {"requests": n_load, "solves_per_s": round(n_load / wall_b, 1),
                        "p50_ms": round(1e3 * _pct(lat_b, 50), 1), "p99_ms": round(1e3 * _pct(lat_b, 99), 1)},

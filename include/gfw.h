@@ -157,8 +157,10 @@ GFW_API gfw_status_t gfw_context_destroy(gfw_context_t ctx);
 
 /* ---- graphs ------------------------------------------------------------------------- */
 /*
- * Validates the problem (GFW_E_GRAPH / GFW_E_LABELS; device-located input is checked by a
- * kernel), copies it into library-owned device memory and forms the operator (Section 1):
+ * Validates the problem (GFW_E_GRAPH / GFW_E_LABELS: sizes, row pointers and labels of
+ * host input on the host; the CSR entries - column range and order, finite non-negative
+ * values, symmetry - by a kernel after the upload), copies it into library-owned device
+ * memory and forms the operator (Section 1):
  * degrees d_i = sum_j w_ij, d_i^{-1/2} (0 for an isolated node, whose row of L_s is then
  * e_i) and the scaled values -d_i^{-1/2} w_ij d_j^{-1/2}.  Symmetry of W (or L) is
  * checked.  The caller's arrays may be freed when the call returns.
@@ -237,7 +239,11 @@ GFW_API gfw_status_t gfw_trace_get(gfw_context_t ctx, int32_t kernel, double *to
  * their device footprint fits `hbm_budget_bytes` and fewer than `max_slots` run, stay
  * resident on the GPU and are advanced together by batched launches; new requests join
  * between macro-steps (continuous batching).  Each result equals the gfw_solve result of
- * the same problem alone.
+ * the same problem alone.  gfw_server_submit checks sizes, row pointers, labels and
+ * parameters (errors are returned at once); the CSR entries are checked on the device when
+ * the request is admitted, and a malformed graph makes that request alone fail with
+ * GFW_E_GRAPH at gfw_server_poll.  A worker thread runs the iterations while an admission
+ * thread builds the graphs of admitted requests on a second stream.
  */
 GFW_API gfw_status_t gfw_server_create(gfw_context_t ctx, size_t hbm_budget_bytes, int32_t max_slots,
                                gfw_server_t *out);

@@ -163,6 +163,21 @@ static gfw_status_t validate_host_labels(const gfw_problem_t *p)
     return GFW_OK;
 }
 
+// The O(n) part of the host checks: sizes, row pointers, labelled set.  The O(nnz) part
+// (column range and order, values, symmetry) runs on the device when a graph is created.
+gfw_status_t check_problem_light(const gfw_problem_t *p)
+{
+    gfw_status_t s = check_scalars(p);
+    if (s != GFW_OK || p->location != GFW_HOST) return s;
+    const int64_t n = p->n, nnz = p->nnz;
+    const int64_t *rp = p->row_ptr;
+    if (rp[0] != 0) return fail(GFW_E_GRAPH, "row_ptr[0] must be 0");
+    if (rp[n] != nnz) return fail(GFW_E_GRAPH, "row_ptr[n] (%lld) != nnz (%lld)", (long long)rp[n], (long long)nnz);
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return fail(GFW_E_GRAPH, "row_ptr decreases at row %lld", (long long)i);
+    return validate_host_labels(p);
+}
+
 gfw_status_t check_problem(const gfw_problem_t *p)
 {
     gfw_status_t s = check_scalars(p);
@@ -261,7 +276,10 @@ static gfw_status_t form_operator(gfw_graph_s *g, const T *wdev, hipStream_t st)
         k_rho_plain<T><<<grid_for(g->n, 256), 256, 0, st>>>(g->n, g->row_ptr, a, rho);
         g->diag_one = 0;
     }
-    k_max_reduce<<<1, kFinishThreads, 0, st>>>(rho, g->n, rmax);
+    const unsigned long long zero = 0; // the bit pattern of +0.0
+    GFW_HIP_TRY(hipMemcpyAsync(rmax, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+    k_max_nonneg<<<(unsigned)std::min<int64_t>(std::max<int64_t>(cdiv(g->n, 1024), 1), 1024), 256, 0, st>>>(
+        rho, g->n, (unsigned long long *)rmax);
     GFW_HIP_TRY(hipGetLastError());
     GFW_HIP_TRY(hipMemcpyAsync(&g->rho_max, rmax, sizeof(double), hipMemcpyDeviceToHost, st));
     GFW_HIP_TRY(hipStreamSynchronize(st));
@@ -408,7 +426,7 @@ static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st, 
 gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st,
                           bool validated)
 {
-    gfw_status_t s = validated ? GFW_OK : check_problem(p);
+    gfw_status_t s = validated ? GFW_OK : check_problem_light(p);
     if (s != GFW_OK) return s;
     GFW_HIP_TRY(hipSetDevice(ctx->device));
     gfw_graph_s *g = new (std::nothrow) gfw_graph_s();
@@ -445,14 +463,25 @@ gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_
     k_fill_i32<<<grid_for(n, 256), 256, 0, st>>>(n, g->lab, -1);
 
     if (p->location == GFW_HOST) {
-        std::vector<int32_t> rp32((size_t)n + 1);
-        for (int64_t i = 0; i <= n; ++i) rp32[(size_t)i] = (int32_t)p->row_ptr[i];
-        GFW_HIP_TRY(hipMemcpyAsync(g->row_ptr, rp32.data(), 4 * (n + 1), hipMemcpyHostToDevice, st));
+        // the row pointers (checked on the host) go up as int64 for the entry checks on the
+        // device, then are narrowed; columns and values are checked where they land
+        int64_t *rp64 = nullptr;
+        if ((s = dalloc((void **)&rp64, 8 * (n + 1))) != GFW_OK) { dfree(flags); return s; }
+        GFW_HIP_TRY(hipMemcpyAsync(rp64, p->row_ptr, 8 * (n + 1), hipMemcpyHostToDevice, st));
         if (nnz) GFW_HIP_TRY(hipMemcpyAsync(g->col, p->col_idx, 4 * nnz, hipMemcpyHostToDevice, st));
         if (p->vals) {
-            if ((s = dalloc(&wraw, vs * nnz)) != GFW_OK) { dfree(flags); return s; }
+            if ((s = dalloc(&wraw, vs * nnz)) != GFW_OK) { dfree(flags); dfree(rp64); return s; }
             if (nnz) GFW_HIP_TRY(hipMemcpyAsync(wraw, p->vals, vs * nnz, hipMemcpyHostToDevice, st));
         }
+        if (p->dtype == GFW_F32)
+            k_validate_graph<float><<<grid_for(n, 256), 256, 0, st>>>(n, nnz, rp64, g->col, (const float *)wraw,
+                                                                     p->kind == GFW_GRAPH_L, flags);
+        else
+            k_validate_graph<double><<<grid_for(n, 256), 256, 0, st>>>(n, nnz, rp64, g->col, (const double *)wraw,
+                                                                      p->kind == GFW_GRAPH_L, flags);
+        k_rowptr_narrow<<<grid_for(n + 1, 256), 256, 0, st>>>(n, rp64, g->row_ptr);
+        GFW_HIP_TRY(hipStreamSynchronize(st));
+        dfree(rp64);
         if (p->n_labelled) {
             int32_t *ti = nullptr, *tl = nullptr;
             if ((s = dalloc((void **)&ti, 4 * p->n_labelled)) != GFW_OK) { dfree(flags); dfree(wraw); return s; }
@@ -502,6 +531,10 @@ gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_
         unsigned int hf = 0;
         GFW_HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
         GFW_HIP_TRY(hipStreamSynchronize(st));
+        const char *what = (hf & 1u) ? "CSR malformed (column range or order)"
+                           : (hf & 4u) ? "negative or non-finite weight"
+                           : (hf & 2u) ? "graph is not symmetric" : nullptr;
+        if (what) { dfree(flags); dfree(wraw); return fail(GFW_E_GRAPH, "%s", what); }
         if (hf) { dfree(flags); dfree(wraw); return fail(GFW_E_LABELS, "labelled set invalid"); }
     }
     dfree(flags);

@@ -388,13 +388,16 @@ struct gfw_server_s {
     gfw_context_s *ctx = nullptr;
     size_t budget = 0, used = 0;
     int32_t max_slots = 0;
-    hipStream_t st = nullptr;
-    std::thread worker;
+    hipStream_t st = nullptr;       // iterations (worker thread)
+    hipStream_t st_admit = nullptr; // graph set-up of admitted requests (admission thread)
+    std::thread worker, admitter;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_admit;
     bool stop = false;
     uint64_t next_ticket = 1;
-    std::deque<gfw::ServerRequest *> queue;
+    int32_t in_setup = 0;                  // admitted, graph being built
+    std::deque<gfw::ServerRequest *> queue; // submitted, not admitted
+    std::deque<gfw::ServerRequest *> ready; // graph built, waiting for the next macro-step
     std::vector<gfw::ServerRequest *> resident;
     std::map<uint64_t, gfw::ServerRequest *> all;
     // device tables reused by every macro-step (grow-only): admission, iteration, retirement
@@ -495,57 +498,80 @@ static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &
     return GFW_OK;
 }
 
+// Admission thread: takes queued requests in order while the budget and the slots allow,
+// builds their graphs on its own stream (copies to the device, operator, workspace, warm
+// start), and hands them to the worker.  Graph set-up thus overlaps the worker's iterations.
+static void admit_loop(gfw_server_s *sv)
+{
+    (void)hipSetDevice(sv->ctx->device);
+    for (;;) {
+        ServerRequest *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_admit.wait(lk, [&] {
+                return sv->stop ||
+                       (!sv->queue.empty() &&
+                        (int32_t)(sv->resident.size() + sv->ready.size()) + sv->in_setup < sv->max_slots &&
+                        sv->used + sv->queue.front()->footprint <= sv->budget);
+            });
+            if (sv->stop) return;
+            r = sv->queue.front();
+            sv->queue.pop_front();
+            sv->used += r->footprint;
+            ++sv->in_setup;
+        }
+        gfw_graph_s *g = nullptr;
+        gfw_status_t s = graph_create(sv->ctx, &r->prob, &g, sv->st_admit, true); // O(n) checks made at submit
+        if (s == GFW_OK) s = ensure_workspace(g, r->prm.max_iter);
+        if (s == GFW_OK && !r->u0h.empty()) { // warm start: U_0 goes to the device with the graph
+            if (hipMalloc(&r->u0d, r->u0h.size()) != hipSuccess ||
+                hipMemcpyAsync(r->u0d, r->u0h.data(), r->u0h.size(), hipMemcpyHostToDevice, sv->st_admit) !=
+                    hipSuccess) {
+                s = fail(GFW_E_NOMEM, "warm-start U_0 allocation");
+                dfree(r->u0d);
+                r->u0d = nullptr;
+            } else {
+                r->prm.U0 = r->u0d;
+            }
+        }
+        if (s == GFW_OK && hipStreamSynchronize(sv->st_admit) != hipSuccess) s = fail(GFW_E_HIP, "graph set-up failed");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        --sv->in_setup;
+        if (s != GFW_OK) {
+            r->status = s;
+            r->error = gfw_last_error();
+            if (g) free_graph(g);
+            sv->used -= r->footprint;
+            r->state = 2;
+            sv->cv_done.notify_all();
+            sv->cv_admit.notify_all();
+            continue;
+        }
+        r->g = g;
+        r->rp.clear();
+        r->ci.clear();
+        r->vals.clear(); // the device copy is the reference from here on
+        sv->ready.push_back(r);
+        sv->cv_work.notify_all();
+    }
+}
+
+// Worker thread: every macro-step takes in the requests whose graphs are ready, advances all
+// resident requests by kMacroIters batched iterations, and retires the finished ones.
 static void server_loop(gfw_server_s *sv)
 {
     (void)hipSetDevice(sv->ctx->device);
     for (;;) {
-        std::vector<ServerRequest *> admit;
-        {
-            std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty() || !sv->resident.empty(); });
-            if (sv->stop) return;
-            while (!sv->queue.empty() && (int32_t)(sv->resident.size() + admit.size()) < sv->max_slots &&
-                   sv->used + sv->queue.front()->footprint <= sv->budget) {
-                ServerRequest *r = sv->queue.front();
-                sv->queue.pop_front();
-                sv->used += r->footprint;
-                admit.push_back(r);
-            }
-        }
-        std::vector<ServerRequest *> fresh, failed;
-        for (ServerRequest *r : admit) {
-            gfw_graph_s *g = nullptr;
-            gfw_status_t s = graph_create(sv->ctx, &r->prob, &g, sv->st, true); // validated at submit
-            if (s == GFW_OK) s = ensure_workspace(g, r->prm.max_iter);
-            if (s != GFW_OK) {
-                r->status = s;
-                r->error = gfw_last_error();
-                if (g) free_graph(g);
-                failed.push_back(r);
-                continue;
-            }
-            if (!r->u0h.empty()) { // warm start: U_0 goes to the device with the graph
-                if (hipMalloc(&r->u0d, r->u0h.size()) != hipSuccess ||
-                    hipMemcpyAsync(r->u0d, r->u0h.data(), r->u0h.size(), hipMemcpyHostToDevice, sv->st) != hipSuccess) {
-                    r->status = fail(GFW_E_NOMEM, "warm-start U_0 allocation");
-                    r->error = gfw_last_error();
-                    dfree(r->u0d);
-                    r->u0d = nullptr;
-                    free_graph(g);
-                    failed.push_back(r);
-                    continue;
-                }
-                r->prm.U0 = r->u0d;
-            }
-            r->g = g;
-            r->rp.clear();
-            r->ci.clear();
-            r->vals.clear(); // the device copy is the reference from here on
-            fresh.push_back(r);
-        }
+        std::vector<ServerRequest *> fresh;
         std::vector<ServerRequest *> run32, run64, fr32, fr64;
         {
-            std::lock_guard<std::mutex> lk(sv->mu);
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->ready.empty() || !sv->resident.empty(); });
+            if (sv->stop) return;
+            while (!sv->ready.empty()) {
+                fresh.push_back(sv->ready.front());
+                sv->ready.pop_front();
+            }
             for (ServerRequest *r : fresh) sv->resident.push_back(r);
             for (ServerRequest *r : sv->resident) (r->g->dtype == GFW_F32 ? run32 : run64).push_back(r);
         }
@@ -553,34 +579,35 @@ static void server_loop(gfw_server_s *sv)
         gfw_status_t s = GFW_OK;
         if (!run32.empty() || !fr32.empty()) s = server_step<float>(sv, fr32, run32);
         if (s == GFW_OK && (!run64.empty() || !fr64.empty())) s = server_step<double>(sv, fr64, run64);
+        std::vector<ServerRequest *> retired;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (s != GFW_OK) { // a device failure ends every resident request
+                for (ServerRequest *r : sv->resident) {
+                    r->status = s;
+                    r->error = gfw_last_error();
+                    r->finished = true;
+                }
+            }
+            std::vector<ServerRequest *> keep;
+            for (ServerRequest *r : sv->resident) (r->finished ? retired : keep).push_back(r);
+            sv->resident.swap(keep);
+        }
+        // device memory of the retired requests is released outside the lock
+        for (ServerRequest *r : retired) {
+            free_graph(r->g);
+            r->g = nullptr;
+            dfree(r->u0d);
+            r->u0d = nullptr;
+            r->u0h.clear();
+        }
         std::lock_guard<std::mutex> lk(sv->mu);
-        if (s != GFW_OK) { // a device failure ends every resident request
-            for (ServerRequest *r : sv->resident) {
-                r->status = s;
-                r->error = gfw_last_error();
-                r->finished = true;
-            }
-        }
-        for (ServerRequest *r : failed) {
-            r->state = 2;
+        for (ServerRequest *r : retired) {
             sv->used -= r->footprint;
+            r->state = 2;
         }
-        std::vector<ServerRequest *> keep;
-        for (ServerRequest *r : sv->resident) {
-            if (r->finished) {
-                free_graph(r->g);
-                r->g = nullptr;
-                dfree(r->u0d);
-                r->u0d = nullptr;
-                r->u0h.clear();
-                sv->used -= r->footprint;
-                r->state = 2;
-            } else {
-                keep.push_back(r);
-            }
-        }
-        sv->resident.swap(keep);
         sv->cv_done.notify_all();
+        sv->cv_admit.notify_all();
     }
 }
 
@@ -639,7 +666,13 @@ gfw_status_t gfw_server_create(gfw_context_t ctx, size_t hbm_budget_bytes, int32
         delete sv;
         return fail(GFW_E_HIP, "stream creation failed");
     }
+    if (hipStreamCreateWithFlags(&sv->st_admit, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(sv->st);
+        delete sv;
+        return fail(GFW_E_HIP, "stream creation failed");
+    }
     sv->worker = std::thread(server_loop, sv);
+    sv->admitter = std::thread(admit_loop, sv);
     *out = sv;
     return GFW_OK;
 }
@@ -648,7 +681,7 @@ gfw_status_t gfw_server_submit(gfw_server_t sv, const gfw_problem_t *p, const gf
 {
     if (!sv || !p || !prm || !ticket) return fail(GFW_E_INVALID_ARG, "NULL argument");
     if (p->location != GFW_HOST) return fail(GFW_E_INVALID_ARG, "server requests must be host-resident");
-    gfw_status_t s = check_problem(p);
+    gfw_status_t s = check_problem_light(p); // the CSR entries are checked on the device at admission
     if (s != GFW_OK) return s;
     if ((s = check_params(prm, p->K)) != GFW_OK) return s;
     if (prm->p_refresh) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported by the server");
@@ -682,7 +715,7 @@ gfw_status_t gfw_server_submit(gfw_server_t sv, const gfw_problem_t *p, const gf
         sv->all[r->ticket] = r;
         sv->queue.push_back(r);
     }
-    sv->cv_work.notify_all();
+    sv->cv_admit.notify_all();
     *ticket = r->ticket;
     return GFW_OK;
 }
@@ -721,14 +754,18 @@ gfw_status_t gfw_server_destroy(gfw_server_t sv)
         sv->stop = true;
     }
     sv->cv_work.notify_all();
+    sv->cv_admit.notify_all();
     if (sv->worker.joinable()) sv->worker.join();
+    if (sv->admitter.joinable()) sv->admitter.join();
     (void)hipStreamSynchronize(sv->st);
+    (void)hipStreamSynchronize(sv->st_admit);
     for (auto &kv : sv->all) {
         if (kv.second->g) free_graph(kv.second->g);
         dfree(kv.second->u0d);
         delete kv.second;
     }
     (void)hipStreamDestroy(sv->st);
+    (void)hipStreamDestroy(sv->st_admit);
     delete sv;
     return GFW_OK;
 }

@@ -121,10 +121,12 @@ struct gfw_graph_s {
 };
 
 namespace gfw {
-gfw_status_t check_problem(const gfw_problem_t *p);
+gfw_status_t check_problem(const gfw_problem_t *p);       // every check, on the host
+gfw_status_t check_problem_light(const gfw_problem_t *p); // sizes, row pointers, labels only
 gfw_status_t check_params(const gfw_params_t *p, int32_t K);
-// validated = true skips the host validation of a host-resident problem that the caller has
-// already checked with check_problem (the server does so at submit).
+// graph_create checks the CSR entries (column range and order, values, symmetry) on the
+// device after the upload.  validated = true skips the O(n) host checks of check_problem_light,
+// which the caller has already made (the server does so at submit).
 gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_s **out, hipStream_t st,
                           bool validated = false);
 void free_graph(gfw_graph_s *g);

@@ -1148,11 +1148,15 @@ static __global__ void k_clear_pending(Ctl *ctl)
     if (threadIdx.x == 0 && blockIdx.x == 0) ctl->pending = 0;
 }
 
-static __global__ void k_max_reduce(const double *__restrict__ v, int64_t n, double *__restrict__ out)
+// Largest of n non-negative values over all blocks of the grid.  A non-negative IEEE double
+// orders like its bit pattern as an unsigned integer, so the block maxima are combined with
+// an integer atomic max (the result does not depend on the order).  *out must hold 0 first.
+static __global__ void k_max_nonneg(const double *__restrict__ v, int64_t n, unsigned long long *__restrict__ out)
 {
-    __shared__ double red[kFinishThreads / 64];
+    __shared__ double red[256 / 64];
     double m = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, v[i]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, v[i]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -1160,7 +1164,7 @@ static __global__ void k_max_reduce(const double *__restrict__ v, int64_t n, dou
     if (threadIdx.x == 0) {
         double s = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, red[w]);
-        *out = s;
+        atomicMax(out, (unsigned long long)__double_as_longlong(s));
     }
 }
 

@@ -96,7 +96,9 @@ def serve_request(seed: int, i: int, sides=(128, 256, 512, 1024), Ks=(3, 4, 6), 
     K = k_draw if K is None else int(K)
     sub = seed * 100003 + i
     g = graphs.image_grid(side * side, K, sub, neighbours=8, side=side)
-    idx, lab = graphs.scribble_labels(g.truth, side, side, K, 0.02, sub)
+    # short strokes (4 pixels) scattered inside the regions: with a few long strokes every
+    # pixel without a labelled neighbour ties at U_0 and the first step ends the solve
+    idx, lab = graphs.scribble_labels(g.truth, side, side, K, 0.02, sub, stroke_len=4)
     return Problem(g, idx, lab, K, "f32", 50.0, 1000.0, 300, 1e-6, f"serve[{i}]")
 
 

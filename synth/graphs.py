@@ -319,9 +319,13 @@ def stratified_labels(truth: np.ndarray, K: int, frac: float, seed: int) -> tupl
     return idx[order], lab[order]
 
 
-def scribble_labels(truth: np.ndarray, H: int, W: int, K: int, frac: float, seed: int) -> tuple:
+def scribble_labels(truth: np.ndarray, H: int, W: int, K: int, frac: float, seed: int,
+                    stroke_len: int | None = None) -> tuple:
     """Random-walk strokes inside each region, about frac * n pixels split evenly over the
-    classes present.  Returns (labelled_idx int32 sorted, labels int32)."""
+    classes present.  stroke_len=None draws one long stroke per class (restarted only at
+    random when it runs into the region's border); an integer starts a new stroke at a random
+    pixel of the class after every stroke_len steps.  Returns (labelled_idx int32 sorted,
+    labels int32)."""
     rg = rng_for(seed, 5)
     region = truth.reshape(H, W)
     total = max(K, int(round(frac * H * W)))
@@ -343,6 +347,10 @@ def scribble_labels(truth: np.ndarray, H: int, W: int, K: int, frac: float, seed
             if not chosen[p]:
                 chosen[p] = True
                 got += 1
+            if stroke_len is not None and tries % stroke_len == 0:
+                start = cells[rg.integers(cells.size)]
+                y, x = divmod(int(start), W)
+                continue
             dy, dx = steps[rg.integers(4)]
             ny, nx = y + dy, x + dx
             if 0 <= ny < H and 0 <= nx < W and region[ny, nx] == c:

@@ -242,6 +242,28 @@ def test_device_input_validation_errors():
     assert e.value.status == -3
 
 
+def test_host_input_entry_checks_on_device():
+    """Host-located input: the CSR entries are checked by a kernel after the upload.  Each
+    malformed graph gets the code the full host check (gfw_check_problem) gives it."""
+    say("[gpu] host input, entry checks on the device")
+    g = graphs.path_graph(6, 2)
+    ip, ix, w = g.indptr.copy(), g.indices.copy(), g.data.astype(np.float64).copy()
+    cases = {}
+    a = ix.copy(); a[ip[1]:ip[2]] = a[ip[1]:ip[2]][::-1]; cases["unsorted"] = (ip, a, w)
+    a = ix.copy(); a[ip[1] + 1] = a[ip[1]]; cases["duplicate"] = (ip, a, w)
+    a = ix.copy(); a[-1] = 9; cases["column range"] = (ip, a, w)
+    b = w.copy(); b[0] = b[1] = -1.0; cases["negative"] = (ip, ix, b)
+    b = w.copy(); b[2] = np.nan; cases["nan"] = (ip, ix, b)
+    b = w.copy(); b[0] = 2.0; cases["asymmetric value"] = (ip, ix, b)
+    p2 = ip.copy(); p2[6] -= 1; cases["asymmetric pattern"] = (p2, ix[:-1], w[:-1])
+    for name, (pp, cc, ww) in cases.items():
+        host = gfw.check_problem_host(g.n, 2, pp, cc, ww, [0], [1], gfw.F64)
+        assert host == -2, name
+        with pytest.raises(gfw.GfwError) as e:
+            gfw.Graph.from_host(ctx(), g.n, 2, pp, cc, ww, [0], [1], gfw.F64)
+        assert e.value.status == host, name
+
+
 def test_edge_cases():
     say("[gpu] edge cases")
     # one node, no edges

@@ -59,8 +59,16 @@ def test_server_rejects_poisoned_request_alone_and_enforces_budget():
     bad = reqs[0].graph
     w = bad.data.copy()
     w[5] = np.nan
+    # a NaN weight is found on the device at admission: that request alone fails, at poll
+    t_bad = sv.submit(bad.n, reqs[0].K, bad.indptr, bad.indices, w, reqs[0].labelled_idx, reqs[0].labels, prm)
     with pytest.raises(gfw.GfwError) as e:
-        sv.submit(bad.n, reqs[0].K, bad.indptr, bad.indices, w, reqs[0].labelled_idx, reqs[0].labels, prm)
+        sv.poll(t_bad)
+    assert e.value.status == -2
+    # a decreasing row pointer is caught at submit
+    ip = bad.indptr.copy()
+    ip[3] = ip[2] - 1
+    with pytest.raises(gfw.GfwError) as e:
+        sv.submit(bad.n, reqs[0].K, ip, bad.indices, bad.data, reqs[0].labelled_idx, reqs[0].labels, prm)
     assert e.value.status == -2
     big = graphs.image_grid(1024 * 1024, 3, 5, neighbours=8, side=1024)
     with pytest.raises(gfw.GfwError) as e:
