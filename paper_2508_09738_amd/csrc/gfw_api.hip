@@ -375,8 +375,12 @@ static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const 
 // neighbour labels are scattered, the plain pass otherwise.  mode: 0 auto, 1 plain, 2 sorted.
 // host_col: the column indices in host memory when the caller has them (else they are
 // copied back from the device when needed).
-static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st, const int32_t *host_col = nullptr)
+static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st, const int32_t *host_col = nullptr);
+static gfw_status_t measure_label_paths(gfw_graph_s *g, hipStream_t st);
+
+static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st, const int32_t *host_col)
 {
+    if (mode == 3) return measure_label_paths(g, st);
     if (mode == 1) {
         g->label_path = 0;
         return GFW_OK;
@@ -632,6 +636,81 @@ static void launch_label(const gfw_graph_s *g, hipStream_t st)
         const size_t lds = sizeof(T) * kRowBlock * g->K;
         k_label<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(make_view<T>(g));
     }
+}
+
+// Mean duration of `reps` launches of the graph's current label pass, timed with events.
+// The pass reads whatever vertices the workspace holds (any values give the same work).
+template <typename T, int KMAX>
+static float time_label_pass(gfw_graph_s *g, hipStream_t st, int reps)
+{
+    if constexpr (KMAX > 16) {
+        return 0.0f;
+    } else {
+        static const bool lds_set = (set_lds_limits<T, KMAX>(), true);
+        (void)lds_set;
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return -1.0f;
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return -1.0f;
+        }
+        launch_label<T, KMAX>(g, st); // warm-up
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps; ++r) launch_label<T, KMAX>(g, st);
+        (void)hipEventRecord(e1, st);
+        float ms = -1.0f;
+        if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return ms < 0.0f ? -1.0f : 1e3f * ms / (float)reps;
+    }
+}
+
+template <typename T>
+static float time_label_any(gfw_graph_s *g, hipStream_t st, int reps)
+{
+    switch (g->shape.kmax) {
+    case 4: return time_label_pass<T, 4>(g, st, reps);
+    case 8: return time_label_pass<T, 8>(g, st, reps);
+    case 16: return time_label_pass<T, 16>(g, st, reps);
+    default: return 0.0f;
+    }
+}
+
+// Measured choice of the label pass: both passes run on the graph itself (the column-sorted
+// copy is built if needed) and the faster one is kept.  Both give the same Q bit for bit.
+static gfw_status_t measure_label_paths(gfw_graph_s *g, hipStream_t st)
+{
+    if (g->K > 16) { // one label pass for many classes
+        g->label_path = 0;
+        return GFW_OK;
+    }
+    gfw_status_t s = choose_label_path(g, 2, st); // builds the sorted tiles once
+    if (s != GFW_OK) {
+        g->label_path = 0; // a row too long for the sorted tiles: the plain pass it is
+        return GFW_OK;
+    }
+    if ((s = ensure_workspace(g, 0)) != GFW_OK) return s;
+    Workspace &w = g->ws;
+    Ctl c;
+    std::memset(&c, 0, sizeof(c));
+    c.active = 1;
+    c.last_eval = -1;
+    GFW_HIP_TRY(hipMemcpyAsync(w.ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
+    GFW_HIP_TRY(hipMemsetAsync(w.s0, 0, g->n, st));
+    GFW_HIP_TRY(hipMemsetAsync(w.s4, 0, (size_t)(g->n + 1) / 2, st));
+    constexpr int reps = 5;
+    float us[2];
+    for (int path = 0; path < 2; ++path) {
+        g->label_path = path;
+        us[path] = g->dtype == GFW_F32 ? time_label_any<float>(g, st, reps) : time_label_any<double>(g, st, reps);
+        GFW_HIP_TRY(hipGetLastError());
+        if (us[path] < 0.0f) return fail(GFW_E_HIP, "timing the label passes failed");
+    }
+    g->label_us[0] = us[0];
+    g->label_us[1] = us[1];
+    g->label_path = us[1] < us[0] ? 1 : 0;
+    return GFW_OK;
 }
 
 template <typename T>
@@ -946,7 +1025,7 @@ gfw_status_t gfw_graph_tune(gfw_graph_t g, gfw_tune_t key, int64_t value)
 {
     if (!g) return fail(GFW_E_INVALID_ARG, "graph is NULL");
     if (key != GFW_TUNE_LABEL_PATH) return fail(GFW_E_INVALID_ARG, "unknown tuning key %d", (int)key);
-    if (value < 0 || value > 2) return fail(GFW_E_INVALID_ARG, "label path must be 0, 1 or 2");
+    if (value < 0 || value > 3) return fail(GFW_E_INVALID_ARG, "label path must be 0, 1, 2 or 3");
     GFW_HIP_TRY(hipSetDevice(g->ctx->device));
     const int before = g->label_path;
     gfw_status_t s = choose_label_path(g, (int)value, nullptr);
@@ -960,9 +1039,12 @@ gfw_status_t gfw_graph_tune(gfw_graph_t g, gfw_tune_t key, int64_t value)
 gfw_status_t gfw_graph_query(gfw_graph_t g, gfw_tune_t key, int64_t *value)
 {
     if (!g || !value) return fail(GFW_E_INVALID_ARG, "NULL argument");
-    if (key != GFW_TUNE_LABEL_PATH) return fail(GFW_E_INVALID_ARG, "unknown tuning key %d", (int)key);
-    *value = g->label_path == 1 ? 2 : 1;
-    return GFW_OK;
+    switch (key) {
+    case GFW_TUNE_LABEL_PATH: *value = g->label_path == 1 ? 2 : 1; return GFW_OK;
+    case GFW_TUNE_LABEL_PLAIN_NS: *value = (int64_t)(1e3 * g->label_us[0]); return GFW_OK;
+    case GFW_TUNE_LABEL_SORTED_NS: *value = (int64_t)(1e3 * g->label_us[1]); return GFW_OK;
+    default: return fail(GFW_E_INVALID_ARG, "unknown tuning key %d", (int)key);
+    }
 }
 
 gfw_status_t gfw_solve(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm, void *U_out, int32_t *labels_out,

@@ -114,6 +114,7 @@ struct gfw_graph_s {
     int32_t *gcol = nullptr;      // int32[nnz], columns sorted within each tile
     uint16_t *gpos = nullptr;     // uint16[nnz], CSR offset inside the tile
     double locality = 0.0;        // mean distinct 128-node label lines per 64 consecutive entries
+    float label_us[2] = {0, 0};   // measured launch times of the plain and sorted passes (0: not measured)
     int diag_one = 1;           // 1: operator is I + A (kind W); 0: operator is A (kind L)
     gfw::Shape shape;
     gfw::Workspace ws;

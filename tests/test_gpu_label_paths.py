@@ -73,3 +73,22 @@ def test_auto_choice():
     grid = graphs.image_grid(20000, 4, 1, neighbours=4)
     G = gpu_graph(grid, 4, [0], [0], gfw.F32)
     assert G.query(gfw.TUNE_LABEL_PATH) == 1  # small and local: plain pass
+
+
+def test_measured_choice():
+    """Value 3 times both passes on the graph and keeps the faster; the solve is the same
+    whichever is kept."""
+    say("[gpu] measured label path choice")
+    g = graphs.sbm_by_degree(200000, 5, 24.0, 8.0, 31)
+    idx, lab = graphs.stratified_labels(g.truth, 5, 0.01, 31)
+    G = gpu_graph(g, 5, idx, lab, gfw.F32)
+    prm = gfw.params(max_iter=20, tol=-1)
+    G.tune(gfw.TUNE_LABEL_PATH, gfw.LABEL_PATH_PLAIN)
+    ref = _np(gfw.solve(ctx(), G, prm)["U"])
+    G.tune(gfw.TUNE_LABEL_PATH, gfw.LABEL_PATH_MEASURED)
+    plain_ns, sorted_ns = G.query(gfw.TUNE_LABEL_PLAIN_NS), G.query(gfw.TUNE_LABEL_SORTED_NS)
+    chosen = G.query(gfw.TUNE_LABEL_PATH)
+    say(f"[gpu] measured: plain {plain_ns / 1e3:.1f} us, sorted {sorted_ns / 1e3:.1f} us, chosen {chosen}")
+    assert plain_ns > 0 and sorted_ns > 0
+    assert chosen == (2 if sorted_ns < plain_ns else 1)
+    np.testing.assert_array_equal(_np(gfw.solve(ctx(), G, prm)["U"]), ref)
