@@ -23,6 +23,8 @@
 
 namespace gfw {
 
+typedef unsigned v4u __attribute__((ext_vector_type(4))); // 16-byte vector moves
+
 constexpr int kRowBlock = 256;     // threads per block of the row-wise kernels
 constexpr int kFinishThreads = 512;
 constexpr int kRowParts = 5;       // per-row partial sums written by the row kernel
@@ -301,24 +303,24 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
     const bool full = rows == kRowBlock;
     if (full) {
         const int nvec = cnt / VE;
-        const uint4 *gu = reinterpret_cast<const uint4 *>(U + base);
-        const uint4 *gp = reinterpret_cast<const uint4 *>(P + base);
-        const uint4 *gq = reinterpret_cast<const uint4 *>(Q + base);
-        uint4 vu[VPT], vp[VPT], vq[VPT];
+        const v4u *gu = reinterpret_cast<const v4u *>(U + base);
+        const v4u *gp = reinterpret_cast<const v4u *>(P + base);
+        const v4u *gq = reinterpret_cast<const v4u *>(Q + base);
+        v4u vu[VPT], vp[VPT], vq[VPT];
 #pragma unroll
         for (int m = 0; m < VPT; ++m) {
             const int v = min(tid + m * kRowBlock, nvec - 1);
-            vu[m] = gu[v];
-            vp[m] = gp[v];
-            vq[m] = gq[v]; // Q is only used when an update is pending (every iteration but the first)
+            vu[m] = __builtin_nontemporal_load(gu + v);
+            vp[m] = __builtin_nontemporal_load(gp + v);
+            vq[m] = __builtin_nontemporal_load(gq + v); // Q is only used when an update is pending (every iteration but the first)
         }
 #pragma unroll
         for (int m = 0; m < VPT; ++m) {
             const int v = tid + m * kRowBlock;
             if (v < nvec) {
-                reinterpret_cast<uint4 *>(lu)[v] = vu[m];
-                reinterpret_cast<uint4 *>(lp)[v] = vp[m];
-                reinterpret_cast<uint4 *>(lq)[v] = vq[m];
+                reinterpret_cast<v4u *>(lu)[v] = vu[m];
+                reinterpret_cast<v4u *>(lp)[v] = vp[m];
+                reinterpret_cast<v4u *>(lq)[v] = vq[m];
             }
         }
     } else {
@@ -449,14 +451,14 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
     if (pending) {
         if (full) {
             const int nvec = cnt / VE;
-            uint4 *gu = reinterpret_cast<uint4 *>(U + base);
-            uint4 *gp = reinterpret_cast<uint4 *>(P + base);
+            v4u *gu = reinterpret_cast<v4u *>(U + base);
+            v4u *gp = reinterpret_cast<v4u *>(P + base);
 #pragma unroll
             for (int m = 0; m < VPT; ++m) {
                 const int v = tid + m * kRowBlock;
                 if (v < nvec) {
-                    gu[v] = reinterpret_cast<const uint4 *>(lu)[v];
-                    gp[v] = reinterpret_cast<const uint4 *>(lp)[v];
+                    __builtin_nontemporal_store(reinterpret_cast<const v4u *>(lu)[v], gu + v);
+                    __builtin_nontemporal_store(reinterpret_cast<const v4u *>(lp)[v], gp + v);
                 }
             }
         } else {
