@@ -141,7 +141,8 @@ def derive_traffic(d: str) -> int:
     src_hash = kernel_sources_hash()
     out = {"calibration": {"copy_bytes": 1 << 30, "fetch_kib_per_copy": copy_fetch, "write_kib_per_copy": copy_write,
                            "fetch_scale": fetch_scale, "write_scale": write_scale, "dispatches": [nf, nw]}}
-    for key, pat in (("label", "k_label_sorted<"), ("row", "k_row<"), ("finish", "k_finish")):
+    for key, pat in (("label", "k_label_sorted<"), ("row", "k_row<"), ("finish", "k_finish("),
+                     ("row_big", "k_row_big<")):
         f, nfd = mean_for("label_fetch", "FETCH_SIZE", lambda k: pat in k)
         w, nwd = mean_for("label_write", "WRITE_SIZE", lambda k: pat in k)
         out[key] = {"source_hash": src_hash, "fetch_kib_raw": f, "write_kib_raw": w,
@@ -213,12 +214,13 @@ def bench_many_classes(gfw, ctx, steps: int = 3, n: int = 100_000, K: int = 585)
     achieved = row_bytes / (per["row"] * 1e-6) / 1e9
     acc = float(np.mean(last["labels"].cpu().numpy() == g.truth))
     G.close()
+    traffic = traffic_from_profile("row_big", kernel_sources_hash())
     return {"workload": f"lfr_many_classes: LFR-shaped network n={g.n}, nnz={g.nnz}, K={K}, 5% labelled, FP32, "
                         f"{prob.max_iter} iterations", "fw_iters_per_s": round(traced, 1),
             "untraced_fw_iters_per_s": round(untraced, 1), "kernels_us": per,
             "roofline": {"bound": "hbm", "kernel": "k_row_big", "algorithmic_bytes_per_launch": row_bytes,
                          "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(achieved / HBM_PEAK_GBS, 4)},
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
             "accuracy": round(acc, 4)}
 
 
