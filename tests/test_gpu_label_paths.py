@@ -11,7 +11,7 @@ from oracle import oracle as O
 from paper_2508_09738_amd import gfw
 from synth import configs, graphs
 
-from gpu_helpers import ctx, gpu_graph, say, torch_u
+from gpu_helpers import ctx, gpu_graph, lockstep, say, torch_u
 
 pytestmark = pytest.mark.gpu
 
@@ -92,3 +92,32 @@ def test_measured_choice():
     assert plain_ns > 0 and sorted_ns > 0
     assert chosen == (2 if sorted_ns < plain_ns else 1)
     np.testing.assert_array_equal(_np(gfw.solve(ctx(), G, prm)["U"]), ref)
+
+
+def test_row_longer_than_a_sorted_tile():
+    """A hub with 70,000 neighbours does not fit a column-sorted tile (65,536 entries): the
+    sorted pass is refused, the measured choice falls back to the plain pass, and the solve
+    still follows the oracle."""
+    say("[gpu] hub row beyond the sorted tile size")
+    import scipy.sparse as sp
+    rng = np.random.default_rng(5)
+    n, K, hub = 90000, 3, 0
+    nb = rng.choice(np.arange(1, n), 70000, replace=False)
+    a = np.concatenate([np.zeros(nb.size, np.int64), rng.integers(1, n, 200000)])
+    b = np.concatenate([nb, rng.integers(1, n, 200000)])
+    keep = a != b
+    W = sp.coo_matrix((np.ones(keep.sum()), (a[keep], b[keep])), shape=(n, n)).tocsr()
+    W = ((W + W.T) > 0).astype(np.float64).tocsr()
+    W.sort_indices()
+    truth = rng.integers(0, K, n).astype(np.int32)
+    g = graphs.Graph(n, K, W.indptr.astype(np.int64), W.indices.astype(np.int32), W.data, truth)
+    assert np.diff(g.indptr)[hub] > 65536
+    idx, lab = graphs.stratified_labels(truth, K, 0.01, 5)
+    G = gpu_graph(g, K, idx, lab, gfw.F64)
+    with pytest.raises(gfw.GfwError) as e:
+        G.tune(gfw.TUNE_LABEL_PATH, gfw.LABEL_PATH_SORTED)
+    assert e.value.status == -6
+    G.tune(gfw.TUNE_LABEL_PATH, gfw.LABEL_PATH_MEASURED)
+    assert G.query(gfw.TUNE_LABEL_PATH) == 1
+    prob = configs.Problem(g, idx, lab, K, "f64", 50.0, 1000.0, 20, 1e-6, "hub")
+    lockstep(prob, gfw.F64, [0, 5, 15], label="hub")
