@@ -42,15 +42,18 @@ def torch_u(U, dtype):
 def glmo_margin(U, G, mode=O.LMO_GREEDY):
     """Per row: gap between the smallest and second smallest G over the GLMO's candidate set
     (inf where there is a single candidate or the row is kept as binary)."""
-    n, K = U.shape
-    m = np.full(n, np.inf)
-    for i in range(n):
-        binary = np.all((U[i] == 0) | (U[i] == 1))
-        if binary and mode == O.LMO_GREEDY:
-            continue
-        cand = np.sort(G[i][(U[i] != 0) | (mode == O.LMO_FULL)])
-        if cand.size >= 2:
-            m[i] = cand[1] - cand[0]
+    binary = np.all((U == 0) | (U == 1), axis=1)
+    cand = (U != 0) if mode == O.LMO_GREEDY else np.ones(U.shape, dtype=bool)
+    Gm = np.where(cand, G, np.inf)
+    if U.shape[1] >= 2:
+        two = np.partition(Gm, 1, axis=1)[:, :2]
+        with np.errstate(invalid="ignore"):
+            m = two[:, 1] - two[:, 0]
+    else:
+        m = np.full(U.shape[0], np.inf)
+    m[cand.sum(axis=1) < 2] = np.inf
+    if mode == O.LMO_GREEDY:
+        m[binary] = np.inf
     return m
 
 
