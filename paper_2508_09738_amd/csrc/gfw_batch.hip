@@ -19,6 +19,7 @@
 #include <string>
 
 #include "gfw_internal.h"
+#include "gfw_kernels_bigk.h"
 
 namespace gfw {
 
@@ -36,6 +37,13 @@ static void set_batch_lds_limits()
 // --------------------------------------------------------------------------------------
 
 static int bucket_of(int kmax) { return kmax == 4 ? 0 : kmax == 8 ? 1 : 2; }
+// K > 16: classes per lane rounded up to 1, 2, 4, 8 or 16
+constexpr int kBigBuckets = 5;
+static int big_bucket_of(int kmax)
+{
+    const int mc = kmax / 64;
+    return mc <= 1 ? 0 : mc <= 2 ? 1 : mc <= 4 ? 2 : mc <= 8 ? 3 : 4;
+}
 
 // A grow-only device array (kept across macro-steps of the server).
 template <typename E>
@@ -62,13 +70,14 @@ template <typename T>
 struct BatchTables {
     std::vector<GraphView<T>> views;
     std::vector<TileRef> rows[3], plain[3], sorted[3], all_rows;
+    std::vector<TileRef> big_rows[kBigBuckets], big_lab; // K > 16: row tiles per MC bucket, 256-row label tiles
     // host staging of the per-graph control blocks, U_0 pointers and label destinations; kept
     // here so that they outlive the asynchronous copies that read them
     std::vector<Ctl> ctl0;
     std::vector<const T *> u0;
     std::vector<int32_t *> lab_out;
     DevArr<GraphView<T>> dv;
-    DevArr<TileRef> drows[3], dplain[3], dsorted[3], dall;
+    DevArr<TileRef> drows[3], dplain[3], dsorted[3], dall, dbig[kBigBuckets], dbiglab;
     DevArr<int32_t> dflag;
     DevArr<const T *> dU0;
     DevArr<int32_t *> dlab;
@@ -78,6 +87,7 @@ struct BatchTables {
     // device pointers of the current contents
     GraphView<T> *d_views = nullptr;
     TileRef *d_rows[3] = {}, *d_plain[3] = {}, *d_sorted[3] = {}, *d_all = nullptr;
+    TileRef *d_big[kBigBuckets] = {}, *d_biglab = nullptr;
     int32_t *d_flag = nullptr;
     const T **d_U0 = nullptr;
     int32_t **d_lab_out = nullptr;
@@ -92,6 +102,8 @@ struct BatchTables {
             sorted[b].clear();
         }
         all_rows.clear();
+        for (int b = 0; b < kBigBuckets; ++b) big_rows[b].clear();
+        big_lab.clear();
         d_U0 = nullptr;
         d_lab_out = nullptr;
     }
@@ -116,8 +128,28 @@ static gfw_status_t upload(std::vector<E> &v, DevArr<E> &arr, E **d, hipStream_t
 }
 
 template <typename T>
+static void batch_big_launch(BatchTables<T> &bt, int kind, int flag, hipStream_t st)
+{
+    // kind 0: row kernel (flag = apply_only); kind 1: SpMM (flag = to_q)
+#define GFW_BIG_BUCKET(B, MC)                                                                                    \
+    if (!bt.big_rows[B].empty()) {                                                                             \
+        if (kind == 0)                                                                                         \
+            k_row_big_batch<T, MC><<<bt.big_rows[B].size(), kBigThreads, 0, st>>>(bt.d_views, bt.d_big[B], flag); \
+        else                                                                                                   \
+            k_spmm_big_batch<T, MC><<<bt.big_rows[B].size(), kBigThreads, 0, st>>>(bt.d_views, bt.d_big[B], flag); \
+    }
+    GFW_BIG_BUCKET(0, 1)
+    GFW_BIG_BUCKET(1, 2)
+    GFW_BIG_BUCKET(2, 4)
+    GFW_BIG_BUCKET(3, 8)
+    GFW_BIG_BUCKET(4, 16)
+#undef GFW_BIG_BUCKET
+}
+
+template <typename T>
 static void batch_row_launch(BatchTables<T> &bt, int apply_only, hipStream_t st)
 {
+    batch_big_launch<T>(bt, 0, apply_only, st);
     if (!bt.rows[0].empty())
         k_row_batch<T, uint8_t, 4><<<bt.rows[0].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 4, st>>>(
             bt.d_views, bt.d_rows[0], apply_only);
@@ -147,6 +179,7 @@ static void batch_iteration(BatchTables<T> &bt, hipStream_t st)
     batch_label_bucket<T, 4>(bt, 0, st);
     batch_label_bucket<T, 8>(bt, 1, st);
     batch_label_bucket<T, 16>(bt, 2, st);
+    if (!bt.big_lab.empty()) k_label_big_batch<T><<<bt.big_lab.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_biglab);
     k_finish_batch<T><<<bt.views.size(), kFinishThreads, 0, st>>>(bt.d_views);
 }
 
@@ -173,14 +206,23 @@ static gfw_status_t batch_prepare(BatchTables<T> &bt, int32_t count, gfw_graph_s
         gfw_graph_s *g = gs[i];
         const gfw_params_t *prm = prms[i];
         bt.views.push_back(make_view<T>(g));
-        const int b = bucket_of(g->shape.kmax);
-        for (int32_t t = 0; t < g->shape.nb_row; ++t) {
-            bt.rows[b].push_back({i, t});
-            bt.all_rows.push_back({i, t});
-            if (g->label_path != 1) bt.plain[b].push_back({i, t});
+        if (g->K > 16) {
+            const int b = big_bucket_of(g->shape.kmax);
+            for (int32_t t = 0; t < g->shape.nb_big; ++t) bt.big_rows[b].push_back({i, t});
+            for (int32_t t = 0; t < g->shape.nb_row; ++t) {
+                bt.big_lab.push_back({i, t});
+                bt.all_rows.push_back({i, t});
+            }
+        } else {
+            const int b = bucket_of(g->shape.kmax);
+            for (int32_t t = 0; t < g->shape.nb_row; ++t) {
+                bt.rows[b].push_back({i, t});
+                bt.all_rows.push_back({i, t});
+                if (g->label_path != 1) bt.plain[b].push_back({i, t});
+            }
+            if (g->label_path == 1)
+                for (int32_t t = 0; t < g->n_tiles; ++t) bt.sorted[b].push_back({i, t});
         }
-        if (g->label_path == 1)
-            for (int32_t t = 0; t < g->n_tiles; ++t) bt.sorted[b].push_back({i, t});
         if (init_state) {
             Ctl &c = ctl0[(size_t)i];
             std::memset(&c, 0, sizeof(c));
@@ -208,6 +250,9 @@ static gfw_status_t batch_prepare(BatchTables<T> &bt, int32_t count, gfw_graph_s
         if ((s = upload(bt.sorted[b], bt.dsorted[b], &bt.d_sorted[b], st)) != GFW_OK) return s;
     }
     if ((s = upload(bt.all_rows, bt.dall, &bt.d_all, st)) != GFW_OK) return s;
+    for (int b = 0; b < kBigBuckets; ++b)
+        if ((s = upload(bt.big_rows[b], bt.dbig[b], &bt.d_big[b], st)) != GFW_OK) return s;
+    if ((s = upload(bt.big_lab, bt.dbiglab, &bt.d_biglab, st)) != GFW_OK) return s;
     if (labels_out && (s = upload(lab_out, bt.dlab, &bt.d_lab_out, st)) != GFW_OK) return s;
     if ((s = bt.dflag.reserve(1)) != GFW_OK) return s;
     bt.d_flag = bt.dflag.p;
@@ -222,6 +267,7 @@ static gfw_status_t batch_prepare(BatchTables<T> &bt, int32_t count, gfw_graph_s
         if (!bt.rows[1].empty()) k_spmm_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
         if (!bt.rows[2].empty())
             k_spmm_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
+        batch_big_launch<T>(bt, 1, 0, st);
         GFW_HIP_TRY(hipGetLastError());
     }
     if (max_iter_out) *max_iter_out = max_iter;
@@ -283,6 +329,7 @@ static gfw_status_t batch_collect(BatchTables<T> &bt, bool labels, std::vector<d
     if (!bt.rows[1].empty()) k_spmm_to_q_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
     if (!bt.rows[2].empty())
         k_spmm_to_q_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
+    batch_big_launch<T>(bt, 1, 1, st);
     k_energy_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all);
     gfw_status_t s;
     if ((s = bt.dE.reserve(count)) != GFW_OK || (s = bt.dctl_out.reserve(count)) != GFW_OK) return s;
@@ -357,8 +404,10 @@ static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter, bool w
     const size_t nb = (size_t)cdiv(p->n, kRowBlock);
     size_t graph = 4 * (n + 1) + (4 + v) * nnz + 4 * n;
     if (p->nnz >= ((int64_t)4 << 20)) graph += 6 * nnz + 4 * (n + 2); // column-sorted copy and its tiles
-    const size_t solve = 3 * v * n * K + 2 * n + 8 * ((size_t)(kRowParts + 4) * nb + 64) + sizeof(Ctl) +
-                         8 * 5 * ((size_t)max_iter + 1) + 4096;
+    const size_t nb_parts = K > 16 ? std::max(nb, (size_t)cdiv(p->n, kBigRowsPerBlock)) : nb;
+    const size_t solve = 3 * v * n * K + (K > 16 ? 4 * n + 2 * nnz : 2 * n) + n / 2 + 16 +
+                         8 * ((size_t)(kRowParts + 4) * nb_parts + 64) + sizeof(Ctl) + 8 * 5 * ((size_t)max_iter + 1) +
+                         4096;
     return graph + solve + (warm ? v * n * K : 0); // a warm start holds its U_0 until retirement
 }
 
@@ -632,7 +681,6 @@ gfw_status_t gfw_solve_batched(gfw_context_t ctx, int32_t count, const gfw_graph
         if (!graphs[i]) return fail(GFW_E_INVALID_ARG, "graph %d is NULL", i);
         if (graphs[i]->ctx != ctx) return fail(GFW_E_INVALID_ARG, "graph %d belongs to another context", i);
         if (graphs[i]->dtype != graphs[0]->dtype) return fail(GFW_E_UNSUPPORTED, "a batch must share one dtype");
-        if (graphs[i]->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by the batched solver");
         ps[(size_t)i] = shared_params ? prm : prm + i;
         gfw_status_t s = check_params(ps[(size_t)i], graphs[i]->K);
         if (s != GFW_OK) return s;
@@ -685,7 +733,6 @@ gfw_status_t gfw_server_submit(gfw_server_t sv, const gfw_problem_t *p, const gf
     if (s != GFW_OK) return s;
     if ((s = check_params(prm, p->K)) != GFW_OK) return s;
     if (prm->p_refresh) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported by the server");
-    if (p->K > 16) return fail(GFW_E_UNSUPPORTED, "K > 16 is not supported by the server");
     const size_t fp = request_footprint(p, prm->max_iter, prm->U0 != nullptr);
     if (fp > sv->budget) return fail(GFW_E_BUDGET, "request needs %zu bytes, budget is %zu", fp, sv->budget);
     auto *r = new (std::nothrow) ServerRequest();

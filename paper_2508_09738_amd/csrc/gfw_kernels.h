@@ -1120,7 +1120,8 @@ template <typename T>
 static __global__ void __launch_bounds__(kFinishThreads) k_finish_batch(const GraphView<T> *__restrict__ views)
 {
     const GraphView<T> &gv = views[blockIdx.x];
-    finish_body(gv.row_part, gv.nb_row, gv.lab_part, gv.n_tiles > 0 ? gv.n_tiles : gv.nb_row, gv.ctl);
+    finish_body(gv.row_part, gv.nb_big > 0 ? gv.nb_big : gv.nb_row, gv.lab_part, gv.n_tiles > 0 ? gv.n_tiles : gv.nb_row,
+                gv.ctl);
 }
 
 // labels_i = lowest-index argmax_c U_ic; s_out = vertex indices of the last GLMO output

@@ -331,4 +331,34 @@ static __global__ void __launch_bounds__(kBigThreads) k_spmm_big(GraphView<T> gv
     spmm_big_body<T, MC>(gv, Uin, Pout, blockIdx.x);
 }
 
+// Batched forms: workgroup -> (graph, tile) through the TileRef table, the same bodies on
+// the same tiles as the single-graph kernels.  A graph's results do not depend on MC as long
+// as 64 * MC >= K (the slots past K take no part in any sum), so a batch groups graphs into
+// a few MC buckets.
+template <typename T, int MC>
+static __global__ void __launch_bounds__(kBigThreads) k_row_big_batch(const GraphView<T> *__restrict__ views,
+                                                                      const TileRef *__restrict__ refs, int apply_only)
+{
+    const TileRef r = refs[blockIdx.x];
+    row_big_body<T, MC>(views[r.graph], r.tile, apply_only);
+}
+
+template <typename T>
+static __global__ void __launch_bounds__(kRowBlock) k_label_big_batch(const GraphView<T> *__restrict__ views,
+                                                                      const TileRef *__restrict__ refs)
+{
+    const TileRef r = refs[blockIdx.x];
+    label_big_body<T>(views[r.graph], r.tile);
+}
+
+// P = L_s U (to_q = 0, start of a solve) or Q = L_s U (to_q = 1, objective of the result)
+template <typename T, int MC>
+static __global__ void __launch_bounds__(kBigThreads) k_spmm_big_batch(const GraphView<T> *__restrict__ views,
+                                                                       const TileRef *__restrict__ refs, int to_q)
+{
+    const TileRef r = refs[blockIdx.x];
+    const GraphView<T> &gv = views[r.graph];
+    spmm_big_body<T, MC>(gv, gv.U, to_q ? gv.Q : gv.P, r.tile);
+}
+
 } // namespace gfw

@@ -66,3 +66,21 @@ def test_batch_rejects_duplicates_and_mixed_dtypes():
     with pytest.raises(gfw.GfwError) as e:
         gfw.solve_batched(ctx(), [G0, G1], gfw.params())
     assert e.value.status == -6
+
+
+def test_batch_with_many_classes_equals_alone_bitwise():
+    """Graphs with K > 16 (LFR-shaped, one of every classes-per-lane bucket) in one batch with
+    small-K graphs: each result is bitwise the result alone."""
+    say("[gpu] batch with many classes vs alone")
+    probs = _members(3, seed=12)
+    for j, K in enumerate((17, 100, 200, 300, 700)):
+        probs.append(configs.lfr_many_classes(seed=40 + j, n=max(2000, 4 * K), K=K, frac=0.05))
+    Gs = [gpu_graph(p.graph, p.K, p.labelled_idx, p.labels, gfw.F32) for p in probs]
+    prms = [gfw.params(max_iter=25 + 5 * i, tol=(1e-6 if i % 2 else -1.0)) for i in range(len(Gs))]
+    alone = [gfw.solve(ctx(), G, pr) for G, pr in zip(Gs, prms)]
+    batch = gfw.solve_batched(ctx(), Gs, prms)
+    for i, (a, b) in enumerate(zip(alone, batch)):
+        say(f"  member {i}: n={Gs[i].n} K={Gs[i].K} iters={a['iters']}")
+        np.testing.assert_array_equal(_np(a["U"]), _np(b["U"]))
+        np.testing.assert_array_equal(_np(a["labels"]), _np(b["labels"]))
+        assert a["iters"] == b["iters"] and a["objective"] == b["objective"] and a["gap"] == b["gap"]

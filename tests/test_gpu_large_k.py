@@ -4,7 +4,8 @@ mean about 5, power-law community sizes), the regime of the paper's LFR experime
 
 SpMM against the oracle's CSR loop; lockstep iterations (the per-iteration contract) with
 the GFW, full-LMO and exact-step variants; a free-running FP64 solve; the objective; the
-limits of the path (K = 17 and K = 1024, isolated nodes, no label pass choice, no batching)."""
+limits of the path (K = 17 and K = 1024, isolated nodes, one label pass).  Batched and
+served many-class problems are covered with the batch and server tests."""
 import numpy as np
 import pytest
 
@@ -121,9 +122,9 @@ def test_large_k_limits():
     # K = 17 (one class per lane, most lanes idle) in lockstep with the oracle
     prob = configs.lfr_many_classes(seed=17, n=1500, K=17, frac=0.05, max_iter=10)
     lockstep(prob, gfw.F64, [0, 4], label="K=17")
-    # the column-sorted label pass packs K <= 16; batching is limited to K <= 16
+    # the column-sorted label pass packs K <= 16: many classes keep the one pass they have
     with pytest.raises(gfw.GfwError):
         G.tune(gfw.TUNE_LABEL_PATH, 2)
     assert G.query(gfw.TUNE_LABEL_PATH) == 1
-    with pytest.raises(gfw.GfwError):
-        gfw.solve_batched(ctx(), [G], gfw.params(max_iter=5))
+    G.tune(gfw.TUNE_LABEL_PATH, 3)
+    assert G.query(gfw.TUNE_LABEL_PATH) == 1

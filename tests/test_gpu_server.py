@@ -94,3 +94,26 @@ def test_server_small_budget_serialises_but_completes():
         out.append(sv.poll(ts[-1]))
     assert all(r["iters"] == 12 for r in out)
     sv.close()
+
+
+def test_server_many_classes_request_equals_alone():
+    say("[gpu] server: many-classes request")
+    prob = configs.lfr_many_classes(seed=21, n=3000, K=120, frac=0.05)
+    small = _requests(2, 24)
+    prm = gfw.params(max_iter=30, tol=-1)
+    sv = gfw.Server(ctx(), 1 << 30, 8)
+    try:
+        g = prob.graph
+        t_big = sv.submit(g.n, prob.K, g.indptr, g.indices, g.data, prob.labelled_idx, prob.labels, prm)
+        ts = [_submit(sv, p, prm) for p in small]
+        r = sv.poll(t_big)
+        rs = [sv.poll(t) for t in ts]
+    finally:
+        sv.close()
+    G = gpu_graph(g, prob.K, prob.labelled_idx, prob.labels, gfw.F32)
+    alone = gfw.solve(ctx(), G, prm)
+    np.testing.assert_array_equal(r["U"], _np(alone["U"]))
+    np.testing.assert_array_equal(r["labels"], _np(alone["labels"]))
+    for p, rr in zip(small, rs):
+        Gp = gpu_graph(p.graph, p.K, p.labelled_idx, p.labels, gfw.F32)
+        np.testing.assert_array_equal(rr["U"], _np(gfw.solve(ctx(), Gp, prm)["U"]))
