@@ -212,18 +212,13 @@ gfw_status_t check_params(const gfw_params_t *p, int32_t K)
 // graph set-up
 // --------------------------------------------------------------------------------------
 
-static Shape shape_for(int64_t n, int64_t nnz, int32_t K)
+static Shape shape_for(int64_t n, int32_t K)
 {
     Shape s;
     // K <= 16: register buckets of the row-per-thread kernels; above: 64 * (classes per lane)
     s.kmax = K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : 64 * (int)cdiv(K, 64);
-    const double avg = (double)nnz / (double)n;
-    int l = 1;
-    while (l < 32 && l < avg * 0.25) l <<= 1;
-    s.lpr = l;
     s.nb_row = (int)cdiv(n, kRowBlock);
     s.nb_big = K > 16 ? (int)cdiv(n, kBigRowsPerBlock) : 0;
-    s.nb_csr = (int)std::min<int64_t>(cdiv(n, kRowBlock / s.lpr), 8192);
     return s;
 }
 
@@ -546,7 +541,7 @@ gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_
                             : form_operator<double>(g, (const double *)wraw, st);
     dfree(wraw);
     if (s != GFW_OK) return s;
-    g->shape = shape_for(n, nnz, p->K);
+    g->shape = shape_for(n, p->K);
     if ((s = choose_label_path(g, 0, st, p->location == GFW_HOST ? p->col_idx : nullptr)) != GFW_OK) return s;
     g->graph_bytes += 4 * (n + 1) + (4 + vs) * nnz + 4 * n;
     g->solve_bytes = 3 * vs * n * p->K + (p->K > 16 ? 4 * n + 2 * nnz : 2 * n) + sizeof(double) * ((kRowParts + 4) * g->shape.nb_row + 64) +

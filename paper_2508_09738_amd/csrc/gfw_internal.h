@@ -61,9 +61,7 @@ struct Workspace {
 // for that graph whatever else runs).
 struct Shape {
     int kmax = 4;       // register bucket for K: 4, 8, 16, or 64..1024 for the large-K kernels
-    int lpr = 8;        // lanes per row of the CSR kernels
     int nb_row = 1;     // 256-row blocks (row kernel, label passes, SpMM, set-up)
-    int nb_csr = 1;     // blocks of the CSR kernels
     int nb_big = 0;     // blocks of the large-K row kernel and SpMM (0 when K <= 16)
 };
 

@@ -75,25 +75,6 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int N>
-__device__ __forceinline__ void block_sum_store(double (&v)[N], double *out)
-{
-    __shared__ double red[kRowBlock / 64][N];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) red[wid][j] = v[j];
-    }
-    __syncthreads();
-    if (threadIdx.x < N) {
-        double s = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-}
-
 // ---------------------------------------------------------------------------------
 // set-up kernels (once per graph)
 // ---------------------------------------------------------------------------------
