@@ -54,3 +54,32 @@ def test_full_size_serving_grid_lockstep():
     say("[gpu] full size: 1024 x 1024 grid lockstep")
     prob = configs.serve_request(4, 0, side=1024, K=6)
     lockstep(prob, gfw.F32, [0, 3], label="grid1024")
+
+
+def test_full_size_knn_mixture():
+    """The k-NN workload at its full size (70,000 points in 784 dimensions, K = 10, about 1 M
+    entries, 500 iterations): lockstep (FP32) at three iterates, then free-running solves
+    against the oracle's.  In FP64 the GPU path follows the oracle: the same step sizes and
+    the objective to 1e-12.  In FP32, U and P are rounded to FP32 at every update (relative
+    2^-24 per update); over 500 updates the objective moves by up to sqrt(500) * 2^-24 * 10 =
+    1.3e-5 relative (the factor 10 covers the terms of E and the steps of an update)."""
+    say("[gpu] full size: k-NN mixture (graph built with blocked products on the GPU)")
+    prob = configs.knn_mixture(device="cuda")
+    lockstep(prob, gfw.F32, [0, 100, 400], label="knn70000")
+    ro = O.solve_problem(prob)
+    acc = np.mean(ro["labels"] == prob.graph.truth)
+    bound = {gfw.F64: 1e-12, gfw.F32: np.sqrt(prob.max_iter) * 2.0 ** -24 * 10}
+    for dt in (gfw.F64, gfw.F32):
+        G = gpu_graph(prob.graph, prob.K, prob.labelled_idx, prob.labels, dt)
+        rg = gfw.solve(ctx(), G, gfw.params(eps=prob.eps, omega0=prob.omega0, max_iter=prob.max_iter, tol=prob.tol),
+                       want_history=True)
+        agree = np.mean(np_of(rg["labels"]) == ro["labels"])
+        dE = abs(rg["objective"] - ro["objective"]) / abs(ro["objective"])
+        same_steps = np.array_equal(rg["alpha"][:ro["iters"]], ro["alpha"][:ro["iters"]])
+        say(f"[gpu] knn70000 dtype={dt}: iters {rg['iters']}/{ro['iters']}, label agreement {agree:.5f}, "
+            f"rel dE {dE:.3e}, same step sizes {same_steps}, oracle accuracy {acc:.4f}")
+        assert rg["iters"] == ro["iters"]
+        assert agree >= 0.999
+        assert dE <= bound[dt]
+        if dt == gfw.F64:
+            assert same_steps
