@@ -279,17 +279,54 @@ static gfw_status_t batch_prepare(BatchTables<T> &bt, int32_t count, gfw_graph_s
 // (one chunk behind) once no graph has work left.  *any_left reports whether some graph
 // may still have work.
 template <typename T>
-static gfw_status_t batch_run(BatchTables<T> &bt, int32_t iters, bool watch, hipStream_t st, bool *any_left)
+static gfw_status_t batch_run(BatchTables<T> &bt, int32_t iters, bool watch, hipStream_t st, bool *any_left,
+                              bool capture = false)
 {
     constexpr int chunk = 8;
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    for (int i = 0; i < 2; ++i) GFW_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
     const int count = (int)bt.views.size();
     const int reps = (int)cdiv(iters, chunk);
+    struct Res { // released on every return path
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        hipStream_t st = nullptr;
+        ~Res()
+        {
+            if (exec) {
+                (void)hipStreamSynchronize(st);
+                (void)hipGraphExecDestroy(exec);
+            }
+            for (int i = 0; i < 2; ++i)
+                if (ev[i]) (void)hipEventDestroy(ev[i]);
+        }
+    } res;
+    res.st = st;
+    // capture: the chunk of iterations is recorded once as a HIP graph (the batch tables do
+    // not change during the call) and replayed; iterations past a graph's stop are no-ops
+    hipGraphExec_t &exec = res.exec;
+    if (capture && reps >= 2) {
+        hipStream_t cs = nullptr;
+        GFW_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int c = 0; c < chunk; ++c) batch_iteration<T>(bt, cs);
+            e = hipStreamEndCapture(cs, &graph);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) return fail(GFW_E_HIP, "capturing the batched iteration failed: %s", hipGetErrorString(e));
+    }
+    hipEvent_t *ev = res.ev;
+    for (int i = 0; i < 2; ++i) GFW_HIP_TRY(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
     bool left = true;
     for (int r = 0; r < reps; ++r) {
         const int n_it = std::min(chunk, iters - r * chunk);
-        for (int c = 0; c < n_it; ++c) batch_iteration<T>(bt, st);
+        if (exec && n_it == chunk) {
+            GFW_HIP_TRY(hipGraphLaunch(exec, st));
+        } else {
+            for (int c = 0; c < n_it; ++c) batch_iteration<T>(bt, st);
+        }
         if (!watch) continue;
         k_any_active<T><<<1, 256, 0, st>>>(bt.d_views, count, bt.d_flag);
         GFW_HIP_TRY(hipMemcpyAsync(&bt.h_flag[r & 1], bt.d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -303,9 +340,8 @@ static gfw_status_t batch_run(BatchTables<T> &bt, int32_t iters, bool watch, hip
         }
     }
     GFW_HIP_TRY(hipGetLastError());
-    for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ev[i]);
     if (any_left) *any_left = left;
-    return GFW_OK;
+    return GFW_OK; // res waits for the replays before releasing the executable graph
 }
 
 // Commits every pending update (apply-only row pass) and clears the pending flags, so that
@@ -361,7 +397,7 @@ static gfw_status_t solve_batched_impl(gfw_context_s *cx, int32_t count, gfw_gra
     gfw_status_t s = batch_prepare<T>(bt, count, gs, prms, labels_out, st, true, &max_iter, &watch);
     if (s != GFW_OK) return s;
     // every graph advances in the same launches until its own stop
-    if ((s = batch_run<T>(bt, max_iter, watch, st, nullptr)) != GFW_OK) return s;
+    if ((s = batch_run<T>(bt, max_iter, watch, st, nullptr, true)) != GFW_OK) return s;
     batch_row_launch<T>(bt, 1, st); // commit the last pending updates
     if (U_out)
         for (int32_t i = 0; i < count; ++i)
