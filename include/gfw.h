@@ -17,8 +17,10 @@
  *
  * General conventions
  *  - Every call returns gfw_status_t; no C++ exception crosses this boundary.  On error
- *    gfw_last_error() returns a thread-local message.  All argument checks run before
- *    the first GPU launch of a call.
+ *    gfw_last_error() returns a thread-local message.  Scalar and O(n) checks run on the
+ *    host before any launch; the checks of the CSR entries (column range and order,
+ *    values, symmetry) run as a kernel on the uploaded copy, before the operator is
+ *    formed.  A failed call leaves nothing allocated.
  *  - Pointers are caller-owned.  Whether a problem's arrays live in host or device
  *    memory is stated by gfw_problem_t.location.  Output arrays of gfw_solve and
  *    gfw_objective are DEVICE pointers; the server's outputs are HOST pointers.
