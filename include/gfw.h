@@ -174,13 +174,22 @@ GFW_API gfw_status_t gfw_graph_footprint(gfw_graph_t g, size_t *graph_bytes, siz
 /* Implementation choices of a graph (results are identical whichever is chosen):
  *  GFW_TUNE_LABEL_PATH: 0 = automatic (chosen at gfw_graph_create from the graph's
  *    locality), 1 = plain label pass, 2 = column-sorted label pass (builds, once, a copy
- *    of the column indices sorted within tiles of rows; GFW_E_UNSUPPORTED if a row has more
- *    than 65536 entries), 3 = measured: times both passes on this graph (5 launches each,
- *    on the default stream, synchronising it) and keeps the faster.  K > 16 has one pass.
+ *    of the entries sorted by column within tiles of rows, 4 bytes per entry: the entry's
+ *    offset in the tile and its column relative to an anchor column per 64 sorted entries;
+ *    GFW_E_UNSUPPORTED if a row has more than 65536 entries), 3 = measured: times both
+ *    passes on this graph (5 launches each, on the default stream, synchronising it) and
+ *    keeps the faster.  K > 16 has one pass.
  * gfw_graph_query returns the current value of a key: GFW_TUNE_LABEL_PATH 1 or 2;
  * GFW_TUNE_LABEL_PLAIN_NS / GFW_TUNE_LABEL_SORTED_NS the mean launch times measured by
- * the last value-3 tuning, in ns (0 if none). */
-typedef enum { GFW_TUNE_LABEL_PATH = 0, GFW_TUNE_LABEL_PLAIN_NS = 1, GFW_TUNE_LABEL_SORTED_NS = 2 } gfw_tune_t;
+ * the last value-3 tuning, in ns (0 if none); GFW_TUNE_SORTED_WIDE_CHUNKS (query only) the
+ * number of 64-entry runs of the column-sorted copy whose columns span more than 65535, so
+ * that their entries read the column from the CSR instead (0 before the copy is built). */
+typedef enum {
+    GFW_TUNE_LABEL_PATH = 0,
+    GFW_TUNE_LABEL_PLAIN_NS = 1,
+    GFW_TUNE_LABEL_SORTED_NS = 2,
+    GFW_TUNE_SORTED_WIDE_CHUNKS = 3
+} gfw_tune_t;
 GFW_API gfw_status_t gfw_graph_tune(gfw_graph_t g, gfw_tune_t key, int64_t value);
 GFW_API gfw_status_t gfw_graph_query(gfw_graph_t g, gfw_tune_t key, int64_t *value);
 

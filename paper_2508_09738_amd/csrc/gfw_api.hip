@@ -231,8 +231,9 @@ void free_graph(gfw_graph_s *g)
     dfree(g->vals);
     dfree(g->lab);
     dfree(g->tile_rows);
-    dfree(g->gcol);
-    dfree(g->gpos);
+    dfree(g->tile_chunk);
+    dfree(g->ganch);
+    dfree(g->gword);
     Workspace &w = g->ws;
     dfree(w.U);
     dfree(w.P);
@@ -325,8 +326,14 @@ static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const 
     tr.push_back((int32_t)n);
     const int32_t nt = (int32_t)tr.size() - 1;
     const int64_t nnz = g->nnz;
-    std::vector<int32_t> sc((size_t)std::max<int64_t>(nnz, 1));
-    std::vector<uint16_t> sp((size_t)std::max<int64_t>(nnz, 1));
+    // chunks of kSortedChunk sorted entries, aligned to the start of each tile
+    std::vector<int32_t> tc((size_t)nt + 1);
+    tc[0] = 0;
+    for (int32_t t = 0; t < nt; ++t) tc[t + 1] = tc[t] + (int32_t)cdiv(rp[tr[t + 1]] - rp[tr[t]], kSortedChunk);
+    const int32_t nch = tc[nt];
+    std::vector<uint32_t> sw((size_t)std::max<int64_t>(nnz, 1));
+    std::vector<int32_t> an((size_t)std::max<int32_t>(nch, 1));
+    std::vector<int64_t> wide(16, 0);
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::thread> pool;
     for (unsigned w = 0; w < nth; ++w) {
@@ -337,32 +344,46 @@ static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const 
                 key.resize((size_t)(e1 - e0));
                 for (int64_t e = e0; e < e1; ++e) key[(size_t)(e - e0)] = ((uint64_t)(uint32_t)col[e] << 16) | (uint64_t)(e - e0);
                 std::sort(key.begin(), key.end());
-                for (int64_t e = e0; e < e1; ++e) {
-                    sc[(size_t)e] = (int32_t)(key[(size_t)(e - e0)] >> 16);
-                    sp[(size_t)e] = (uint16_t)(key[(size_t)(e - e0)] & 0xffff);
+                for (int64_t c0 = 0; c0 < e1 - e0; c0 += kSortedChunk) {
+                    const int64_t c1 = std::min<int64_t>(e1 - e0, c0 + kSortedChunk);
+                    const int32_t lo = (int32_t)(key[(size_t)c0] >> 16), hi = (int32_t)(key[(size_t)(c1 - 1)] >> 16);
+                    const bool fits = hi - lo <= 0xffff;
+                    an[(size_t)(tc[t] + c0 / kSortedChunk)] = fits ? lo : -1;
+                    wide[w] += fits ? 0 : 1;
+                    for (int64_t q = c0; q < c1; ++q) {
+                        const uint32_t off = (uint32_t)(key[(size_t)q] & 0xffff);
+                        const uint32_t dc = fits ? (uint32_t)((int32_t)(key[(size_t)q] >> 16) - lo) : 0u;
+                        sw[(size_t)(e0 + q)] = (dc << 16) | off;
+                    }
                 }
             }
         });
     }
     for (auto &th : pool) th.join();
     dfree(g->tile_rows);
-    dfree(g->gcol);
-    dfree(g->gpos);
+    dfree(g->tile_chunk);
+    dfree(g->ganch);
+    dfree(g->gword);
     g->tile_rows = nullptr;
-    g->gcol = nullptr;
-    g->gpos = nullptr;
+    g->tile_chunk = nullptr;
+    g->ganch = nullptr;
+    g->gword = nullptr;
     if (hipMalloc(&g->tile_rows, sizeof(int32_t) * (nt + 1)) != hipSuccess ||
-        hipMalloc(&g->gcol, sizeof(int32_t) * std::max<int64_t>(nnz, 4)) != hipSuccess ||
-        hipMalloc(&g->gpos, sizeof(uint16_t) * std::max<int64_t>(nnz, 8)) != hipSuccess)
+        hipMalloc(&g->tile_chunk, sizeof(int32_t) * (nt + 1)) != hipSuccess ||
+        hipMalloc(&g->ganch, sizeof(int32_t) * std::max<int32_t>(nch, 1)) != hipSuccess ||
+        hipMalloc(&g->gword, sizeof(uint32_t) * std::max<int64_t>(nnz, 1)) != hipSuccess)
         return fail(GFW_E_NOMEM, "device allocation for the sorted label pass failed");
     GFW_HIP_TRY(hipMemcpyAsync(g->tile_rows, tr.data(), sizeof(int32_t) * (nt + 1), hipMemcpyHostToDevice, st));
+    GFW_HIP_TRY(hipMemcpyAsync(g->tile_chunk, tc.data(), sizeof(int32_t) * (nt + 1), hipMemcpyHostToDevice, st));
     if (nnz) {
-        GFW_HIP_TRY(hipMemcpyAsync(g->gcol, sc.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
-        GFW_HIP_TRY(hipMemcpyAsync(g->gpos, sp.data(), sizeof(uint16_t) * nnz, hipMemcpyHostToDevice, st));
+        GFW_HIP_TRY(hipMemcpyAsync(g->ganch, an.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, st));
+        GFW_HIP_TRY(hipMemcpyAsync(g->gword, sw.data(), sizeof(uint32_t) * nnz, hipMemcpyHostToDevice, st));
     }
     GFW_HIP_TRY(hipStreamSynchronize(st));
     g->n_tiles = nt;
-    g->graph_bytes += sizeof(int32_t) * (nt + 1) + 6 * (size_t)nnz;
+    g->wide_chunks = 0;
+    for (int64_t x : wide) g->wide_chunks += x;
+    g->graph_bytes += sizeof(int32_t) * (2 * (size_t)(nt + 1) + (size_t)std::max<int32_t>(nch, 1)) + 4 * (size_t)nnz;
     return GFW_OK;
 }
 
@@ -403,7 +424,7 @@ static gfw_status_t choose_label_path(gfw_graph_s *g, int mode, hipStream_t st, 
         g->label_path = 0;
         return GFW_OK;
     }
-    if (!g->gcol) {
+    if (!g->gword) {
         std::vector<int32_t> rp((size_t)g->n + 1);
         GFW_HIP_TRY(hipMemcpyAsync(rp.data(), g->row_ptr, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToHost, st));
         GFW_HIP_TRY(hipStreamSynchronize(st));
@@ -1038,6 +1059,7 @@ gfw_status_t gfw_graph_query(gfw_graph_t g, gfw_tune_t key, int64_t *value)
     case GFW_TUNE_LABEL_PATH: *value = g->label_path == 1 ? 2 : 1; return GFW_OK;
     case GFW_TUNE_LABEL_PLAIN_NS: *value = (int64_t)(1e3 * g->label_us[0]); return GFW_OK;
     case GFW_TUNE_LABEL_SORTED_NS: *value = (int64_t)(1e3 * g->label_us[1]); return GFW_OK;
+    case GFW_TUNE_SORTED_WIDE_CHUNKS: *value = g->wide_chunks; return GFW_OK;
     default: return fail(GFW_E_INVALID_ARG, "unknown tuning key %d", (int)key);
     }
 }

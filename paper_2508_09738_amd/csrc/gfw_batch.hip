@@ -439,7 +439,9 @@ static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter, bool w
     const size_t n = (size_t)p->n, nnz = (size_t)p->nnz, K = (size_t)p->K;
     const size_t nb = (size_t)cdiv(p->n, kRowBlock);
     size_t graph = 4 * (n + 1) + (4 + v) * nnz + 4 * n;
-    if (p->nnz >= ((int64_t)4 << 20)) graph += 6 * nnz + 4 * (n + 2); // column-sorted copy and its tiles
+    // column-sorted copy (4 bytes per entry), its anchors (one per 64 entries, plus one
+    // partial run per tile) and two tile tables, with at most n tiles
+    if (p->nnz >= ((int64_t)4 << 20)) graph += 4 * nnz + 4 * (nnz / 64 + n + 1) + 8 * (n + 2);
     const size_t nb_parts = K > 16 ? std::max(nb, (size_t)cdiv(p->n, kBigRowsPerBlock)) : nb;
     const size_t solve = 3 * v * n * K + (K > 16 ? 4 * n + 2 * nnz : 2 * n) + n / 2 + 16 +
                          8 * ((size_t)(kRowParts + 4) * nb_parts + 64) + sizeof(Ctl) + 8 * 5 * ((size_t)max_iter + 1) +

@@ -108,9 +108,11 @@ struct gfw_graph_s {
     // column-sorted copy of the CSR for the label pass (see k_label_sorted)
     int label_path = 0;         // 0: plain (k_label), 1: column-sorted (k_label_sorted)
     int32_t n_tiles = 0;
-    int32_t *tile_rows = nullptr; // int32[n_tiles + 1]
-    int32_t *gcol = nullptr;      // int32[nnz], columns sorted within each tile
-    uint16_t *gpos = nullptr;     // uint16[nnz], CSR offset inside the tile
+    int32_t *tile_rows = nullptr;  // int32[n_tiles + 1]
+    int32_t *tile_chunk = nullptr; // int32[n_tiles + 1], first anchor of each tile
+    int32_t *ganch = nullptr;      // int32[chunks], anchor column of each 64-entry chunk, -1: wide
+    uint32_t *gword = nullptr;     // uint32[nnz], sorted within each tile: (col - anchor) << 16 | offset
+    int64_t wide_chunks = 0;       // chunks whose columns span more than 16 bits
     double locality = 0.0;        // mean distinct 128-node label lines per 64 consecutive entries
     float label_us[2] = {0, 0};   // measured launch times of the plain and sorted passes (0: not measured)
     int diag_one = 1;           // 1: operator is I + A (kind W); 0: operator is A (kind L)
@@ -159,8 +161,9 @@ GraphView<T> make_view(const gfw_graph_s *g)
     v.nb_big = g->shape.nb_big;
     v.n_tiles = g->label_path == 1 ? g->n_tiles : 0;
     v.tile_rows = g->tile_rows;
-    v.gcol = g->gcol;
-    v.gpos = g->gpos;
+    v.tile_chunk = g->tile_chunk;
+    v.ganch = g->ganch;
+    v.gword = g->gword;
     return v;
 }
 } // namespace gfw

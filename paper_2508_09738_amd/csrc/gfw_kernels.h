@@ -210,6 +210,7 @@ __device__ __forceinline__ void block_sum_store_strided(double (&v)[N], double *
 constexpr int kLabelTile = 2048; // CSR entries staged in LDS per step of the label pass
 constexpr int kSortedThreads = 1024;   // threads per tile of the column-sorted label pass
 constexpr int kSortedMaxEntries = 65536; // CSR entries per tile (16-bit positions, 64 KB of labels)
+constexpr int kSortedChunk = 64;         // column-sorted entries that share one anchor column
 
 // Everything a per-iteration kernel needs to know about one graph and its solve state.
 // The single-graph kernels take one view as an argument; the batched kernels look up the
@@ -231,8 +232,10 @@ struct GraphView {
     int32_t nb_row;   // 256-row tiles (row kernel, plain label pass, SpMM)
     int32_t nb_big;   // blocks of the large-K row kernel (stride of its partials)
     int32_t n_tiles;  // tiles of the column-sorted label pass (0: plain pass)
-    const int32_t *tile_rows, *gcol;
-    const uint16_t *gpos;
+    const int32_t *tile_rows;  // first row of each tile
+    const int32_t *tile_chunk; // first anchor of each tile
+    const int32_t *ganch;      // anchor column of each 64-entry chunk (-1: read the CSR column)
+    const uint32_t *gword;     // per column-sorted entry: (column - anchor) << 16 | CSR offset
 };
 
 // workgroup -> (graph, tile) of a batched launch
@@ -564,12 +567,17 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
 // Column-sorted label pass body: the same Q = L_s S and per-tile partial as label_body, for
 // graphs whose neighbour labels are scattered (random node order).  A workgroup owns one
 // tile of consecutive rows holding at most kSortedMaxEntries CSR entries.  The tile's
-// entries are stored twice: in CSR order (values) and sorted by column (gcol, with gpos the
-// entry's offset inside the tile's CSR range).
+// entries are stored twice: in CSR order (values) and sorted by column.  A column-sorted
+// entry is one 32-bit word: its offset inside the tile's CSR range (low 16 bits) and its
+// column minus the anchor of its chunk (high 16 bits), where the anchor is the first column
+// of each aligned run of kSortedChunk sorted entries.  A chunk whose columns span more than
+// 16 bits has anchor -1; its entries take their column from the CSR column array at their
+// offset instead.
 //  1. gather: consecutive threads take consecutive column-sorted entries, so the labels they
-//     load lie close together and share cache lines; labels are read from the packed
-//     two-per-byte copy (half the lines of the byte array) and each is written into an LDS
-//     array at the entry's CSR offset.
+//     load lie close together and share cache lines; a wavefront's 64 entries form one
+//     chunk, whose anchor is a scalar load; labels are read from the packed two-per-byte
+//     copy (half the lines of the byte array) and each is written into an LDS array at the
+//     entry's CSR offset.
 //  2. rows: each thread sums the histogram of one row at a time in CSR order, values read
 //     from global memory (a row's values are contiguous) and labels from LDS (the same
 //     order, hence the same result, as label_body), and writes the row of Q directly.
@@ -584,8 +592,8 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
     const int32_t K = gv.K;
     const int32_t *__restrict__ rp = gv.rp;
     const int32_t *__restrict__ tile_rows = gv.tile_rows;
-    const int32_t *__restrict__ gcol = gv.gcol;
-    const uint16_t *__restrict__ gpos = gv.gpos;
+    const uint32_t *__restrict__ gword = gv.gword;
+    const int32_t *__restrict__ ci = gv.ci;
     const T *__restrict__ a = gv.a;
     const int diag_one = gv.diag_one;
     const uint8_t *__restrict__ s4 = gv.s4;
@@ -603,22 +611,31 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
     const int rows = r1 - r0;
 
     // 1. gather labels in column order, scatter them to CSR positions in LDS
+    static_assert(kSortedThreads % kSortedChunk == 0 && kSortedChunk == 64, "a wavefront reads one chunk");
+    const int32_t *__restrict__ anch = gv.ganch + gv.tile_chunk[tile];
+    const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63); // first entry of the wavefront's chunk
     constexpr int G = 8;
     for (int b = 0; b < E; b += G * kSortedThreads) {
-        int32_t cc[G];
-        int pp[G];
+        uint32_t ww[G];
+        int32_t an[G];
 #pragma unroll
         for (int m = 0; m < G; ++m) {
+            // lanes past the end repeat the last entry, which lies in the wavefront's chunk
             const int e = min(b + tid + m * kSortedThreads, E - 1);
-            cc[m] = __builtin_nontemporal_load(gcol + e0 + e);
-            pp[m] = (int)__builtin_nontemporal_load(gpos + e0 + e);
+            ww[m] = __builtin_nontemporal_load(gword + e0 + e);
+            an[m] = anch[min(b + wbase + m * kSortedThreads, E - 1) / kSortedChunk];
         }
+        int32_t cc[G];
+#pragma unroll
+        for (int m = 0; m < G; ++m)
+            cc[m] = an[m] >= 0 ? an[m] + (int32_t)(ww[m] >> 16) : ci[e0 + (int32_t)(ww[m] & 0xffffu)];
         uint32_t ss[G];
 #pragma unroll
         for (int m = 0; m < G; ++m) ss[m] = (uint32_t)s4[cc[m] >> 1];
 #pragma unroll
         for (int m = 0; m < G; ++m)
-            if (b + tid + m * kSortedThreads < E) llab[pp[m]] = (uint8_t)((ss[m] >> ((cc[m] & 1) << 2)) & 15u);
+            if (b + tid + m * kSortedThreads < E)
+                llab[ww[m] & 0xffffu] = (uint8_t)((ss[m] >> ((cc[m] & 1) << 2)) & 15u);
     }
     __syncthreads();
 

@@ -33,7 +33,7 @@ EXPORTED = [
     "gfw_server_poll", "gfw_server_destroy", "gfw_trace_enable", "gfw_trace_reset", "gfw_trace_get",
     "gfw_graph_tune", "gfw_graph_query",
 ]
-TUNE_LABEL_PATH, TUNE_LABEL_PLAIN_NS, TUNE_LABEL_SORTED_NS = 0, 1, 2
+TUNE_LABEL_PATH, TUNE_LABEL_PLAIN_NS, TUNE_LABEL_SORTED_NS, TUNE_SORTED_WIDE_CHUNKS = 0, 1, 2, 3
 LABEL_PATH_AUTO, LABEL_PATH_PLAIN, LABEL_PATH_SORTED, LABEL_PATH_MEASURED = 0, 1, 2, 3
 KERNEL_ROW, KERNEL_LABEL, KERNEL_FINISH, KERNEL_SPMM = 0, 1, 2, 3
 

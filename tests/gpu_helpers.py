@@ -111,9 +111,11 @@ def np_of(t):
     return t.detach().cpu().numpy()
 
 
-def lockstep(prob, dtype, ks, lmo=O.LMO_GREEDY, ls=O.LS_ARMIJO, u_tol=None, label=""):
+def lockstep(prob, dtype, ks, lmo=O.LMO_GREEDY, ls=O.LS_ARMIJO, u_tol=None, label="", label_path=None):
     L = O.operator_for(prob.graph)
     G = gpu_graph(prob.graph, prob.K, prob.labelled_idx, prob.labels, dtype)
+    if label_path is not None:
+        G.tune(gfw.TUNE_LABEL_PATH, label_path)
     Uhat, omega = O.fidelity(prob.n, prob.K, prob.labelled_idx, prob.labels, prob.omega0)
     u_tol = u_tol if u_tol is not None else (1e-12 if dtype == gfw.F64 else 1e-5)
     # FP64 objectives: a sequential sum of the n*K per-entry terms (the oracle's) may be off by

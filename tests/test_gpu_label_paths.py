@@ -3,7 +3,8 @@
 Both passes sum every row's label histogram in CSR order, so Q = L_s S is the same; only the
 order of the per-tile partial sums differs.  Graphs here are forced onto the sorted path with
 gfw_graph_tune; they cover FP32/FP64, K = 2..16 (labels packed two per byte),
-rows without entries and a ragged last tile."""
+rows without entries, a ragged last tile, and runs of sorted entries whose columns span more
+than 16 bits (read through the CSR columns instead of the anchor)."""
 import numpy as np
 import pytest
 
@@ -121,3 +122,56 @@ def test_row_longer_than_a_sorted_tile():
     assert G.query(gfw.TUNE_LABEL_PATH) == 1
     prob = configs.Problem(g, idx, lab, K, "f64", 50.0, 1000.0, 20, 1e-6, "hub")
     lockstep(prob, gfw.F64, [0, 5, 15], label="hub")
+
+
+def _wide_graph(seed=9, n_dense=60000, n_sparse=140000, K=4):
+    """A random graph on the first n_dense nodes (mean degree about 12) plus a sparse region
+    of mostly isolated nodes, where every 4000th node links to 20 random nodes of the whole
+    graph.  The column-sorted tiles of the sparse region hold about a hundred entries spread
+    over all columns, so their 64-entry runs span more than 65,535 columns."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    n = n_dense + n_sparse
+    m = n_dense * 6
+    a = rng.integers(0, n_dense, m)
+    b = rng.integers(0, n_dense, m)
+    hubs = np.arange(n_dense, n, 4000)
+    a = np.concatenate([a, np.repeat(hubs, 20)])
+    b = np.concatenate([b, rng.integers(0, n, hubs.size * 20)])
+    keep = a != b
+    w = rng.uniform(0.5, 2.0, keep.sum())
+    W = sp.coo_matrix((w, (a[keep], b[keep])), shape=(n, n)).tocsr()
+    W = (W + W.T).tocsr()
+    W.sum_duplicates()
+    W.sort_indices()
+    truth = rng.integers(0, K, n).astype(np.int32)
+    return graphs.Graph(n, K, W.indptr.astype(np.int64), W.indices.astype(np.int32), W.data, truth)
+
+
+@pytest.mark.parametrize("dtype", [gfw.F32, gfw.F64])
+def test_sorted_wide_chunks_match_plain(dtype):
+    say(f"[gpu] sorted pass with wide chunks dtype={dtype}")
+    g = _wide_graph()
+    idx, lab = graphs.stratified_labels(g.truth, g.K, 0.02, 9)
+    G = gpu_graph(g, g.K, idx, lab, dtype)
+    prm = gfw.params(max_iter=25, tol=-1)
+    G.tune(gfw.TUNE_LABEL_PATH, 1)
+    assert G.query(gfw.TUNE_SORTED_WIDE_CHUNKS) == 0  # no sorted copy yet
+    a = gfw.solve(ctx(), G, prm, want_history=True)
+    G.tune(gfw.TUNE_LABEL_PATH, 2)
+    wide = G.query(gfw.TUNE_SORTED_WIDE_CHUNKS)
+    say(f"[gpu] wide chunks: {wide} of about {g.nnz // 64}")
+    assert 0 < wide < g.nnz // 64 // 2  # both kinds of chunk are present
+    b = gfw.solve(ctx(), G, prm, want_history=True)
+    np.testing.assert_array_equal(a["alpha"], b["alpha"])
+    np.testing.assert_array_equal(_np(a["labels"]), _np(b["labels"]))
+    np.testing.assert_array_equal(_np(a["U"]), _np(b["U"]))
+    np.testing.assert_allclose(a["q"][:25], b["q"][:25], rtol=1e-9 if dtype == gfw.F64 else 1e-5)
+
+
+def test_sorted_wide_chunks_lockstep_against_oracle():
+    say("[gpu] sorted pass with wide chunks: lockstep")
+    g = _wide_graph(seed=10)
+    idx, lab = graphs.stratified_labels(g.truth, g.K, 0.02, 10)
+    prob = configs.Problem(g, idx, lab, g.K, "f64", 50.0, 1000.0, 20, 1e-6, "wide")
+    lockstep(prob, gfw.F64, [0, 4], label="wide", label_path=gfw.LABEL_PATH_SORTED)
