@@ -176,13 +176,14 @@ GFW_API gfw_status_t gfw_graph_footprint(gfw_graph_t g, size_t *graph_bytes, siz
  *    locality), 1 = plain label pass, 2 = column-sorted label pass (builds, once, a copy
  *    of the entries sorted by column within tiles of rows, 4 bytes per entry: the entry's
  *    offset in the tile and its column relative to an anchor column per 64 sorted entries;
- *    GFW_E_UNSUPPORTED if a row has more than 65536 entries), 3 = measured: times both
+ *    tiles are sized so that their count fills whole rounds of the device's compute units;
+ *    GFW_E_UNSUPPORTED if a row has more than 131072 entries), 3 = measured: times both
  *    passes on this graph (5 launches each, on the default stream, synchronising it) and
  *    keeps the faster.  K > 16 has one pass.
  * gfw_graph_query returns the current value of a key: GFW_TUNE_LABEL_PATH 1 or 2;
  * GFW_TUNE_LABEL_PLAIN_NS / GFW_TUNE_LABEL_SORTED_NS the mean launch times measured by
  * the last value-3 tuning, in ns (0 if none); GFW_TUNE_SORTED_WIDE_CHUNKS (query only) the
- * number of 64-entry runs of the column-sorted copy whose columns span more than 65535, so
+ * number of 64-entry runs of the column-sorted copy whose columns span more than 32767, so
  * that their entries read the column from the CSR instead (0 before the copy is built). */
 typedef enum {
     GFW_TUNE_LABEL_PATH = 0,

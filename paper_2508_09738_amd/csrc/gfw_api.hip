@@ -303,25 +303,49 @@ static double label_locality(int64_t nnz, const int32_t *col)
     return tot / samples;
 }
 
+// Entries per tile of the column-sorted label pass.  A CU runs one tile at a time, and the
+// tiles of a launch cost about the same, so the launch takes as many rounds as the tile count
+// divided by the CU count, rounded up: the target is the largest tile size (densest gathers)
+// whose tiles fill a whole number of rounds.  Greedy tiling closes a tile only when the next
+// row would pass the target, so every closed tile holds more than target - maxrow entries
+// and there are at most cus * R tiles.
+static int64_t sorted_tile_target(int64_t nnz, int64_t maxrow, int64_t cus)
+{
+    if (maxrow >= kSortedMaxEntries) return kSortedMaxEntries;
+    const int64_t room = kSortedMaxEntries - maxrow;
+    int64_t R = std::max<int64_t>(1, cdiv(nnz, cus * room));
+    for (;; ++R) {
+        const int64_t t = cdiv(nnz, std::max<int64_t>(cus * R - 1, 1)) + maxrow;
+        if (t <= kSortedMaxEntries) return std::max<int64_t>(t, 1);
+    }
+}
+
 // Row tiles for the column-sorted label pass and the per-tile column order of the entries.
 static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const int32_t *col, hipStream_t st)
 {
     const int64_t n = g->n;
     const int64_t rcap = 16 * kSortedThreads; // rows per tile (a thread sums at most 16)
-    std::vector<int32_t> tr;
-    tr.push_back(0);
-    int64_t cr = 0, ce = 0;
+    int64_t maxrow = 0;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t d = rp[i + 1] - rp[i];
         if (d > kSortedMaxEntries) return fail(GFW_E_UNSUPPORTED, "row %lld has more than %d entries", (long long)i,
                                                kSortedMaxEntries);
-        if (cr + 1 > rcap || ce + d > kSortedMaxEntries) {
+        maxrow = std::max(maxrow, d);
+    }
+    const int64_t target = sorted_tile_target(g->nnz, maxrow, std::max(1, g->ctx->num_cu));
+    std::vector<int32_t> tr;
+    tr.push_back(0);
+    int64_t cr = 0, ce = 0, emax = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t d = rp[i + 1] - rp[i];
+        if (cr + 1 > rcap || ce + d > target) {
             tr.push_back((int32_t)i);
             cr = 0;
             ce = 0;
         }
         ++cr;
         ce += d;
+        emax = std::max(emax, ce);
     }
     tr.push_back((int32_t)n);
     const int32_t nt = (int32_t)tr.size() - 1;
@@ -342,18 +366,20 @@ static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const 
             for (int32_t t = (int32_t)w; t < nt; t += (int32_t)nth) {
                 const int64_t e0 = rp[tr[t]], e1 = rp[tr[t + 1]];
                 key.resize((size_t)(e1 - e0));
-                for (int64_t e = e0; e < e1; ++e) key[(size_t)(e - e0)] = ((uint64_t)(uint32_t)col[e] << 16) | (uint64_t)(e - e0);
+                for (int64_t e = e0; e < e1; ++e)
+                    key[(size_t)(e - e0)] = ((uint64_t)(uint32_t)col[e] << kSortedOffsetBits) | (uint64_t)(e - e0);
                 std::sort(key.begin(), key.end());
                 for (int64_t c0 = 0; c0 < e1 - e0; c0 += kSortedChunk) {
                     const int64_t c1 = std::min<int64_t>(e1 - e0, c0 + kSortedChunk);
-                    const int32_t lo = (int32_t)(key[(size_t)c0] >> 16), hi = (int32_t)(key[(size_t)(c1 - 1)] >> 16);
-                    const bool fits = hi - lo <= 0xffff;
+                    const int32_t lo = (int32_t)(key[(size_t)c0] >> kSortedOffsetBits);
+                    const int32_t hi = (int32_t)(key[(size_t)(c1 - 1)] >> kSortedOffsetBits);
+                    const bool fits = hi - lo <= kSortedMaxSpan;
                     an[(size_t)(tc[t] + c0 / kSortedChunk)] = fits ? lo : -1;
                     wide[w] += fits ? 0 : 1;
                     for (int64_t q = c0; q < c1; ++q) {
-                        const uint32_t off = (uint32_t)(key[(size_t)q] & 0xffff);
-                        const uint32_t dc = fits ? (uint32_t)((int32_t)(key[(size_t)q] >> 16) - lo) : 0u;
-                        sw[(size_t)(e0 + q)] = (dc << 16) | off;
+                        const uint32_t off = (uint32_t)(key[(size_t)q] & kSortedOffsetMask);
+                        const uint32_t dc = fits ? (uint32_t)((int32_t)(key[(size_t)q] >> kSortedOffsetBits) - lo) : 0u;
+                        sw[(size_t)(e0 + q)] = (dc << kSortedOffsetBits) | off;
                     }
                 }
             }
@@ -381,6 +407,7 @@ static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const 
     }
     GFW_HIP_TRY(hipStreamSynchronize(st));
     g->n_tiles = nt;
+    g->sorted_lds = (int32_t)std::max<int64_t>(16, (emax + 15) / 16 * 16);
     g->wide_chunks = 0;
     for (int64_t x : wide) g->wide_chunks += x;
     g->graph_bytes += sizeof(int32_t) * (2 * (size_t)(nt + 1) + (size_t)std::max<int32_t>(nch, 1)) + 4 * (size_t)nnz;
@@ -647,7 +674,7 @@ static void launch_label(const gfw_graph_s *g, hipStream_t st)
     if constexpr (KMAX > 16) {
         k_label_big<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g));
     } else if (g->label_path == 1) {
-        k_label_sorted<T, uint8_t, KMAX><<<g->n_tiles, kSortedThreads, kSortedMaxEntries, st>>>(make_view<T>(g));
+        k_label_sorted<T, uint8_t, KMAX><<<g->n_tiles, kSortedThreads, g->sorted_lds, st>>>(make_view<T>(g));
     } else {
         const size_t lds = sizeof(T) * kRowBlock * g->K;
         k_label<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(make_view<T>(g));

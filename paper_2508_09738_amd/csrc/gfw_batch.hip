@@ -70,6 +70,7 @@ template <typename T>
 struct BatchTables {
     std::vector<GraphView<T>> views;
     std::vector<TileRef> rows[3], plain[3], sorted[3], all_rows;
+    int32_t sorted_lds[3] = {}; // dynamic LDS of a bucket's sorted launch: its largest tile
     std::vector<TileRef> big_rows[kBigBuckets], big_lab; // K > 16: row tiles per MC bucket, 256-row label tiles
     // host staging of the per-graph control blocks, U_0 pointers and label destinations; kept
     // here so that they outlive the asynchronous copies that read them
@@ -100,6 +101,7 @@ struct BatchTables {
             rows[b].clear();
             plain[b].clear();
             sorted[b].clear();
+            sorted_lds[b] = 0;
         }
         all_rows.clear();
         for (int b = 0; b < kBigBuckets; ++b) big_rows[b].clear();
@@ -168,7 +170,7 @@ static void batch_label_bucket(BatchTables<T> &bt, int b, hipStream_t st)
         k_label_batch<T, uint8_t, KB><<<bt.plain[b].size(), kRowBlock, sizeof(T) * kRowBlock * KB, st>>>(bt.d_views,
                                                                                                        bt.d_plain[b]);
     if (!bt.sorted[b].empty())
-        k_label_sorted_batch<T, uint8_t, KB><<<bt.sorted[b].size(), kSortedThreads, kSortedMaxEntries, st>>>(
+        k_label_sorted_batch<T, uint8_t, KB><<<bt.sorted[b].size(), kSortedThreads, bt.sorted_lds[b], st>>>(
             bt.d_views, bt.d_sorted[b]);
 }
 
@@ -220,8 +222,10 @@ static gfw_status_t batch_prepare(BatchTables<T> &bt, int32_t count, gfw_graph_s
                 bt.all_rows.push_back({i, t});
                 if (g->label_path != 1) bt.plain[b].push_back({i, t});
             }
-            if (g->label_path == 1)
+            if (g->label_path == 1) {
                 for (int32_t t = 0; t < g->n_tiles; ++t) bt.sorted[b].push_back({i, t});
+                bt.sorted_lds[b] = std::max(bt.sorted_lds[b], g->sorted_lds);
+            }
         }
         if (init_state) {
             Ctl &c = ctl0[(size_t)i];

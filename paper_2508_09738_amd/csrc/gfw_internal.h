@@ -111,8 +111,9 @@ struct gfw_graph_s {
     int32_t *tile_rows = nullptr;  // int32[n_tiles + 1]
     int32_t *tile_chunk = nullptr; // int32[n_tiles + 1], first anchor of each tile
     int32_t *ganch = nullptr;      // int32[chunks], anchor column of each 64-entry chunk, -1: wide
-    uint32_t *gword = nullptr;     // uint32[nnz], sorted within each tile: (col - anchor) << 16 | offset
-    int64_t wide_chunks = 0;       // chunks whose columns span more than 16 bits
+    uint32_t *gword = nullptr;     // uint32[nnz], sorted within each tile: (col - anchor) << 17 | offset
+    int64_t wide_chunks = 0;       // chunks whose columns span more than kSortedMaxSpan
+    int32_t sorted_lds = 0;        // dynamic LDS of the sorted pass: bytes of the largest tile
     double locality = 0.0;        // mean distinct 128-node label lines per 64 consecutive entries
     float label_us[2] = {0, 0};   // measured launch times of the plain and sorted passes (0: not measured)
     int diag_one = 1;           // 1: operator is I + A (kind W); 0: operator is A (kind L)

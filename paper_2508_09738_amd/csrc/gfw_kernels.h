@@ -209,8 +209,11 @@ __device__ __forceinline__ void block_sum_store_strided(double (&v)[N], double *
 
 constexpr int kLabelTile = 2048; // CSR entries staged in LDS per step of the label pass
 constexpr int kSortedThreads = 1024;   // threads per tile of the column-sorted label pass
-constexpr int kSortedMaxEntries = 65536; // CSR entries per tile (16-bit positions, 64 KB of labels)
-constexpr int kSortedChunk = 64;         // column-sorted entries that share one anchor column
+constexpr int kSortedMaxEntries = 131072; // CSR entries per tile (17-bit offsets, at most 128 KB of labels)
+constexpr int kSortedOffsetBits = 17;     // low bits of a column-sorted word: the entry's CSR offset
+constexpr uint32_t kSortedOffsetMask = (1u << kSortedOffsetBits) - 1u;
+constexpr int32_t kSortedMaxSpan = (1 << (32 - kSortedOffsetBits)) - 1; // column - anchor in the high bits
+constexpr int kSortedChunk = 64;          // column-sorted entries that share one anchor column
 
 // Everything a per-iteration kernel needs to know about one graph and its solve state.
 // The single-graph kernels take one view as an argument; the batched kernels look up the
@@ -235,7 +238,7 @@ struct GraphView {
     const int32_t *tile_rows;  // first row of each tile
     const int32_t *tile_chunk; // first anchor of each tile
     const int32_t *ganch;      // anchor column of each 64-entry chunk (-1: read the CSR column)
-    const uint32_t *gword;     // per column-sorted entry: (column - anchor) << 16 | CSR offset
+    const uint32_t *gword;     // per column-sorted entry: (column - anchor) << 17 | CSR offset
 };
 
 // workgroup -> (graph, tile) of a batched launch
@@ -568,11 +571,11 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
 // graphs whose neighbour labels are scattered (random node order).  A workgroup owns one
 // tile of consecutive rows holding at most kSortedMaxEntries CSR entries.  The tile's
 // entries are stored twice: in CSR order (values) and sorted by column.  A column-sorted
-// entry is one 32-bit word: its offset inside the tile's CSR range (low 16 bits) and its
-// column minus the anchor of its chunk (high 16 bits), where the anchor is the first column
+// entry is one 32-bit word: its offset inside the tile's CSR range (low 17 bits) and its
+// column minus the anchor of its chunk (high 15 bits), where the anchor is the first column
 // of each aligned run of kSortedChunk sorted entries.  A chunk whose columns span more than
-// 16 bits has anchor -1; its entries take their column from the CSR column array at their
-// offset instead.
+// kSortedMaxSpan has anchor -1; its entries take their column from the CSR column array at
+// their offset instead.
 //  1. gather: consecutive threads take consecutive column-sorted entries, so the labels they
 //     load lie close together and share cache lines; a wavefront's 64 entries form one
 //     chunk, whose anchor is a scalar load; labels are read from the packed two-per-byte
@@ -581,7 +584,7 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
 //  2. rows: each thread sums the histogram of one row at a time in CSR order, values read
 //     from global memory (a row's values are contiguous) and labels from LDS (the same
 //     order, hence the same result, as label_body), and writes the row of Q directly.
-// Dynamic LDS: kSortedMaxEntries bytes.
+// Dynamic LDS: one byte per entry of the graph's largest tile (at most kSortedMaxEntries).
 // On a randomly ordered graph the gathers of phase 1 bound this kernel: the cost follows the
 // number of distinct cache lines each gather instruction touches, which the column order
 // and the packed labels both reduce.
@@ -603,7 +606,7 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
     if (!ctl->active) return;
     const ST *__restrict__ s = (ctl->k & 1) ? gv.s1 : gv.s0;
     extern __shared__ unsigned char lds_raw[];
-    uint8_t *llab = lds_raw; // [kSortedMaxEntries]
+    uint8_t *llab = lds_raw; // [entries of the tile]
     const int tid = threadIdx.x;
     const int32_t r0 = tile_rows[tile], r1 = tile_rows[tile + 1];
     const int32_t e0 = rp[r0], e1 = rp[r1];
@@ -628,14 +631,15 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
         int32_t cc[G];
 #pragma unroll
         for (int m = 0; m < G; ++m)
-            cc[m] = an[m] >= 0 ? an[m] + (int32_t)(ww[m] >> 16) : ci[e0 + (int32_t)(ww[m] & 0xffffu)];
+            cc[m] = an[m] >= 0 ? an[m] + (int32_t)(ww[m] >> kSortedOffsetBits)
+                               : ci[e0 + (int32_t)(ww[m] & kSortedOffsetMask)];
         uint32_t ss[G];
 #pragma unroll
         for (int m = 0; m < G; ++m) ss[m] = (uint32_t)s4[cc[m] >> 1];
 #pragma unroll
         for (int m = 0; m < G; ++m)
             if (b + tid + m * kSortedThreads < E)
-                llab[ww[m] & 0xffffu] = (uint8_t)((ss[m] >> ((cc[m] & 1) << 2)) & 15u);
+                llab[ww[m] & kSortedOffsetMask] = (uint8_t)((ss[m] >> ((cc[m] & 1) << 2)) & 15u);
     }
     __syncthreads();
 

@@ -96,23 +96,23 @@ def test_measured_choice():
 
 
 def test_row_longer_than_a_sorted_tile():
-    """A hub with 70,000 neighbours does not fit a column-sorted tile (65,536 entries): the
+    """A hub with 140,000 neighbours does not fit a column-sorted tile (131,072 entries): the
     sorted pass is refused, the measured choice falls back to the plain pass, and the solve
     still follows the oracle."""
     say("[gpu] hub row beyond the sorted tile size")
     import scipy.sparse as sp
     rng = np.random.default_rng(5)
-    n, K, hub = 90000, 3, 0
-    nb = rng.choice(np.arange(1, n), 70000, replace=False)
-    a = np.concatenate([np.zeros(nb.size, np.int64), rng.integers(1, n, 200000)])
-    b = np.concatenate([nb, rng.integers(1, n, 200000)])
+    n, K, hub = 160000, 3, 0
+    nb = rng.choice(np.arange(1, n), 140000, replace=False)
+    a = np.concatenate([np.zeros(nb.size, np.int64), rng.integers(1, n, 300000)])
+    b = np.concatenate([nb, rng.integers(1, n, 300000)])
     keep = a != b
     W = sp.coo_matrix((np.ones(keep.sum()), (a[keep], b[keep])), shape=(n, n)).tocsr()
     W = ((W + W.T) > 0).astype(np.float64).tocsr()
     W.sort_indices()
     truth = rng.integers(0, K, n).astype(np.int32)
     g = graphs.Graph(n, K, W.indptr.astype(np.int64), W.indices.astype(np.int32), W.data, truth)
-    assert np.diff(g.indptr)[hub] > 65536
+    assert np.diff(g.indptr)[hub] > 131072
     idx, lab = graphs.stratified_labels(truth, K, 0.01, 5)
     G = gpu_graph(g, K, idx, lab, gfw.F64)
     with pytest.raises(gfw.GfwError) as e:
@@ -128,7 +128,7 @@ def _wide_graph(seed=9, n_dense=60000, n_sparse=140000, K=4):
     """A random graph on the first n_dense nodes (mean degree about 12) plus a sparse region
     of mostly isolated nodes, where every 4000th node links to 20 random nodes of the whole
     graph.  The column-sorted tiles of the sparse region hold about a hundred entries spread
-    over all columns, so their 64-entry runs span more than 65,535 columns."""
+    over all columns, so their 64-entry runs span more than 32,767 columns."""
     import scipy.sparse as sp
     rng = np.random.default_rng(seed)
     n = n_dense + n_sparse
