@@ -645,15 +645,38 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
     X(4) X(8) X(16) X(64) X(128) X(192) X(256) X(320) X(384) X(448) X(512) X(576) X(640) X(704) X(768) X(832) \
     X(896) X(960) X(1024)
 
+// The single-graph column-sorted pass is instantiated for every class count K <= 16: each
+// entry's histogram update costs K compare/select/add steps instead of the bucket's.  The
+// sums of the first K classes are the same in every instantiation (the batched launches use
+// the buckets).
+#define GFW_FOR_EACH_SORTED_K(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
 template <typename T, int KMAX>
 static void set_lds_limits()
 {
     if constexpr (KMAX <= 16) { // the large-K kernels use static LDS only
         // the largest dynamic LDS any launch of these kernels asks for
-        (void)hipFuncSetAttribute((const void *)k_label_sorted<T, uint8_t, KMAX>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, kSortedMaxEntries);
+#define GFW_SET_SORTED(KX)                                                                                       \
+    (void)hipFuncSetAttribute((const void *)k_label_sorted<T, uint8_t, KX>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                              kSortedMaxEntries);
+        GFW_FOR_EACH_SORTED_K(GFW_SET_SORTED)
+#undef GFW_SET_SORTED
         (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   3 * (int)sizeof(T) * kRowBlock * KMAX);
+    }
+}
+
+template <typename T>
+static void launch_label_sorted(const gfw_graph_s *g, hipStream_t st)
+{
+    switch (g->K) {
+#define GFW_SORTED_CASE(KX)                                                                                      \
+    case KX:                                                                                                     \
+        k_label_sorted<T, uint8_t, KX><<<g->n_tiles, kSortedThreads, g->sorted_lds, st>>>(make_view<T>(g));      \
+        break;
+        GFW_FOR_EACH_SORTED_K(GFW_SORTED_CASE)
+#undef GFW_SORTED_CASE
+    default: break; // K > 16 has no sorted pass
     }
 }
 
@@ -674,7 +697,7 @@ static void launch_label(const gfw_graph_s *g, hipStream_t st)
     if constexpr (KMAX > 16) {
         k_label_big<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g));
     } else if (g->label_path == 1) {
-        k_label_sorted<T, uint8_t, KMAX><<<g->n_tiles, kSortedThreads, g->sorted_lds, st>>>(make_view<T>(g));
+        launch_label_sorted<T>(g, st);
     } else {
         const size_t lds = sizeof(T) * kRowBlock * g->K;
         k_label<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, lds, st>>>(make_view<T>(g));
