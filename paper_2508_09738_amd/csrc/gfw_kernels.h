@@ -67,12 +67,56 @@ struct Ctl {
 
 // ---------------------------------------------------------------------------------
 // wave / block reductions in a fixed order (deterministic for a fixed launch shape)
+//
+// Wavefront reductions run on DPP lane permutations (VALU operand modifiers, no LDS
+// traffic), in six steps over the 64 lanes (four rows of 16):
+//   quad_perm [1,0,3,2] and [2,3,0,1]  -> every lane holds its quad's result
+//   row_half_mirror, row_mirror         -> every lane holds its row's result
+//   row_bcast:15 into rows 1 and 3      -> rows 1 and 3 hold rows 0-1 and 2-3
+//   row_bcast:31 into rows 2 and 3      -> lane 63 holds the whole wavefront's result
+// and lane 63 is read into every lane.  The callers run with every lane of the wavefront
+// active (the reductions sit before block barriers or under wavefront-uniform conditions).
 // ---------------------------------------------------------------------------------
+constexpr int kDppQuadSwap1 = 0xb1;     // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4e;     // quad_perm [2,3,0,1]
+constexpr int kDppRowMirror = 0x140;    // lane i of a row reads lane 15 - i
+constexpr int kDppRowHalfMirror = 0x141; // lane i of a half-row reads lane 7 - i
+constexpr int kDppRowBcast15 = 0x142;   // a row reads lane 15 of the row before it
+constexpr int kDppRowBcast31 = 0x143;   // a row reads lane 31
+
+// src permuted by CTRL in the rows of ROW_MASK; lanes of the other rows get `old`
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i32(int src, int old)
+{
+    return __builtin_amdgcn_update_dpp(old, src, CTRL, ROW_MASK, 0xf, false);
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_f64(double src, double old)
+{
+    const long long s = __double_as_longlong(src), o = __double_as_longlong(old);
+    const int lo = dpp_i32<CTRL, ROW_MASK>((int)(s & 0xffffffffll), (int)(o & 0xffffffffll));
+    const int hi = dpp_i32<CTRL, ROW_MASK>((int)(s >> 32), (int)(o >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const long long s = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(s & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(s >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_f64<kDppQuadSwap1>(v, 0.0);
+    v += dpp_f64<kDppQuadSwap2>(v, 0.0);
+    v += dpp_f64<kDppRowHalfMirror>(v, 0.0);
+    v += dpp_f64<kDppRowMirror>(v, 0.0);
+    v += dpp_f64<kDppRowBcast15, 0xa>(v, 0.0);
+    v += dpp_f64<kDppRowBcast31, 0xc>(v, 0.0);
+    return readlane_f64(v, 63);
 }
 
 // ---------------------------------------------------------------------------------

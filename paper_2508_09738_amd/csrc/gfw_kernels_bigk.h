@@ -33,28 +33,42 @@ constexpr int kBigThreads = 256;                             // 4 wavefronts per
 constexpr int kBigRowsPerWave = 4;                           // rows a wavefront takes in turn
 constexpr int kBigRowsPerBlock = kBigRowsPerWave * (kBigThreads / 64);
 
+// Wavefront minimum (the DPP steps of wave_sum).
 __device__ __forceinline__ int wave_min_int(int v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
-    return v;
+    v = min(v, dpp_i32<kDppQuadSwap1>(v, INT_MAX));
+    v = min(v, dpp_i32<kDppQuadSwap2>(v, INT_MAX));
+    v = min(v, dpp_i32<kDppRowHalfMirror>(v, INT_MAX));
+    v = min(v, dpp_i32<kDppRowMirror>(v, INT_MAX));
+    v = min(v, dpp_i32<kDppRowBcast15, 0xa>(v, INT_MAX));
+    v = min(v, dpp_i32<kDppRowBcast31, 0xc>(v, INT_MAX));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// One step of the lowest-index minimum: take the pair (ov, oi) read from another lane if it
+// is a candidate that precedes (v, idx).
+__device__ __forceinline__ void argmin_take(double &v, int &idx, const double ov, const int oi)
+{
+    const bool take = oi != INT_MAX && (idx == INT_MAX || ov < v || (ov == v && oi < idx));
+    if (take) {
+        v = ov;
+        idx = oi;
+    }
 }
 
 // Lowest-index minimum over the wavefront of (value, index) pairs; index INT_MAX marks a
-// lane without a candidate.  The pairs are totally ordered, so every lane ends with the
-// same result.
+// lane without a candidate.  The pairs are totally ordered, so the result does not depend on
+// the order of the steps; every lane ends with it.
 __device__ __forceinline__ void wave_argmin(double &v, int &idx)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int oi = __shfl_xor(idx, off, 64);
-        const bool take = oi != INT_MAX && (idx == INT_MAX || ov < v || (ov == v && oi < idx));
-        if (take) {
-            v = ov;
-            idx = oi;
-        }
-    }
+    argmin_take(v, idx, dpp_f64<kDppQuadSwap1>(v, v), dpp_i32<kDppQuadSwap1>(idx, INT_MAX));
+    argmin_take(v, idx, dpp_f64<kDppQuadSwap2>(v, v), dpp_i32<kDppQuadSwap2>(idx, INT_MAX));
+    argmin_take(v, idx, dpp_f64<kDppRowHalfMirror>(v, v), dpp_i32<kDppRowHalfMirror>(idx, INT_MAX));
+    argmin_take(v, idx, dpp_f64<kDppRowMirror>(v, v), dpp_i32<kDppRowMirror>(idx, INT_MAX));
+    argmin_take(v, idx, dpp_f64<kDppRowBcast15, 0xa>(v, v), dpp_i32<kDppRowBcast15, 0xa>(idx, INT_MAX));
+    argmin_take(v, idx, dpp_f64<kDppRowBcast31, 0xc>(v, v), dpp_i32<kDppRowBcast31, 0xc>(idx, INT_MAX));
+    v = readlane_f64(v, 63);
+    idx = __builtin_amdgcn_readlane(idx, 63);
 }
 
 // Row kernel for large K: pending update (with the Q row rebuilt from s_{k-1}), gradient,
