@@ -309,15 +309,43 @@ static double label_locality(int64_t nnz, const int32_t *col)
 // whose tiles fill a whole number of rounds.  Greedy tiling closes a tile only when the next
 // row would pass the target, so every closed tile holds more than target - maxrow entries
 // and there are at most cus * R tiles.
-static int64_t sorted_tile_target(int64_t nnz, int64_t maxrow, int64_t cus)
+int64_t sorted_tile_target(int64_t nnz, int64_t maxrow, int64_t cus, int64_t *rounds)
 {
+    if (rounds) *rounds = 0;
     if (maxrow >= kSortedMaxEntries) return kSortedMaxEntries;
     const int64_t room = kSortedMaxEntries - maxrow;
     int64_t R = std::max<int64_t>(1, cdiv(nnz, cus * room));
     for (;; ++R) {
         const int64_t t = cdiv(nnz, std::max<int64_t>(cus * R - 1, 1)) + maxrow;
-        if (t <= kSortedMaxEntries) return std::max<int64_t>(t, 1);
+        if (t <= kSortedMaxEntries) {
+            if (rounds) *rounds = R;
+            return std::max<int64_t>(t, 1);
+        }
     }
+}
+
+// Tiles closed by the entry target number fewer than cus * R (each holds more than
+// nnz / (cus * R - 1) entries); the row cap closes at most n / rcap more; one is last.
+int64_t sorted_tile_bound(int64_t n, int64_t nnz, int64_t maxrow, int64_t cus)
+{
+    int64_t R = 0;
+    (void)sorted_tile_target(nnz, maxrow, cus, &R);
+    if (R == 0) return n + 1; // a row fills a whole tile: at most one tile per row
+    return cus * R + cdiv(n, 16 * kSortedThreads) + 1;
+}
+
+// The buffers of ensure_workspace except the per-iteration history (5 doubles per iteration).
+void refresh_solve_bytes(gfw_graph_s *g)
+{
+    const size_t vs = dsize(g->dtype), n = (size_t)g->n, K = (size_t)g->K, nnz = (size_t)g->nnz;
+    const size_t nb = (size_t)g->shape.nb_row;
+    const size_t row_parts = kRowParts * std::max<size_t>(nb, (size_t)g->shape.nb_big);
+    const size_t lab = std::max<size_t>(nb, (size_t)g->n_tiles);
+    const size_t scratch = 3 * std::max<size_t>(nb, 64);
+    g->solve_bytes = 3 * vs * n * K                     // U, P, Q
+                     + (K > 16 ? 4 * n + 2 * nnz : 2 * n) // vertex pair (and nv for K > 16)
+                     + (n + 1) / 2                        // packed vertices
+                     + sizeof(double) * (row_parts + lab + scratch) + sizeof(Ctl);
 }
 
 // Row tiles for the column-sorted label pass and the per-tile column order of the entries.
@@ -407,6 +435,7 @@ static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const 
     }
     GFW_HIP_TRY(hipStreamSynchronize(st));
     g->n_tiles = nt;
+    refresh_solve_bytes(g);
     g->sorted_lds = (int32_t)std::max<int64_t>(16, (emax + 15) / 16 * 16);
     g->wide_chunks = 0;
     for (int64_t x : wide) g->wide_chunks += x;
@@ -592,8 +621,7 @@ gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_
     g->shape = shape_for(n, p->K);
     if ((s = choose_label_path(g, 0, st, p->location == GFW_HOST ? p->col_idx : nullptr)) != GFW_OK) return s;
     g->graph_bytes += 4 * (n + 1) + (4 + vs) * nnz + 4 * n;
-    g->solve_bytes = 3 * vs * n * p->K + (p->K > 16 ? 4 * n + 2 * nnz : 2 * n) + sizeof(double) * ((kRowParts + 4) * g->shape.nb_row + 64) +
-                     sizeof(Ctl);
+    refresh_solve_bytes(g);
     guard.g = nullptr;
     *out = g;
     return GFW_OK;
@@ -621,8 +649,22 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
     if (g->K > 16 && (s = dalloc((void **)&w.nv, sizeof(uint16_t) * (size_t)g->nnz)) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.row_part, sizeof(double) * kRowParts * std::max(g->shape.nb_row, g->shape.nb_big)))
         != GFW_OK) return s;
-    if ((s = dalloc((void **)&w.lab_part, sizeof(double) * std::max<int64_t>(g->shape.nb_row, g->n_tiles)))
-        != GFW_OK) return s;
+    // one label-pass partial per 256-row block (plain pass) or per tile (sorted pass, whose
+    // tiles may be built after the first solve: then the buffer grows, and the captured
+    // iterations, which hold the old buffer, are dropped)
+    const int64_t need_lab = std::max<int64_t>(g->shape.nb_row, g->n_tiles);
+    if (w.lab_part && w.lab_cap < need_lab) {
+        if (w.iter_exec) {
+            (void)hipGraphExecDestroy(w.iter_exec);
+            w.iter_exec = nullptr;
+        }
+        dfree(w.lab_part);
+        w.lab_part = nullptr;
+    }
+    if (!w.lab_part) {
+        if ((s = dalloc((void **)&w.lab_part, sizeof(double) * need_lab)) != GFW_OK) return s;
+        w.lab_cap = need_lab;
+    }
     if ((s = dalloc((void **)&w.scratch, sizeof(double) * 3 * std::max(g->shape.nb_row, 64))) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.ctl, sizeof(Ctl))) != GFW_OK) return s;
     const int64_t need = 5 * ((int64_t)max_iter + 1);

@@ -437,19 +437,25 @@ static gfw_status_t solve_batched_impl(gfw_context_s *cx, int32_t count, gfw_gra
 
 // Device bytes a problem will hold while resident (graph + one solve), an upper bound of
 // gfw_graph_footprint for the same problem.
-static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter, bool warm)
+static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter, bool warm, int cus)
 {
     const size_t v = dsize(p->dtype);
     const size_t n = (size_t)p->n, nnz = (size_t)p->nnz, K = (size_t)p->K;
     const size_t nb = (size_t)cdiv(p->n, kRowBlock);
     size_t graph = 4 * (n + 1) + (4 + v) * nnz + 4 * n;
-    // column-sorted copy (4 bytes per entry), its anchors (one per 64 entries, plus one
-    // partial run per tile) and two tile tables, with at most n tiles
-    if (p->nnz >= ((int64_t)4 << 20)) graph += 4 * nnz + 4 * (nnz / 64 + n + 1) + 8 * (n + 2);
+    size_t tiles = 0; // label-pass partials beyond one per 256-row block (sorted tiles)
+    if (p->nnz >= ((int64_t)4 << 20) && K <= 16) {
+        int64_t maxrow = 0;
+        for (int64_t i = 0; i < p->n; ++i) maxrow = std::max<int64_t>(maxrow, p->row_ptr[i + 1] - p->row_ptr[i]);
+        tiles = (size_t)sorted_tile_bound(p->n, p->nnz, maxrow, std::max(1, cus));
+        // column-sorted copy (4 bytes per entry), its anchors (one per 64 entries plus one
+        // partial run per tile) and two tile tables
+        graph += 4 * nnz + 4 * (nnz / 64 + tiles) + 8 * (tiles + 1);
+    }
     const size_t nb_parts = K > 16 ? std::max(nb, (size_t)cdiv(p->n, kBigRowsPerBlock)) : nb;
     const size_t solve = 3 * v * n * K + (K > 16 ? 4 * n + 2 * nnz : 2 * n) + n / 2 + 16 +
-                         8 * ((size_t)(kRowParts + 4) * nb_parts + 64) + sizeof(Ctl) + 8 * 5 * ((size_t)max_iter + 1) +
-                         4096;
+                         8 * ((size_t)(kRowParts + 4) * nb_parts + std::max(tiles, nb) + 64) + sizeof(Ctl) +
+                         8 * 5 * ((size_t)max_iter + 1) + 4096;
     return graph + solve + (warm ? v * n * K : 0); // a warm start holds its U_0 until retirement
 }
 
@@ -775,7 +781,7 @@ gfw_status_t gfw_server_submit(gfw_server_t sv, const gfw_problem_t *p, const gf
     if (s != GFW_OK) return s;
     if ((s = check_params(prm, p->K)) != GFW_OK) return s;
     if (prm->p_refresh) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported by the server");
-    const size_t fp = request_footprint(p, prm->max_iter, prm->U0 != nullptr);
+    const size_t fp = request_footprint(p, prm->max_iter, prm->U0 != nullptr, sv->ctx->num_cu);
     if (fp > sv->budget) return fail(GFW_E_BUDGET, "request needs %zu bytes, budget is %zu", fp, sv->budget);
     auto *r = new (std::nothrow) ServerRequest();
     if (!r) return fail(GFW_E_NOMEM, "host allocation failed");

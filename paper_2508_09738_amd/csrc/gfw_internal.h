@@ -47,6 +47,7 @@ struct Workspace {
     uint8_t *s4 = nullptr;                         // the current vertices packed two per byte (K <= 16)
     uint16_t *nv = nullptr;                        // per CSR entry, the vertex of its column (K > 16)
     double *row_part = nullptr, *lab_part = nullptr, *scratch = nullptr;
+    int64_t lab_cap = 0; // entries of lab_part: one per 256-row block or per sorted tile
     Ctl *ctl = nullptr;
     double *hist = nullptr;
     int64_t hist_cap = 0;
@@ -133,6 +134,13 @@ gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_
                           bool validated = false);
 void free_graph(gfw_graph_s *g);
 gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter);
+// Column-sorted tiles: the entry target per tile for a graph of nnz entries whose longest row
+// has maxrow entries on a device of cus compute units (rounds: the launch's rounds of tiles),
+// and an upper bound of the resulting tile count for n rows.
+int64_t sorted_tile_target(int64_t nnz, int64_t maxrow, int64_t cus, int64_t *rounds = nullptr);
+int64_t sorted_tile_bound(int64_t n, int64_t nnz, int64_t maxrow, int64_t cus);
+// Device bytes of one solve on the graph as it stands (its label pass included).
+void refresh_solve_bytes(gfw_graph_s *g);
 SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm);
 
 // view of a graph and its solve workspace for the per-iteration kernels

@@ -175,3 +175,28 @@ def test_sorted_wide_chunks_lockstep_against_oracle():
     idx, lab = graphs.stratified_labels(g.truth, g.K, 0.02, 10)
     prob = configs.Problem(g, idx, lab, g.K, "f64", 50.0, 1000.0, 20, 1e-6, "wide")
     lockstep(prob, gfw.F64, [0, 4], label="wide", label_path=gfw.LABEL_PATH_SORTED)
+
+
+def test_sorted_tiles_built_after_a_solve_grow_the_partials():
+    """A small graph gets about one sorted tile per CU, more tiles than 256-row blocks.  When
+    the tiles are built after a solve on the plain pass, the label-pass partials buffer (sized
+    at that solve) grows, the footprint counts it, and the sorted solves that follow match the
+    plain one."""
+    say("[gpu] sorted tiles built after a plain solve")
+    n, K = 9000, 3
+    g = graphs.sbm_by_degree(n, K, 24.0, 8.0, 44)
+    idx, lab = graphs.stratified_labels(g.truth, K, 0.02, 44)
+    G = gpu_graph(g, K, idx, lab, gfw.F64)
+    prm = gfw.params(max_iter=20, tol=-1)
+    assert G.query(gfw.TUNE_LABEL_PATH) == 1
+    plain = gfw.solve(ctx(), G, prm, want_history=True)
+    _, solve_before = G.footprint()
+    G.tune(gfw.TUNE_LABEL_PATH, 2)
+    _, solve_after = G.footprint()
+    nb_row = -(-n // 256)
+    assert solve_after - solve_before >= 8 * (200 - nb_row)  # about 255 tiles on 256 CUs
+    for _ in range(2):  # the second solve replays the captured iterations
+        b = gfw.solve(ctx(), G, prm, want_history=True)
+        np.testing.assert_array_equal(plain["alpha"], b["alpha"])
+        np.testing.assert_array_equal(_np(plain["labels"]), _np(b["labels"]))
+        np.testing.assert_allclose(_np(plain["U"]), _np(b["U"]), atol=1e-12)
