@@ -244,6 +244,7 @@ void free_graph(gfw_graph_s *g)
     dfree(w.nv);
     dfree(w.row_part);
     dfree(w.lab_part);
+    dfree(w.row_fold);
     dfree(w.scratch);
     dfree(w.ctl);
     dfree(w.hist);
@@ -340,7 +341,7 @@ void refresh_solve_bytes(gfw_graph_s *g)
     const size_t vs = dsize(g->dtype), n = (size_t)g->n, K = (size_t)g->K, nnz = (size_t)g->nnz;
     const size_t nb = (size_t)g->shape.nb_row;
     const size_t row_parts = kRowParts * std::max<size_t>(nb, (size_t)g->shape.nb_big);
-    const size_t lab = std::max<size_t>(nb, (size_t)g->n_tiles);
+    const size_t lab = std::max<size_t>(nb, (size_t)g->n_tiles) + kRowParts * (size_t)g->n_tiles; // + folded rows
     const size_t scratch = 3 * std::max<size_t>(nb, 64);
     g->solve_bytes = 3 * vs * n * K                     // U, P, Q
                      + (K > 16 ? 4 * n + 2 * nnz : 2 * n) // vertex pair (and nv for K > 16)
@@ -665,6 +666,16 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
         if ((s = dalloc((void **)&w.lab_part, sizeof(double) * need_lab)) != GFW_OK) return s;
         w.lab_cap = need_lab;
     }
+    if (g->n_tiles > 0 && w.fold_cap < g->n_tiles) { // the sorted pass's folded row partials
+        if (w.iter_exec) {
+            (void)hipGraphExecDestroy(w.iter_exec);
+            w.iter_exec = nullptr;
+        }
+        dfree(w.row_fold);
+        w.row_fold = nullptr;
+        if ((s = dalloc((void **)&w.row_fold, sizeof(double) * kRowParts * (size_t)g->n_tiles)) != GFW_OK) return s;
+        w.fold_cap = g->n_tiles;
+    }
     if ((s = dalloc((void **)&w.scratch, sizeof(double) * 3 * std::max(g->shape.nb_row, 64))) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.ctl, sizeof(Ctl))) != GFW_OK) return s;
     const int64_t need = 5 * ((int64_t)max_iter + 1);
@@ -870,9 +881,11 @@ static void launch_iteration(gfw_graph_s *g, hipStream_t st, bool traced)
     launch_label<T, KMAX>(g, st);
     trace_end(cx, GFW_KERNEL_LABEL, ev, st);
     ev = trace_begin(cx, st);
-    const int nb_rows = KMAX > 16 ? g->shape.nb_big : g->shape.nb_row;
-    const int nb_lab = (KMAX <= 16 && g->label_path == 1) ? g->n_tiles : g->shape.nb_row;
-    k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, nb_rows, w.lab_part, nb_lab, w.ctl);
+    if (KMAX <= 16 && g->label_path == 1) // the sorted pass folds the row partials per tile
+        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_fold, g->n_tiles, w.lab_part, g->n_tiles, w.ctl);
+    else
+        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, KMAX > 16 ? g->shape.nb_big : g->shape.nb_row, w.lab_part,
+                                               g->shape.nb_row, w.ctl);
     trace_end(cx, GFW_KERNEL_FINISH, ev, st);
 }
 

@@ -48,6 +48,8 @@ struct Workspace {
     uint16_t *nv = nullptr;                        // per CSR entry, the vertex of its column (K > 16)
     double *row_part = nullptr, *lab_part = nullptr, *scratch = nullptr;
     int64_t lab_cap = 0; // entries of lab_part: one per 256-row block or per sorted tile
+    double *row_fold = nullptr; // [kRowParts][n_tiles]: row partials folded per sorted tile
+    int64_t fold_cap = 0;       // tiles row_fold holds
     Ctl *ctl = nullptr;
     double *hist = nullptr;
     int64_t hist_cap = 0;
@@ -166,6 +168,7 @@ GraphView<T> make_view(const gfw_graph_s *g)
     v.ctl = w.ctl;
     v.row_part = w.row_part;
     v.lab_part = w.lab_part;
+    v.row_fold = (g->label_path == 1 && g->K <= 16) ? w.row_fold : nullptr;
     v.nb_row = g->shape.nb_row;
     v.nb_big = g->shape.nb_big;
     v.n_tiles = g->label_path == 1 ? g->n_tiles : 0;

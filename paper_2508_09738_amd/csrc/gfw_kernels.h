@@ -276,6 +276,7 @@ struct GraphView {
     uint16_t *nv;     // per CSR entry, the last evaluated vertex of its column (large-K kernels)
     Ctl *ctl;
     double *row_part, *lab_part;
+    double *row_fold; // sorted pass: the row partials folded per tile, [kRowParts][n_tiles] (else null)
     int32_t nb_row;   // 256-row tiles (row kernel, plain label pass, SpMM)
     int32_t nb_big;   // blocks of the large-K row kernel (stride of its partials)
     int32_t n_tiles;  // tiles of the column-sorted label pass (0: plain pass)
@@ -657,6 +658,20 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
     const int E = e1 - e0;
     const int rows = r1 - r0;
 
+    // 0. the row kernel's partials of a fixed slice of 256-row blocks, folded into this tile's
+    //    entry of row_fold so that the finish reads n_tiles partials instead of nb_row: the
+    //    first wavefront loads them here and sums them (lane order, then a wavefront tree) at
+    //    the end
+    const int nbr = gv.nb_row, ntl = gv.n_tiles;
+    const int fb0 = (int)((int64_t)tile * nbr / ntl), fb1 = (int)((int64_t)(tile + 1) * nbr / ntl);
+    double fold[kRowParts];
+#pragma unroll
+    for (int j = 0; j < kRowParts; ++j) fold[j] = 0.0;
+    if (tid < 64)
+        for (int b = fb0 + tid; b < fb1; b += 64)
+#pragma unroll
+            for (int j = 0; j < kRowParts; ++j) fold[j] += gv.row_part[(int64_t)j * nbr + b];
+
     // 1. gather labels in column order, scatter them to CSR positions in LDS
     static_assert(kSortedThreads % kSortedChunk == 0 && kSortedChunk == 64, "a wavefront reads one chunk");
     const int32_t *__restrict__ anch = gv.ganch + gv.tile_chunk[tile];
@@ -729,6 +744,13 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
     __shared__ double red[kSortedThreads / 64];
     own = wave_sum(own);
     if ((tid & 63) == 0) red[tid >> 6] = own;
+    if (tid < 64) { // the whole first wavefront
+#pragma unroll
+        for (int j = 0; j < kRowParts; ++j) fold[j] = wave_sum(fold[j]);
+        if (tid == 0)
+#pragma unroll
+            for (int j = 0; j < kRowParts; ++j) gv.row_fold[(int64_t)j * ntl + tile] = fold[j];
+    }
     __syncthreads();
     if (tid == 0) {
         double t = 0.0;
@@ -1166,8 +1188,10 @@ template <typename T>
 static __global__ void __launch_bounds__(kFinishThreads) k_finish_batch(const GraphView<T> *__restrict__ views)
 {
     const GraphView<T> &gv = views[blockIdx.x];
-    finish_body(gv.row_part, gv.nb_big > 0 ? gv.nb_big : gv.nb_row, gv.lab_part, gv.n_tiles > 0 ? gv.n_tiles : gv.nb_row,
-                gv.ctl);
+    if (gv.row_fold) // sorted label pass: row partials folded per tile
+        finish_body(gv.row_fold, gv.n_tiles, gv.lab_part, gv.n_tiles, gv.ctl);
+    else
+        finish_body(gv.row_part, gv.nb_big > 0 ? gv.nb_big : gv.nb_row, gv.lab_part, gv.nb_row, gv.ctl);
 }
 
 // labels_i = lowest-index argmax_c U_ic; s_out = vertex indices of the last GLMO output
