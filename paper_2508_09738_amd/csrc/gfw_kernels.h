@@ -709,7 +709,22 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
         T acc[KB];
 #pragma unroll
         for (int c = 0; c < KB; ++c) acc[c] = (T)0;
+        // the row's values in batches of 8, then 4, then singly: each batch's loads are in
+        // flight together (a row has about 24 entries on the large SBM: three batches)
         int p = rb;
+        for (; p + 8 <= re; p += 8) {
+            T v[8];
+            int32_t sj[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                v[u] = a[e0 + p + u];
+                sj[u] = (int32_t)llab[p + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? v[u] : (T)0;
+        }
         for (; p + 4 <= re; p += 4) {
             T v[4];
             int32_t sj[4];
