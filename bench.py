@@ -381,7 +381,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--iters", type=int, default=1000)
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="graphs in the batch measurement (0: skip)")
     ap.add_argument("--serve", type=int, default=160, help="requests under load in the serving measurement (0: skip)")
