@@ -200,3 +200,22 @@ def test_sorted_tiles_built_after_a_solve_grow_the_partials():
         np.testing.assert_array_equal(plain["alpha"], b["alpha"])
         np.testing.assert_array_equal(_np(plain["labels"]), _np(b["labels"]))
         np.testing.assert_allclose(_np(plain["U"]), _np(b["U"]), atol=1e-12)
+
+
+@pytest.mark.parametrize("K", list(range(2, 17)))
+def test_every_class_count_sorted_equals_plain(K):
+    """The single-graph row kernel and sorted label pass are instantiated per class count
+    K = 2..16: each gives the same iterates as the plain pass (FP64, small SBM)."""
+    say(f"[gpu] class count {K}: sorted vs plain")
+    g = graphs.sbm_by_degree(3000, K, 20.0, 8.0, 500 + K)
+    idx, lab = graphs.stratified_labels(g.truth, K, 0.05, 500 + K)
+    G = gpu_graph(g, K, idx, lab, gfw.F64)
+    prm = gfw.params(max_iter=10, tol=-1)
+    G.tune(gfw.TUNE_LABEL_PATH, 1)
+    a = gfw.solve(ctx(), G, prm, want_history=True)
+    G.tune(gfw.TUNE_LABEL_PATH, 2)
+    b = gfw.solve(ctx(), G, prm, want_history=True)
+    np.testing.assert_array_equal(a["alpha"], b["alpha"])
+    np.testing.assert_array_equal(_np(a["labels"]), _np(b["labels"]))
+    np.testing.assert_allclose(_np(a["U"]), _np(b["U"]), rtol=0, atol=1e-12)
+    assert np.all(np.isfinite(a["E"][:10]))
