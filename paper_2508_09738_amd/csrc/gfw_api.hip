@@ -698,10 +698,10 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
     X(4) X(8) X(16) X(64) X(128) X(192) X(256) X(320) X(384) X(448) X(512) X(576) X(640) X(704) X(768) X(832) \
     X(896) X(960) X(1024)
 
-// The single-graph column-sorted pass is instantiated for every class count K <= 16: each
-// entry's histogram update costs K compare/select/add steps instead of the bucket's.  The
-// sums of the first K classes are the same in every instantiation (the batched launches use
-// the buckets).
+// The single-graph column-sorted pass and row kernel are instantiated for every class count
+// K <= 16: each entry's histogram update, and each row's class loops, cost K steps instead of
+// the bucket's.  Classes past K take no part in any result, so every instantiation gives the
+// same results (the batched launches use the buckets).
 #define GFW_FOR_EACH_SORTED_K(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
 template <typename T, int KMAX>
@@ -711,7 +711,9 @@ static void set_lds_limits()
         // the largest dynamic LDS any launch of these kernels asks for
 #define GFW_SET_SORTED(KX)                                                                                       \
     (void)hipFuncSetAttribute((const void *)k_label_sorted<T, uint8_t, KX>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                              kSortedMaxEntries);
+                              kSortedMaxEntries);                                                                \
+    (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KX>, hipFuncAttributeMaxDynamicSharedMemorySize,    \
+                              3 * (int)sizeof(T) * kRowBlock * KX);
         GFW_FOR_EACH_SORTED_K(GFW_SET_SORTED)
 #undef GFW_SET_SORTED
         (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -734,6 +736,21 @@ static void launch_label_sorted(const gfw_graph_s *g, hipStream_t st)
 }
 
 static size_t row_lds_bytes(const gfw_graph_s *g) { return 3 * dsize(g->dtype) * kRowBlock * (size_t)g->K; }
+
+template <typename T>
+static void launch_row_exact(const gfw_graph_s *g, int apply_only, hipStream_t st)
+{
+    switch (g->K) {
+#define GFW_ROW_CASE(KX)                                                                                         \
+    case KX:                                                                                                     \
+        k_row<T, uint8_t, KX><<<g->shape.nb_row, kRowBlock, row_lds_bytes(g), st>>>(make_view<T>(g), apply_only); \
+        break;
+        GFW_FOR_EACH_SORTED_K(GFW_ROW_CASE)
+#undef GFW_ROW_CASE
+    default: break; // K > 16 runs the large-K row kernel
+    }
+}
+
 
 template <typename T, int KMAX>
 static void launch_spmm(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
@@ -864,7 +881,7 @@ static void launch_row(gfw_graph_s *g, int apply_only, hipStream_t st)
     if constexpr (KMAX > 16)
         k_row_big<T, KMAX / 64><<<g->shape.nb_big, kBigThreads, 0, st>>>(make_view<T>(g), apply_only);
     else
-        k_row<T, uint8_t, KMAX><<<g->shape.nb_row, kRowBlock, row_lds_bytes(g), st>>>(make_view<T>(g), apply_only);
+        launch_row_exact<T>(g, apply_only, st);
 }
 
 // One GFW iteration (row kernel, label pass, finish), optionally bracketed by trace events.
