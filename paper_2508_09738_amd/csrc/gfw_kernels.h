@@ -676,7 +676,7 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
     static_assert(kSortedThreads % kSortedChunk == 0 && kSortedChunk == 64, "a wavefront reads one chunk");
     const int32_t *__restrict__ anch = gv.ganch + gv.tile_chunk[tile];
     const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63); // first entry of the wavefront's chunk
-    constexpr int G = 8;
+    constexpr int G = 16; // sorted entries per thread per batch (n = 2 M SBM: 4, 8, 16 took 143, 128, 124 us)
     for (int b = 0; b < E; b += G * kSortedThreads) {
         uint32_t ww[G];
         int32_t an[G];
