@@ -630,9 +630,12 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
 //     from global memory (a row's values are contiguous) and labels from LDS (the same
 //     order, hence the same result, as label_body), and writes the row of Q directly.
 // Dynamic LDS: one byte per entry of the graph's largest tile (at most kSortedMaxEntries).
-// On a randomly ordered graph the gathers of phase 1 bound this kernel: the cost follows the
-// number of distinct cache lines each gather instruction touches, which the column order
-// and the packed labels both reduce.
+// One tile runs per CU at a time, and the tiles are sized so that their count fills whole
+// rounds of the CUs.  On a randomly ordered graph both phases wait on memory: the gathers of
+// phase 1 cost in proportion to the distinct cache lines each gather instruction touches
+// (which the column order and the packed labels reduce), and the row walks of phase 2 wait
+// on their values; both keep several loads in flight per thread (16 sorted entries per
+// gather batch, row values in batches of 8).
 template <typename T, typename ST, int KB>
 __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const int tile)
 {
