@@ -341,7 +341,8 @@ void refresh_solve_bytes(gfw_graph_s *g)
     const size_t vs = dsize(g->dtype), n = (size_t)g->n, K = (size_t)g->K, nnz = (size_t)g->nnz;
     const size_t nb = (size_t)g->shape.nb_row;
     const size_t row_parts = kRowParts * std::max<size_t>(nb, (size_t)g->shape.nb_big);
-    const size_t lab = std::max<size_t>(nb, (size_t)g->n_tiles) + kRowParts * (size_t)g->n_tiles; // + folded rows
+    const size_t lab = std::max<size_t>(nb, (size_t)g->n_tiles) // label partials, folded row partials
+                       + kRowParts * std::max<size_t>((size_t)g->n_tiles, K > 16 ? nb : 0);
     const size_t scratch = 3 * std::max<size_t>(nb, 64);
     g->solve_bytes = 3 * vs * n * K                     // U, P, Q
                      + (K > 16 ? 4 * n + 2 * nnz : 2 * n) // vertex pair (and nv for K > 16)
@@ -666,15 +667,16 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
         if ((s = dalloc((void **)&w.lab_part, sizeof(double) * need_lab)) != GFW_OK) return s;
         w.lab_cap = need_lab;
     }
-    if (g->n_tiles > 0 && w.fold_cap < g->n_tiles) { // the sorted pass's folded row partials
+    const int64_t need_fold = std::max<int64_t>(g->n_tiles, g->K > 16 ? g->shape.nb_row : 0);
+    if (need_fold > 0 && w.fold_cap < need_fold) { // row partials folded by the label pass
         if (w.iter_exec) {
             (void)hipGraphExecDestroy(w.iter_exec);
             w.iter_exec = nullptr;
         }
         dfree(w.row_fold);
         w.row_fold = nullptr;
-        if ((s = dalloc((void **)&w.row_fold, sizeof(double) * kRowParts * (size_t)g->n_tiles)) != GFW_OK) return s;
-        w.fold_cap = g->n_tiles;
+        if ((s = dalloc((void **)&w.row_fold, sizeof(double) * kRowParts * (size_t)need_fold)) != GFW_OK) return s;
+        w.fold_cap = need_fold;
     }
     if ((s = dalloc((void **)&w.scratch, sizeof(double) * 3 * std::max(g->shape.nb_row, 64))) != GFW_OK) return s;
     if ((s = dalloc((void **)&w.ctl, sizeof(Ctl))) != GFW_OK) return s;
@@ -900,9 +902,10 @@ static void launch_iteration(gfw_graph_s *g, hipStream_t st, bool traced)
     ev = trace_begin(cx, st);
     if (KMAX <= 16 && g->label_path == 1) // the sorted pass folds the row partials per tile
         k_finish<<<1, kFinishThreads, 0, st>>>(w.row_fold, g->n_tiles, w.lab_part, g->n_tiles, w.ctl);
+    else if (KMAX > 16) // the large-K label pass folds them per 256-row block
+        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_fold, g->shape.nb_row, w.lab_part, g->shape.nb_row, w.ctl);
     else
-        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, KMAX > 16 ? g->shape.nb_big : g->shape.nb_row, w.lab_part,
-                                               g->shape.nb_row, w.ctl);
+        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, g->shape.nb_row, w.lab_part, g->shape.nb_row, w.ctl);
     trace_end(cx, GFW_KERNEL_FINISH, ev, st);
 }
 

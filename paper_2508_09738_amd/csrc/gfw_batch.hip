@@ -454,7 +454,8 @@ static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter, bool w
     }
     const size_t nb_parts = K > 16 ? std::max(nb, (size_t)cdiv(p->n, kBigRowsPerBlock)) : nb;
     const size_t solve = 3 * v * n * K + (K > 16 ? 4 * n + 2 * nnz : 2 * n) + n / 2 + 16 +
-                         8 * ((size_t)(kRowParts + 4) * nb_parts + std::max(tiles, nb) + kRowParts * tiles + 64) +
+                         8 * ((size_t)(kRowParts + 4) * nb_parts + std::max(tiles, nb) +
+                              kRowParts * std::max(tiles, K > 16 ? nb : (size_t)0) + 64) +
                          sizeof(Ctl) +
                          8 * 5 * ((size_t)max_iter + 1) + 4096;
     return graph + solve + (warm ? v * n * K : 0); // a warm start holds its U_0 until retirement

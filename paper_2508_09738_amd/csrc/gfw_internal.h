@@ -48,8 +48,8 @@ struct Workspace {
     uint16_t *nv = nullptr;                        // per CSR entry, the vertex of its column (K > 16)
     double *row_part = nullptr, *lab_part = nullptr, *scratch = nullptr;
     int64_t lab_cap = 0; // entries of lab_part: one per 256-row block or per sorted tile
-    double *row_fold = nullptr; // [kRowParts][n_tiles]: row partials folded per sorted tile
-    int64_t fold_cap = 0;       // tiles row_fold holds
+    double *row_fold = nullptr; // [kRowParts][n_fold]: row partials folded per label-pass block
+    int64_t fold_cap = 0;       // blocks row_fold holds
     Ctl *ctl = nullptr;
     double *hist = nullptr;
     int64_t hist_cap = 0;
@@ -146,6 +146,14 @@ void refresh_solve_bytes(gfw_graph_s *g);
 SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm);
 
 // view of a graph and its solve workspace for the per-iteration kernels
+// Label-pass blocks that fold the row kernel's partials for the finish: the sorted tiles, or
+// the 256-row blocks of the large-K label pass; 0 on the plain pass.
+inline int64_t fold_blocks(const gfw_graph_s *g)
+{
+    if (g->K > 16) return g->shape.nb_row;
+    return g->label_path == 1 ? g->n_tiles : 0;
+}
+
 template <typename T>
 GraphView<T> make_view(const gfw_graph_s *g)
 {
@@ -168,7 +176,8 @@ GraphView<T> make_view(const gfw_graph_s *g)
     v.ctl = w.ctl;
     v.row_part = w.row_part;
     v.lab_part = w.lab_part;
-    v.row_fold = (g->label_path == 1 && g->K <= 16) ? w.row_fold : nullptr;
+    v.n_fold = (int32_t)fold_blocks(g);
+    v.row_fold = v.n_fold > 0 ? w.row_fold : nullptr;
     v.nb_row = g->shape.nb_row;
     v.nb_big = g->shape.nb_big;
     v.n_tiles = g->label_path == 1 ? g->n_tiles : 0;

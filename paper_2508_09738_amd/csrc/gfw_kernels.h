@@ -276,7 +276,8 @@ struct GraphView {
     uint16_t *nv;     // per CSR entry, the last evaluated vertex of its column (large-K kernels)
     Ctl *ctl;
     double *row_part, *lab_part;
-    double *row_fold; // sorted pass: the row partials folded per tile, [kRowParts][n_tiles] (else null)
+    double *row_fold; // the row partials folded per label-pass block, [kRowParts][n_fold] (else null)
+    int32_t n_fold;   // label-pass blocks that fold: sorted tiles, or the 256-row blocks for K > 16
     int32_t nb_row;   // 256-row tiles (row kernel, plain label pass, SpMM)
     int32_t nb_big;   // blocks of the large-K row kernel (stride of its partials)
     int32_t n_tiles;  // tiles of the column-sorted label pass (0: plain pass)
@@ -1206,8 +1207,8 @@ template <typename T>
 static __global__ void __launch_bounds__(kFinishThreads) k_finish_batch(const GraphView<T> *__restrict__ views)
 {
     const GraphView<T> &gv = views[blockIdx.x];
-    if (gv.row_fold) // sorted label pass: row partials folded per tile
-        finish_body(gv.row_fold, gv.n_tiles, gv.lab_part, gv.n_tiles, gv.ctl);
+    if (gv.row_fold) // row partials folded by the label pass, one per label-pass block
+        finish_body(gv.row_fold, gv.n_fold, gv.lab_part, gv.n_fold, gv.ctl);
     else
         finish_body(gv.row_part, gv.nb_big > 0 ? gv.nb_big : gv.nb_row, gv.lab_part, gv.nb_row, gv.ctl);
 }

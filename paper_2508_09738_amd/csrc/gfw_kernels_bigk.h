@@ -30,7 +30,7 @@
 namespace gfw {
 
 constexpr int kBigThreads = 256;                             // 4 wavefronts per block
-constexpr int kBigRowsPerWave = 4;                           // rows a wavefront takes in turn
+constexpr int kBigRowsPerWave = 2;                           // rows a wavefront takes in turn
 constexpr int kBigRowsPerBlock = kBigRowsPerWave * (kBigThreads / 64);
 
 // Wavefront minimum (the DPP steps of wave_sum).
@@ -276,6 +276,18 @@ __device__ __forceinline__ void label_big_body(const GraphView<T> &gv, const int
     if (!ctl->active) return;
     const uint16_t *__restrict__ s = reinterpret_cast<const uint16_t *>((ctl->k & 1) ? gv.s1 : gv.s0);
     const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x;
+    // the row kernel's partials of a fixed slice of its blocks, folded into this block's entry
+    // of row_fold (loaded here by the first wavefront, summed at the end), so that the finish
+    // reads nb_row partials instead of nb_big
+    const int nbb = gv.nb_big, nbr = gv.nb_row;
+    const int fb0 = (int)((int64_t)tile * nbb / nbr), fb1 = (int)((int64_t)(tile + 1) * nbb / nbr);
+    double fold[kRowParts];
+#pragma unroll
+    for (int j = 0; j < kRowParts; ++j) fold[j] = 0.0;
+    if (threadIdx.x < 64)
+        for (int b = fb0 + (int)threadIdx.x; b < fb1; b += 64)
+#pragma unroll
+            for (int j = 0; j < kRowParts; ++j) fold[j] += gv.row_part[(int64_t)j * nbb + b];
     double own = 0.0;
     if (i < gv.n) {
         const int32_t si = (int32_t)s[i];
@@ -287,6 +299,13 @@ __device__ __forceinline__ void label_big_body(const GraphView<T> &gv, const int
             if ((int32_t)sj == si) acc += gv.a[e];
         }
         own = (double)(acc + (gv.diag_one ? (T)1 : (T)0));
+    }
+    if (threadIdx.x < 64) { // the whole first wavefront
+#pragma unroll
+        for (int j = 0; j < kRowParts; ++j) fold[j] = wave_sum(fold[j]);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int j = 0; j < kRowParts; ++j) gv.row_fold[(int64_t)j * nbr + tile] = fold[j];
     }
     double v[1] = {own};
     block_sum_store_strided<1>(v, gv.lab_part + tile, gv.nb_row);
