@@ -251,7 +251,8 @@ __device__ __forceinline__ void block_sum_store_strided(double (&v)[N], double *
     }
 }
 
-constexpr int kLabelTile = 2048; // CSR entries staged in LDS per step of the label pass
+constexpr int kLabelTile = 2048;       // CSR entries staged in LDS per step of the SpMM and batched label pass
+constexpr int kLabelTileSingle = 4096; // the same for the single-graph label pass (more gathers in flight)
 constexpr int kSortedThreads = 1024;   // threads per tile of the column-sorted label pass
 constexpr int kSortedMaxEntries = 131072; // CSR entries per tile (17-bit offsets, at most 128 KB of labels)
 constexpr int kSortedOffsetBits = 17;     // low bits of a column-sorted word: the entry's CSR offset
@@ -512,7 +513,10 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
 // with coalesced accesses and gather the one-byte labels of the columns; then each thread
 // sums the entries of its own row in CSR order.  Q is staged in LDS (dynamic, kRowBlock *
 // K * sizeof(T)) and written back coalesced.  One partial per tile: lab_part[tile].
-template <typename T, typename ST, int KB>
+// LT entries per sub-tile: the single-graph launch stages 4,096 (16 gathers in flight per
+// thread), the batched launch 2,048 (half the LDS, so more blocks of a mixed batch share a
+// CU); the sub-tiles do not change any sum.
+template <typename T, typename ST, int KB, int LT>
 __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int tile)
 {
     const int64_t n = gv.n;
@@ -528,8 +532,8 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
     double *__restrict__ part = gv.lab_part;
     if (!ctl->active) return;
     const ST *__restrict__ s = (ctl->k & 1) ? s1 : s0;
-    __shared__ ST ls[kLabelTile];
-    __shared__ T lv[kLabelTile];
+    __shared__ ST ls[LT];
+    __shared__ T lv[LT];
     extern __shared__ unsigned char lds_raw[];
     T *lq = reinterpret_cast<T *>(lds_raw);
     const int tid = threadIdx.x;
@@ -542,9 +546,9 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
     T acc[KB];
 #pragma unroll
     for (int c = 0; c < KB; ++c) acc[c] = (T)0;
-    constexpr int PER = kLabelTile / kRowBlock;
-    for (int32_t t0 = t_begin; t0 < t_end; t0 += kLabelTile) {
-        const int cnt = (int)min((int32_t)kLabelTile, t_end - t0);
+    constexpr int PER = LT / kRowBlock;
+    for (int32_t t0 = t_begin; t0 < t_end; t0 += LT) {
+        const int cnt = (int)min((int32_t)LT, t_end - t0);
         // issue every load of the tile before using any of them: indices and values (clamped
         // to the last entry of the tile, so that every address is valid), then the label
         // gathers, then the LDS stores
@@ -1028,7 +1032,7 @@ static __global__ void __launch_bounds__(kRowBlock) k_row_batch(const GraphView<
 template <typename T, typename ST, int KB>
 static __global__ void __launch_bounds__(kRowBlock) k_label(GraphView<T> gv)
 {
-    label_body<T, ST, KB>(gv, blockIdx.x);
+    label_body<T, ST, KB, kLabelTileSingle>(gv, blockIdx.x);
 }
 
 template <typename T, typename ST, int KB>
@@ -1036,7 +1040,7 @@ static __global__ void __launch_bounds__(kRowBlock) k_label_batch(const GraphVie
                                                             const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
-    label_body<T, ST, KB>(views[r.graph], r.tile);
+    label_body<T, ST, KB, kLabelTile>(views[r.graph], r.tile);
 }
 
 template <typename T, typename ST, int KB>
