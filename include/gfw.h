@@ -240,10 +240,13 @@ typedef enum {
     GFW_KERNEL_SPMM = 3,   /* L_s U                                                          */
     GFW_KERNEL_COUNT = 4
 } gfw_kernel_t;
-/* When enabled, every hot-path launch made through ctx is bracketed by HIP events on the
- * launch stream; durations are accumulated when the owning call completes (tracing makes
- * gfw_solve synchronise its stream).  gfw_trace_get returns the summed milliseconds and
- * the launch count of a kernel class since the last reset. */
+/* enable: 0 = off; 1 = every hot-path launch made through ctx is bracketed by HIP events on
+ * the launch stream; 2 = only the label passes (GFW_KERNEL_LABEL) are.  While tracing,
+ * gfw_solve launches each iteration's kernels one by one instead of replaying captured
+ * iterations.  Durations are accumulated when the owning call completes (tracing makes
+ * gfw_solve synchronise its stream).  gfw_trace_get returns the summed milliseconds and the
+ * launch count of a kernel class since the last reset.  GFW_E_INVALID_ARG for another value
+ * of enable. */
 GFW_API gfw_status_t gfw_trace_enable(gfw_context_t ctx, int enable);
 GFW_API gfw_status_t gfw_trace_reset(gfw_context_t ctx);
 GFW_API gfw_status_t gfw_trace_get(gfw_context_t ctx, int32_t kernel, double *total_ms, int64_t *launches);

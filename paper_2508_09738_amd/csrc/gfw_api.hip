@@ -50,9 +50,9 @@ static hipEvent_t pool_event(gfw_context_s *c)
     return c->ev_pool[c->ev_used++];
 }
 
-hipEvent_t trace_begin(gfw_context_s *c, hipStream_t st)
+hipEvent_t trace_begin(gfw_context_s *c, int kernel, hipStream_t st)
 {
-    if (!c || !c->trace) return nullptr;
+    if (!c || !c->trace || !((c->trace_mask >> kernel) & 1u)) return nullptr;
     hipEvent_t a = pool_event(c);
     if (a) (void)hipEventRecord(a, st);
     return a;
@@ -893,13 +893,13 @@ static void launch_iteration(gfw_graph_s *g, hipStream_t st, bool traced)
 {
     Workspace &w = g->ws;
     gfw_context_s *cx = traced ? g->ctx : nullptr;
-    hipEvent_t ev = trace_begin(cx, st);
+    hipEvent_t ev = trace_begin(cx, GFW_KERNEL_ROW, st);
     launch_row<T, KMAX>(g, 0, st);
     trace_end(cx, GFW_KERNEL_ROW, ev, st);
-    ev = trace_begin(cx, st);
+    ev = trace_begin(cx, GFW_KERNEL_LABEL, st);
     launch_label<T, KMAX>(g, st);
     trace_end(cx, GFW_KERNEL_LABEL, ev, st);
-    ev = trace_begin(cx, st);
+    ev = trace_begin(cx, GFW_KERNEL_FINISH, st);
     if (KMAX <= 16 && g->label_path == 1) // the sorted pass folds the row partials per tile
         k_finish<<<1, kFinishThreads, 0, st>>>(w.row_fold, g->n_tiles, w.lab_part, g->n_tiles, w.ctl);
     else if (KMAX > 16) // the large-K label pass folds them per 256-row block
@@ -958,7 +958,7 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     const int64_t nK = g->n * g->K;
     k_init_u<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), (const T *)prm->U0);
     gfw_context_s *cx = g->ctx;
-    hipEvent_t ev = trace_begin(cx, st);
+    hipEvent_t ev = trace_begin(cx, GFW_KERNEL_SPMM, st);
     spmm_any<T>(g, U, P, st);
     trace_end(cx, GFW_KERNEL_SPMM, ev, st);
     const bool use_graph = !cx->trace && prm->p_refresh == 0 && prm->max_iter >= kGraphChunk;
@@ -1225,7 +1225,9 @@ gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t 
 gfw_status_t gfw_trace_enable(gfw_context_t ctx, int enable)
 {
     if (!ctx) return fail(GFW_E_INVALID_ARG, "ctx is NULL");
+    if (enable < 0 || enable > 2) return fail(GFW_E_INVALID_ARG, "trace mode must be 0, 1 or 2 (got %d)", enable);
     ctx->trace = enable != 0;
+    ctx->trace_mask = enable == 1 ? (1u << GFW_KERNEL_COUNT) - 1u : enable == 2 ? 1u << GFW_KERNEL_LABEL : 0u;
     return GFW_OK;
 }
 

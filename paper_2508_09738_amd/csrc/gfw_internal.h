@@ -75,7 +75,8 @@ struct gfw_context_s {
     int num_cu = 0;
     std::string arch;
     // tracing: events bracketing hot-path launches, resolved when the owning call ends
-    bool trace = false;
+    bool trace = false;       // hot-path launches bracketed by events (no captured iterations)
+    uint32_t trace_mask = 0;  // kernel classes timed while tracing (bit k: class k)
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     struct Rec {
@@ -90,7 +91,7 @@ struct gfw_context_s {
 namespace gfw {
 // Records a start event for a traced launch (no-op when tracing is off); returns the
 // event to hand to trace_end.
-hipEvent_t trace_begin(gfw_context_s *c, hipStream_t st);
+hipEvent_t trace_begin(gfw_context_s *c, int kernel, hipStream_t st);
 void trace_end(gfw_context_s *c, int kernel, hipEvent_t a, hipStream_t st);
 // Waits for `st` and folds the pending records into the totals.
 gfw_status_t trace_flush(gfw_context_s *c, hipStream_t st);

@@ -246,7 +246,11 @@ def solve(ctx: Context, g: Graph, prm: Params, want_U: bool = True, want_labels:
     return out
 
 
-def trace_enable(ctx: Context, on: bool = True) -> None:
+TRACE_OFF, TRACE_ALL, TRACE_LABEL = 0, 1, 2
+
+
+def trace_enable(ctx: Context, on=True) -> None:
+    """on: False/True or a trace mode (TRACE_OFF, TRACE_ALL, TRACE_LABEL: label passes only)."""
     check(lib().gfw_trace_enable(ctx.handle, int(on)))
 
 
