@@ -241,7 +241,8 @@ typedef enum {
     GFW_KERNEL_COUNT = 4
 } gfw_kernel_t;
 /* enable: 0 = off; 1 = every hot-path launch made through ctx is bracketed by HIP events on
- * the launch stream; 2 = only the label passes (GFW_KERNEL_LABEL) are.  While tracing,
+ * the launch stream; 2 = only the label passes (GFW_KERNEL_LABEL) are; 3 = only the row
+ * kernels (GFW_KERNEL_ROW) of the iterations are.  While tracing,
  * gfw_solve launches each iteration's kernels one by one instead of replaying captured
  * iterations.  Durations are accumulated when the owning call completes (tracing makes
  * gfw_solve synchronise its stream).  gfw_trace_get returns the summed milliseconds and the

@@ -1225,9 +1225,12 @@ gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t 
 gfw_status_t gfw_trace_enable(gfw_context_t ctx, int enable)
 {
     if (!ctx) return fail(GFW_E_INVALID_ARG, "ctx is NULL");
-    if (enable < 0 || enable > 2) return fail(GFW_E_INVALID_ARG, "trace mode must be 0, 1 or 2 (got %d)", enable);
+    if (enable < 0 || enable > 3) return fail(GFW_E_INVALID_ARG, "trace mode must be 0, 1, 2 or 3 (got %d)", enable);
     ctx->trace = enable != 0;
-    ctx->trace_mask = enable == 1 ? (1u << GFW_KERNEL_COUNT) - 1u : enable == 2 ? 1u << GFW_KERNEL_LABEL : 0u;
+    ctx->trace_mask = enable == 1   ? (1u << GFW_KERNEL_COUNT) - 1u
+                      : enable == 2 ? 1u << GFW_KERNEL_LABEL
+                      : enable == 3 ? 1u << GFW_KERNEL_ROW
+                                    : 0u;
     return GFW_OK;
 }
 

@@ -246,11 +246,12 @@ def solve(ctx: Context, g: Graph, prm: Params, want_U: bool = True, want_labels:
     return out
 
 
-TRACE_OFF, TRACE_ALL, TRACE_LABEL = 0, 1, 2
+TRACE_OFF, TRACE_ALL, TRACE_LABEL, TRACE_ROW = 0, 1, 2, 3
 
 
 def trace_enable(ctx: Context, on=True) -> None:
-    """on: False/True or a trace mode (TRACE_OFF, TRACE_ALL, TRACE_LABEL: label passes only)."""
+    """on: False/True or a trace mode (TRACE_OFF, TRACE_ALL, TRACE_LABEL: label passes only,
+    TRACE_ROW: row kernels only)."""
     check(lib().gfw_trace_enable(ctx.handle, int(on)))
 
 
