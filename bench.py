@@ -431,8 +431,8 @@ def main() -> int:
     if args.calibrate_copy:
         return calibrate_copy()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design, "
-              "not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no multi-GPU "
+              "path.", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -1,4 +1,4 @@
-// Host side of libgfw: argument checks, graph set-up, the solve driver, objective and
+// Host side of libgfw: argument checks, graph set-up, the solve loop, objective and
 // SpMM entry points.  See include/gfw.h for the contract of every exported function.
 #include <hip/hip_runtime.h>
 
