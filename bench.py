@@ -183,17 +183,47 @@ def derive_traffic(d: str) -> int:
     return 0
 
 
-def cpu_baseline(prob, iters: int) -> dict:
+def cpu_model() -> str:
+    """The host CPU's model name, from /proc/cpuinfo."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, iters_serial: int, iters_parallel: int) -> dict:
+    """The FP64 oracle on the same graph, timed on the host: the serial build on one core and
+    the OpenMP timing build (row loops over all the threads OpenMP is given; bit for bit the
+    serial results) on all of them.  Each leg times `iters` iterations with the stop test
+    disabled; the objective evaluation the oracle makes after its last iteration is timed on
+    its own and subtracted, so the rate covers the iterations only."""
     from oracle import oracle as O
 
     O.build(force=False)
     L = O.operator_for(prob.graph)
-    t0 = time.perf_counter()
-    O.solve(L, prob.K, prob.labelled_idx, prob.labels, eps=prob.eps, omega0=prob.omega0, max_iter=iters, tol=-1.0)
-    dt = time.perf_counter() - t0
-    return {"value": iters / dt, "unit": "FW iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} iterations of the same graph (n={prob.n}, nnz={prob.graph.nnz}, K={prob.K}), "
-                      f"FP64, serial C, including the final objective evaluation; {dt:.1f} s"}
+    Uhat, omega = O.fidelity(prob.n, prob.K, prob.labelled_idx, prob.labels, prob.omega0)
+    legs = {}
+    for name, parallel, iters in (("serial", False, iters_serial), ("parallel", True, iters_parallel)):
+        t0 = time.perf_counter()
+        O.objective(L, Uhat, Uhat, omega, prob.eps, parallel=parallel)  # the same evaluation, same build
+        t_obj = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.solve(L, prob.K, prob.labelled_idx, prob.labels, eps=prob.eps, omega0=prob.omega0, max_iter=iters,
+                tol=-1.0, parallel=parallel)
+        dt = time.perf_counter() - t0
+        legs[name] = (iters / max(dt - t_obj, 1e-9), dt, O.threads(parallel), iters, t_obj)
+    v, dt, thr, it, t_obj = legs["parallel"]
+    vs, dts, _, its, t_objs = legs["serial"]
+    return {"value": v, "unit": "FW iterations/s", "cores": thr, "kind": "oracle",
+            "sample": f"{it} iterations of the same graph (n={prob.n}, nnz={prob.graph.nnz}, K={prob.K}), FP64, "
+                      f"OpenMP build of the oracle over {thr} threads ({dt:.1f} s, the final objective "
+                      f"evaluation of {t_obj:.2f} s subtracted); serial build: {its} iterations, {dts:.1f} s "
+                      f"({t_objs:.2f} s subtracted)",
+            "serial_value": vs, "serial_cores": 1, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
 def bench_many_classes(gfw, ctx, steps: int = 3, n: int = 100_000, K: int = 585) -> dict:
@@ -418,7 +448,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--iters", type=int, default=1000)
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=8, help="oracle iterations timed on one core")
+    ap.add_argument("--cpu-par-iters", type=int, default=24, help="oracle iterations timed on all cores")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="graphs in the batch measurement (0: skip)")
     ap.add_argument("--serve", type=int, default=160, help="requests under load in the serving measurement (0: skip)")
@@ -547,8 +578,8 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu:
-        log(f"[bench] cpu baseline: {args.cpu_iters} oracle iterations")
-        cpu = cpu_baseline(prob, args.cpu_iters)
+        log(f"[bench] cpu baseline: {args.cpu_iters} serial and {args.cpu_par_iters} parallel oracle iterations")
+        cpu = cpu_baseline(prob, args.cpu_iters, args.cpu_par_iters)
 
     out = {
         "metric": "FW iters/s + SpMM HBM GB/s (% peak); batched/served solves/s & p99 vs plain",

@@ -13,6 +13,12 @@
  * definitions cited at each function.  Compiled with -ffp-contract=off so that
  * a*b+c is two roundings, as written.
  *
+ * Timing build.  Compiled with -fopenmp -DORC_OPENMP, the loops marked ROW_LOOP
+ * (loops over rows whose iterations write disjoint outputs and read nothing another
+ * iteration writes) are split over threads.  Every sum that crosses rows stays a
+ * serial loop in index order, so the timing build returns bit for bit what the
+ * serial build returns; the serial build is the one the parity tests use.
+ *
  * Readings where the paper is silent (each is also listed in the design notes):
  *  - argmin/argmax ties are broken towards the lowest class index;
  *  - d_i = 0 (isolated node) gives d_i^{-1/2} = 0, so row i of L_s is e_i;
@@ -30,6 +36,15 @@
 #include <string.h>
 
 #include "gfw_oracle.h"
+
+#ifdef ORC_OPENMP
+#include <omp.h>
+#define ROW_LOOP _Pragma("omp parallel for schedule(static)")
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+#define ROW_LOOP
+int orc_threads(void) { return 1; }
+#endif
 
 /* ------------------------------------------------------------------------- */
 /* Graph quantities (Section 1: degrees, L = D - W, L_s = I - D^-1/2 W D^-1/2) */
@@ -101,6 +116,7 @@ int64_t orc_build_sym_laplacian(int64_t n, const int64_t *rp, const int32_t *ci,
 int orc_spmm(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const double *v,
              const double *U, double *P)
 {
+    ROW_LOOP
     for (int64_t i = 0; i < n; ++i) {
         for (int32_t c = 0; c < K; ++c) {
             double s = 0.0;
@@ -150,6 +166,7 @@ double orc_objective(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci,
 int orc_gradient_from_P(int64_t n, int32_t K, const double *P, const double *U, const double *Uhat,
                         const double *omega, double inv_eps, double *G)
 {
+    ROW_LOOP
     for (int64_t i = 0; i < n; ++i) {
         for (int32_t c = 0; c < K; ++c) {
             double u = U[i * K + c];
@@ -184,6 +201,9 @@ static int row_is_binary(const double *u, int32_t K)
 int64_t orc_lmo(int64_t n, int32_t K, const double *U, const double *G, int mode, int32_t *s)
 {
     int64_t nonbinary = 0;
+#ifdef ORC_OPENMP
+#pragma omp parallel for schedule(static) reduction(+ : nonbinary)
+#endif
     for (int64_t i = 0; i < n; ++i) {
         const double *u = U + i * K;
         const double *g = G + i * K;
@@ -288,13 +308,11 @@ int orc_solve(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const 
         if (s_hist) memcpy(s_hist + (int64_t)k * n, s, sizeof(int32_t) * (size_t)n);
 
         /* D_k = S_k - U_k and the gap g_k = -<grad E(U_k), D_k> */
-        double gd = 0.0;
+        ROW_LOOP
         for (int64_t i = 0; i < n; ++i)
-            for (int32_t c = 0; c < K; ++c) {
-                double d = (c == s[i] ? 1.0 : 0.0) - U[i * K + c];
-                Dm[i * K + c] = d;
-                gd += G[i * K + c] * d;
-            }
+            for (int32_t c = 0; c < K; ++c) Dm[i * K + c] = (c == s[i] ? 1.0 : 0.0) - U[i * K + c];
+        double gd = 0.0;
+        for (int64_t t = 0; t < nK; ++t) gd += G[t] * Dm[t];
         double g = -gd;
         out.gap = g;
         if (isnan(g) || isnan(Ek)) {
@@ -356,6 +374,7 @@ int orc_solve(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const 
 
         /* step 6: U_{k+1} = (1 - a) U_k + a S_k; a row whose direction d_i is zero (a
          * binary row kept by the GLMO) is left exactly as it is */
+        ROW_LOOP
         for (int64_t i = 0; i < n; ++i) {
             int zero_dir = 1;
             for (int32_t c = 0; c < K; ++c)
@@ -363,7 +382,8 @@ int orc_solve(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const 
             if (zero_dir) continue;
             for (int32_t c = 0; c < K; ++c) {
                 double sv = c == s[i] ? 1.0 : 0.0;
-                U[i * K + c] = (1.0 - alpha) * U[i * K + c] + alpha * sv;
+                double u = (1.0 - alpha) * U[i * K + c] + alpha * sv;
+                U[i * K + c] = prm->store_f32 ? (double)(float)u : u;
             }
         }
         if (prm->osfw) { ++k; break; }

@@ -22,6 +22,8 @@ typedef struct {
     int32_t osfw;        /* 1: one-shot FW (U_1 = S_0)                         */
     double lipschitz;    /* Lbar for the short step                            */
     int32_t armijo_direct; /* 1: evaluate E at Armijo trial points directly    */
+    int32_t store_f32;   /* 1: round U to the nearest FP32 value after every
+                            update (models FP32 storage of the iterate)        */
 } orc_params_t;
 
 typedef struct {
@@ -39,6 +41,9 @@ double orc_objective(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci,
 int orc_gradient_from_P(int64_t n, int32_t K, const double *P, const double *U, const double *Uhat,
                         const double *omega, double inv_eps, double *G);
 int64_t orc_lmo(int64_t n, int32_t K, const double *U, const double *G, int mode, int32_t *s);
+/* threads the row loops may use: 1 in the serial build, the OpenMP team size in
+ * the timing build (compiled with -fopenmp -DORC_OPENMP) */
+int orc_threads(void);
 int orc_solve(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const double *v,
               const double *Uhat, const double *omega, const orc_params_t *prm,
               double *U, int32_t *labels, orc_stats_t *st, double *hist, int32_t *s_hist,

@@ -21,6 +21,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gfw_oracle.c")
 _LIB = os.path.join(_HERE, "libgfw_oracle.so")
+# timing build of the same source: the row loops split over OpenMP threads, every sum
+# across rows serial, so it returns bit for bit what the serial build returns
+_LIB_OMP = os.path.join(_HERE, "libgfw_oracle_omp.so")
 
 LMO_GREEDY, LMO_FULL = 0, 1
 LS_ARMIJO, LS_EXACT, LS_SHORT = 0, 1, 2
@@ -28,12 +31,13 @@ STOP_MAXITER, STOP_TOL, STOP_NUMERIC = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no FP contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall", "-Wextra",
-               "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
-        subprocess.run(cmd, check=True, cwd=_HERE)
-        os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle with gcc (plain -O2, no FP contraction, no fast-math): the serial
+    build the tests use, and the OpenMP timing build of the same source."""
+    base = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC"]
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp", "-DORC_OPENMP"])):
+        if force or not os.path.exists(out):
+            subprocess.run(base + extra + ["-o", out + ".tmp", _SRC, "-lm"], check=True, cwd=_HERE)
+            os.replace(out + ".tmp", out)
     return _LIB
 
 
@@ -41,7 +45,7 @@ class _Params(C.Structure):
     _fields_ = [("eps", C.c_double), ("omega0", C.c_double), ("max_iter", C.c_int32),
                 ("tol", C.c_double), ("ls", C.c_int32), ("delta", C.c_double), ("gamma", C.c_double),
                 ("lmo", C.c_int32), ("osfw", C.c_int32), ("lipschitz", C.c_double),
-                ("armijo_direct", C.c_int32)]
+                ("armijo_direct", C.c_int32), ("store_f32", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -49,15 +53,16 @@ class _Stats(C.Structure):
                 ("objective", C.c_double), ("alpha_last", C.c_double)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def lib(parallel: bool = False):
+    """The serial build (parallel=False, the parity reference) or the OpenMP timing build."""
+    path = _LIB_OMP if parallel else _LIB
+    if path not in _libs:
+        if not os.path.exists(path):
             build(force=True)
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
         p = C.c_void_p
         L.orc_build_sym_laplacian.restype = C.c_int64
         L.orc_build_sym_laplacian.argtypes = [C.c_int64, p, p, p, p, p, p]
@@ -69,8 +74,15 @@ def lib():
         L.orc_lmo.argtypes = [C.c_int64, C.c_int32, p, p, C.c_int, p]
         L.orc_solve.argtypes = [C.c_int64, C.c_int32, p, p, p, p, p, C.POINTER(_Params), p, p,
                                 C.POINTER(_Stats), p, p, p]
-        _lib = L
-    return _lib
+        L.orc_threads.restype = C.c_int
+        L.orc_threads.argtypes = []
+        _libs[path] = L
+    return _libs[path]
+
+
+def threads(parallel: bool = False) -> int:
+    """Threads the row loops of a build use (1 for the serial build)."""
+    return int(lib(parallel).orc_threads())
 
 
 def _p(a):
@@ -151,10 +163,10 @@ def inv_eps(eps: float) -> float:
     return 0.0 if math.isinf(eps) else 1.0 / eps
 
 
-def objective(L: Operator, U, Uhat, omega, eps: float) -> float:
+def objective(L: Operator, U, Uhat, omega, eps: float, parallel: bool = False) -> float:
     U, Uhat, omega = _f64(U), _f64(Uhat), _f64(omega)
     n, K = U.shape
-    return lib().orc_objective(n, K, _p(L.indptr), _p(L.indices), _p(L.data), _p(U), _p(Uhat), _p(omega),
+    return lib(parallel).orc_objective(n, K, _p(L.indptr), _p(L.indices), _p(L.data), _p(U), _p(Uhat), _p(omega),
                                inv_eps(eps))
 
 
@@ -176,24 +188,31 @@ def lmo(U, G, mode: int = LMO_GREEDY):
     return s, int(nb)
 
 
+def default_lipschitz(L: Operator, eps: float, omega0: float) -> float:
+    """Prop. 2: Lbar = lambda_max(L) + 2/eps + omega0, with lambda_max bounded above by the
+    largest absolute row sum of L (Gershgorin), which keeps Lbar a Lipschitz constant of the
+    gradient (the short step of eq. alphabound needs an upper bound, not the exact value)."""
+    rs = np.zeros(L.n)
+    np.add.at(rs, np.repeat(np.arange(L.n), np.diff(L.indptr)), np.abs(L.data))
+    return float(rs.max(initial=0.0)) + 2.0 * inv_eps(eps) + omega0
+
+
 def solve(L: Operator, K: int, labelled_idx, labels, eps: float = 50.0, omega0: float = 1000.0,
           max_iter: int = 30, tol: float = 1e-6, ls: int = LS_ARMIJO, delta: float = 0.5,
           gamma: float = 1e-6, lmo_mode: int = LMO_GREEDY, osfw: bool = False,
           lipschitz: float | None = None, armijo_direct: bool = False, U0=None,
-          record_s: bool = False, s_first=None) -> dict:
+          record_s: bool = False, s_first=None, store_f32: bool = False, parallel: bool = False) -> dict:
     """Greedy Frank-Wolfe (Alg. 3) with Armijo / exact / short steps; FW (Alg. 2) with
-    lmo_mode=LMO_FULL; OSFW (Alg. 4) with osfw=True.  Returns U, labels, stats, history."""
+    lmo_mode=LMO_FULL; OSFW (Alg. 4) with osfw=True.  Returns U, labels, stats, history.
+    store_f32 rounds U to FP32 after every update (FP64 arithmetic, FP32 storage of the
+    iterate); parallel runs the OpenMP timing build (same results, bit for bit)."""
     n = L.n
     Uhat, omega = fidelity(n, K, labelled_idx, labels, omega0)
     U = Uhat.copy() if U0 is None else np.array(U0, dtype=np.float64, copy=True)
     if lipschitz is None:
-        # Prop. 2: Lbar = lambda_max(L) + 2/eps + omega0, with lambda_max bounded by the
-        # largest absolute row sum (Gershgorin)
-        rs = np.zeros(n)
-        np.add.at(rs, np.repeat(np.arange(n), np.diff(L.indptr)), np.abs(L.data))
-        lipschitz = float(rs.max(initial=0.0)) + 2.0 * inv_eps(eps) + omega0
+        lipschitz = default_lipschitz(L, eps, omega0)
     prm = _Params(eps, omega0, max_iter, tol, ls, delta, gamma, lmo_mode, int(osfw), lipschitz,
-                  int(armijo_direct))
+                  int(armijo_direct), int(store_f32))
     st = _Stats()
     hist = np.full((5, max_iter + 1), np.nan)
     s_hist = np.zeros((max_iter + 1, n), np.int32) if record_s else None
@@ -201,7 +220,7 @@ def solve(L: Operator, K: int, labelled_idx, labels, eps: float = 50.0, omega0: 
     sf = None if s_first is None else _i32(s_first)
     if sf is not None and sf.shape != (n,):
         raise ValueError("s_first needs one vertex per node")
-    rc = lib().orc_solve(n, K, _p(L.indptr), _p(L.indices), _p(L.data), _p(Uhat), _p(omega), C.byref(prm),
+    rc = lib(parallel).orc_solve(n, K, _p(L.indptr), _p(L.indices), _p(L.data), _p(Uhat), _p(omega), C.byref(prm),
                          _p(U), _p(lab), C.byref(st), _p(hist), _p(s_hist), _p(sf))
     if rc != 0:
         raise RuntimeError(f"orc_solve failed ({rc})")

@@ -23,6 +23,9 @@ FLAGS = [
     "-Wno-unused-result",
     # packed FP32 instructions are not used by this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a*b + c is two roundings, as written (no fused multiply-add contraction): the FP64
+    # sums of L U then round exactly as a plain CSR loop over the operator does
+    "-ffp-contract=off",
     "-fvisibility=hidden",
 ]
 
@@ -32,12 +35,29 @@ def sources() -> list:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into paper_2508_09738_amd/libgfw.so (always rebuilds)."""
-    out_tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", out_tmp] + sources()
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True, cwd=CSRC)
+    """Compile every HIP source into paper_2508_09738_amd/libgfw.so (always rebuilds).  The
+    sources compile to objects in parallel, then link."""
+    import tempfile
+
+    inc = ["-I", os.path.join(ROOT, "include")]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="gfw_build_") as tmp:
+        objs, procs = [], []
+        for src in sources():
+            obj = os.path.join(tmp, os.path.basename(src) + ".o")
+            cmd = [HIPCC] + compile_flags + inc + ["-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((subprocess.Popen(cmd, cwd=CSRC), cmd))
+            objs.append(obj)
+        for pr, cmd in procs:
+            if pr.wait() != 0:
+                raise subprocess.CalledProcessError(pr.returncode, cmd)
+        out_tmp = LIB + ".tmp"
+        cmd = [HIPCC] + FLAGS + ["-o", out_tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True, cwd=CSRC)
     os.replace(out_tmp, LIB)
     return LIB
 

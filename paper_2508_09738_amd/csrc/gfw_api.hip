@@ -343,8 +343,8 @@ void refresh_solve_bytes(gfw_graph_s *g)
     const size_t row_parts = kRowParts * std::max<size_t>(nb, (size_t)g->shape.nb_big);
     const size_t lab = std::max<size_t>(nb, (size_t)g->n_tiles) // label partials, folded row partials
                        + kRowParts * std::max<size_t>((size_t)g->n_tiles, K > 16 ? nb : 0);
-    const size_t scratch = 3 * std::max<size_t>(nb, 64);
-    g->solve_bytes = 3 * vs * n * K                     // U, P, Q
+    const size_t scratch = 3 * std::max<size_t>({nb, (size_t)g->shape.nb_big, 64});
+    g->solve_bytes = (2 * vs + 8) * n * K               // U, Q; P in FP64
                      + (K > 16 ? 4 * n + 2 * nnz : 2 * n) // vertex pair (and nv for K > 16)
                      + (n + 1) / 2                        // packed vertices
                      + sizeof(double) * (row_parts + lab + scratch) + sizeof(Ctl);
@@ -642,7 +642,7 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
     };
     gfw_status_t s;
     if ((s = dalloc(&w.U, vs * nK)) != GFW_OK) return s;
-    if ((s = dalloc(&w.P, vs * nK)) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.P, sizeof(double) * nK)) != GFW_OK) return s;
     if ((s = dalloc(&w.Q, vs * nK)) != GFW_OK) return s;
     const size_t sb = g->K > 16 ? 2 : 1; // vertex bytes: 16-bit for the large-K kernels
     if ((s = dalloc((void **)&w.s0, sb * g->n)) != GFW_OK) return s;
@@ -678,7 +678,9 @@ gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter)
         if ((s = dalloc((void **)&w.row_fold, sizeof(double) * kRowParts * (size_t)need_fold)) != GFW_OK) return s;
         w.fold_cap = need_fold;
     }
-    if ((s = dalloc((void **)&w.scratch, sizeof(double) * 3 * std::max(g->shape.nb_row, 64))) != GFW_OK) return s;
+    if ((s = dalloc((void **)&w.scratch, sizeof(double) * 3 * std::max({g->shape.nb_row, g->shape.nb_big, 64}))) !=
+        GFW_OK)
+        return s;
     if ((s = dalloc((void **)&w.ctl, sizeof(Ctl))) != GFW_OK) return s;
     const int64_t need = 5 * ((int64_t)max_iter + 1);
     if (w.hist_cap < need) {
@@ -715,11 +717,11 @@ static void set_lds_limits()
     (void)hipFuncSetAttribute((const void *)k_label_sorted<T, uint8_t, KX>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                               kSortedMaxEntries);                                                                \
     (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KX>, hipFuncAttributeMaxDynamicSharedMemorySize,    \
-                              3 * (int)sizeof(T) * kRowBlock * KX);
+                              (int)row_lds_per_class<T>() * KX);
         GFW_FOR_EACH_SORTED_K(GFW_SET_SORTED)
 #undef GFW_SET_SORTED
         (void)hipFuncSetAttribute((const void *)k_row<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  3 * (int)sizeof(T) * kRowBlock * KMAX);
+                                  (int)row_lds_per_class<T>() * KMAX);
     }
 }
 
@@ -737,7 +739,10 @@ static void launch_label_sorted(const gfw_graph_s *g, hipStream_t st)
     }
 }
 
-static size_t row_lds_bytes(const gfw_graph_s *g) { return 3 * dsize(g->dtype) * kRowBlock * (size_t)g->K; }
+static size_t row_lds_bytes(const gfw_graph_s *g)
+{
+    return (g->dtype == GFW_F32 ? row_lds_per_class<float>() : row_lds_per_class<double>()) * (size_t)g->K;
+}
 
 template <typename T>
 static void launch_row_exact(const gfw_graph_s *g, int apply_only, hipStream_t st)
@@ -754,13 +759,13 @@ static void launch_row_exact(const gfw_graph_s *g, int apply_only, hipStream_t s
 }
 
 
-template <typename T, int KMAX>
-static void launch_spmm(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
+template <typename T, int KMAX, typename PT>
+static void launch_spmm(const gfw_graph_s *g, const T *U, PT *P, hipStream_t st)
 {
     if constexpr (KMAX > 16)
-        k_spmm_big<T, KMAX / 64><<<g->shape.nb_big, kBigThreads, 0, st>>>(make_view<T>(g), U, P);
+        k_spmm_big<T, KMAX / 64, PT><<<g->shape.nb_big, kBigThreads, 0, st>>>(make_view<T>(g), U, P);
     else
-        k_spmm<T, KMAX><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), U, P);
+        k_spmm<T, KMAX, PT><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), U, P);
 }
 
 template <typename T, int KMAX>
@@ -851,12 +856,13 @@ static gfw_status_t measure_label_paths(gfw_graph_s *g, hipStream_t st)
     return GFW_OK;
 }
 
-template <typename T>
-static void spmm_any(const gfw_graph_s *g, const T *U, T *P, hipStream_t st)
+// P = L_s U with FP64 sums, stored as PT (the graph's dtype, or FP64 for the carried P)
+template <typename T, typename PT>
+static void spmm_any(const gfw_graph_s *g, const T *U, PT *P, hipStream_t st)
 {
     switch (g->shape.kmax) {
 #define GFW_SPMM_CASE(KM) \
-    case KM: launch_spmm<T, KM>(g, U, P, st); break;
+    case KM: launch_spmm<T, KM, PT>(g, U, P, st); break;
         GFW_FOR_EACH_KMAX(GFW_SPMM_CASE)
 #undef GFW_SPMM_CASE
     default: break;
@@ -941,7 +947,8 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     static const bool lds_set = (set_lds_limits<T, KMAX>(), true); // once per instantiation, thread-safe
     (void)lds_set;
     Workspace &w = g->ws;
-    T *U = (T *)w.U, *P = (T *)w.P;
+    T *U = (T *)w.U;
+    double *P = w.P;
     Ctl c0;
     std::memset(&c0, 0, sizeof(c0));
     c0.active = prm->max_iter > 0 ? 1 : 0;
@@ -1043,18 +1050,48 @@ static gfw_status_t solve_dispatch(gfw_graph_s *g, const gfw_params_t *prm, void
     }
 }
 
+// Block partials of E(U) (no P buffer: each row of L U is used where it is formed); returns
+// the number of partials per quantity written to part ([3][count]).
+template <typename T>
+static int energy_partials(const gfw_graph_s *g, const T *U, double omega0, double *part, hipStream_t st)
+{
+    const GraphView<T> v = make_view<T>(g);
+    switch (g->shape.kmax) {
+    case 4: k_energy<T, 4><<<g->shape.nb_row, kRowBlock, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
+    case 8: k_energy<T, 8><<<g->shape.nb_row, kRowBlock, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
+    case 16: k_energy<T, 16><<<g->shape.nb_row, kRowBlock, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
+#define GFW_ENERGY_BIG(KM)                                                                                       \
+    case KM: k_energy_big<T, KM / 64><<<g->shape.nb_big, kBigThreads, 0, st>>>(v, U, omega0, part);              \
+        return g->shape.nb_big;
+        GFW_ENERGY_BIG(64) GFW_ENERGY_BIG(128) GFW_ENERGY_BIG(192) GFW_ENERGY_BIG(256) GFW_ENERGY_BIG(320)
+        GFW_ENERGY_BIG(384) GFW_ENERGY_BIG(448) GFW_ENERGY_BIG(512) GFW_ENERGY_BIG(576) GFW_ENERGY_BIG(640)
+        GFW_ENERGY_BIG(704) GFW_ENERGY_BIG(768) GFW_ENERGY_BIG(832) GFW_ENERGY_BIG(896) GFW_ENERGY_BIG(960)
+        GFW_ENERGY_BIG(1024)
+#undef GFW_ENERGY_BIG
+    default: return 0;
+    }
+}
+
+// Stream-ordered E(U) into device memory *E_dev: block partials in part ([3][blocks]), then a
+// fixed-order sum.
+template <typename T>
+static gfw_status_t objective_to_device(const gfw_graph_s *g, const gfw_params_t *prm, const T *U, double *part,
+                                        double *E_dev, hipStream_t st)
+{
+    const int nb = energy_partials<T>(g, U, prm->omega0, part, st);
+    if (nb <= 0) return fail(GFW_E_UNSUPPORTED, "no kernels for K = %d", g->K);
+    const double inv_eps = std::isinf(prm->eps) ? 0.0 : 1.0 / prm->eps;
+    k_energy_sum<<<1, kFinishThreads, 0, st>>>(part, nb, inv_eps, E_dev);
+    GFW_HIP_TRY(hipGetLastError());
+    return GFW_OK;
+}
+
 template <typename T>
 static gfw_status_t objective_impl(gfw_graph_s *g, const gfw_params_t *prm, const T *U, double *E, hipStream_t st)
 {
     gfw_status_t s = ensure_workspace(g, 0);
     if (s != GFW_OK) return s;
-    T *P = (T *)g->ws.Q; // Q is free between solves
-    spmm_any<T>(g, U, P, st);
-    const int nb = g->shape.nb_row;
-    k_energy<T><<<nb, kRowBlock, 0, st>>>(make_view<T>(g), U, P, prm->omega0, g->ws.scratch);
-    const double inv_eps = std::isinf(prm->eps) ? 0.0 : 1.0 / prm->eps;
-    k_energy_sum<<<1, kFinishThreads, 0, st>>>(g->ws.scratch, nb, inv_eps, g->ws.row_part);
-    GFW_HIP_TRY(hipGetLastError());
+    if ((s = objective_to_device<T>(g, prm, U, g->ws.scratch, g->ws.row_part, st)) != GFW_OK) return s;
     GFW_HIP_TRY(hipMemcpyAsync(E, g->ws.row_part, sizeof(double), hipMemcpyDeviceToHost, st));
     GFW_HIP_TRY(hipStreamSynchronize(st));
     return GFW_OK;

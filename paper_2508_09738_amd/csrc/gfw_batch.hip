@@ -29,7 +29,7 @@ static void set_batch_lds_limits()
     (void)hipFuncSetAttribute((const void *)k_label_sorted_batch<T, uint8_t, KMAX>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kSortedMaxEntries);
     (void)hipFuncSetAttribute((const void *)k_row_batch<T, uint8_t, KMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              3 * (int)sizeof(T) * kRowBlock * KMAX);
+                              (int)row_lds_per_class<T>() * KMAX);
 }
 
 // --------------------------------------------------------------------------------------
@@ -132,13 +132,15 @@ static gfw_status_t upload(std::vector<E> &v, DevArr<E> &arr, E **d, hipStream_t
 template <typename T>
 static void batch_big_launch(BatchTables<T> &bt, int kind, int flag, hipStream_t st)
 {
-    // kind 0: row kernel (flag = apply_only); kind 1: SpMM (flag = to_q)
+    // kind 0: row kernel (flag = apply_only); kind 1: SpMM P_0 = L_s U_0; kind 2: objective partials
 #define GFW_BIG_BUCKET(B, MC)                                                                                    \
     if (!bt.big_rows[B].empty()) {                                                                             \
         if (kind == 0)                                                                                         \
             k_row_big_batch<T, MC><<<bt.big_rows[B].size(), kBigThreads, 0, st>>>(bt.d_views, bt.d_big[B], flag); \
+        else if (kind == 1)                                                                                    \
+            k_spmm_big_batch<T, MC><<<bt.big_rows[B].size(), kBigThreads, 0, st>>>(bt.d_views, bt.d_big[B]);   \
         else                                                                                                   \
-            k_spmm_big_batch<T, MC><<<bt.big_rows[B].size(), kBigThreads, 0, st>>>(bt.d_views, bt.d_big[B], flag); \
+            k_energy_big_batch<T, MC><<<bt.big_rows[B].size(), kBigThreads, 0, st>>>(bt.d_views, bt.d_big[B]); \
     }
     GFW_BIG_BUCKET(0, 1)
     GFW_BIG_BUCKET(1, 2)
@@ -153,13 +155,13 @@ static void batch_row_launch(BatchTables<T> &bt, int apply_only, hipStream_t st)
 {
     batch_big_launch<T>(bt, 0, apply_only, st);
     if (!bt.rows[0].empty())
-        k_row_batch<T, uint8_t, 4><<<bt.rows[0].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 4, st>>>(
+        k_row_batch<T, uint8_t, 4><<<bt.rows[0].size(), kRowBlock, row_lds_per_class<T>() * 4, st>>>(
             bt.d_views, bt.d_rows[0], apply_only);
     if (!bt.rows[1].empty())
-        k_row_batch<T, uint8_t, 8><<<bt.rows[1].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 8, st>>>(
+        k_row_batch<T, uint8_t, 8><<<bt.rows[1].size(), kRowBlock, row_lds_per_class<T>() * 8, st>>>(
             bt.d_views, bt.d_rows[1], apply_only);
     if (!bt.rows[2].empty())
-        k_row_batch<T, uint8_t, 16><<<bt.rows[2].size(), kRowBlock, 3 * sizeof(T) * kRowBlock * 16, st>>>(
+        k_row_batch<T, uint8_t, 16><<<bt.rows[2].size(), kRowBlock, row_lds_per_class<T>() * 16, st>>>(
             bt.d_views, bt.d_rows[2], apply_only);
 }
 
@@ -365,12 +367,11 @@ static gfw_status_t batch_collect(BatchTables<T> &bt, bool labels, std::vector<d
 {
     const int count = (int)bt.views.size();
     if (labels) k_labels_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_lab_out);
-    if (!bt.rows[0].empty()) k_spmm_to_q_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
-    if (!bt.rows[1].empty()) k_spmm_to_q_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
+    if (!bt.rows[0].empty()) k_energy_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
+    if (!bt.rows[1].empty()) k_energy_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
     if (!bt.rows[2].empty())
-        k_spmm_to_q_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
-    batch_big_launch<T>(bt, 1, 1, st);
-    k_energy_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all);
+        k_energy_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
+    batch_big_launch<T>(bt, 2, 0, st);
     gfw_status_t s;
     if ((s = bt.dE.reserve(count)) != GFW_OK || (s = bt.dctl_out.reserve(count)) != GFW_OK) return s;
     bt.d_E = bt.dE.p;
@@ -453,7 +454,7 @@ static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter, bool w
         graph += 4 * nnz + 4 * (nnz / 64 + tiles) + 8 * (tiles + 1);
     }
     const size_t nb_parts = K > 16 ? std::max(nb, (size_t)cdiv(p->n, kBigRowsPerBlock)) : nb;
-    const size_t solve = 3 * v * n * K + (K > 16 ? 4 * n + 2 * nnz : 2 * n) + n / 2 + 16 +
+    const size_t solve = (2 * v + 8) * n * K + (K > 16 ? 4 * n + 2 * nnz : 2 * n) + n / 2 + 16 +
                          8 * ((size_t)(kRowParts + 4) * nb_parts + std::max(tiles, nb) +
                               kRowParts * std::max(tiles, K > 16 ? nb : (size_t)0) + 64) +
                          sizeof(Ctl) +

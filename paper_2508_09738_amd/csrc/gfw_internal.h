@@ -30,6 +30,11 @@ inline int grid_for(int64_t work, int threads, int cap = 65535)
 
 inline size_t dsize(gfw_dtype_t d) { return d == GFW_F32 ? 4 : 8; }
 
+// Dynamic LDS of the row kernel per class of its bucket: a 256-row tile of U and Q in the
+// graph's dtype and of P in FP64.
+template <typename T>
+constexpr size_t row_lds_per_class() { return (size_t)kRowBlock * (2 * sizeof(T) + sizeof(double)); }
+
 #define GFW_HIP_TRY(expr)                                                                   \
     do {                                                                                    \
         hipError_t e_ = (expr);                                                             \
@@ -42,7 +47,8 @@ inline size_t dsize(gfw_dtype_t d) { return d == GFW_F32 ? 4 : 8; }
 
 // Per-solve device workspace, owned by a graph (one solve at a time per graph).
 struct Workspace {
-    void *U = nullptr, *P = nullptr, *Q = nullptr; // n x K of the graph dtype
+    void *U = nullptr, *Q = nullptr; // n x K of the graph dtype
+    double *P = nullptr;             // n x K, L_s U carried in FP64
     uint8_t *s0 = nullptr, *s1 = nullptr;          // vertex indices (ping-pong)
     uint8_t *s4 = nullptr;                         // the current vertices packed two per byte (K <= 16)
     uint16_t *nv = nullptr;                        // per CSR entry, the vertex of its column (K > 16)
@@ -168,7 +174,7 @@ GraphView<T> make_view(const gfw_graph_s *g)
     v.a = (const T *)g->vals;
     v.lab = g->lab;
     v.U = (T *)w.U;
-    v.P = (T *)w.P;
+    v.P = w.P;
     v.Q = (T *)w.Q;
     v.s0 = w.s0;
     v.s1 = w.s1;

@@ -3,13 +3,17 @@
 // One GFW iteration k (Alg. 3 of the paper) is split into three launches:
 //   row    : apply the pending update of iteration k-1
 //              U_k = (1-a) U_{k-1} + a S_{k-1},  P_k = (1-a) P_{k-1} + a Q_{k-1}
-//            (P = L_s U is carried by linearity instead of recomputed), then form the
+//            (P = L_s U is carried by linearity instead of recomputed, in FP64 whatever
+//            the graph's dtype: P is a small difference of O(1) terms, and rounding it to
+//            FP32 at every update lets it drift away from L_s U over a few hundred
+//            iterations until a step size changes), then form the
 //            gradient G = P + (1/eps)(1 - 2U) - D_w (Uhat - U) (eq. gradgl_vv2g), the
 //            GLMO vertex s_i (Section 4) and the per-row terms of g_k, E(U_k) and the
 //            curvature; block partials in FP64.
 //   label  : Q_k = L_s S_k, a sparse product with a one-hot right operand, i.e. a
 //            per-row histogram of neighbour labels s_j weighted by the scaled edge
-//            values; plus the per-row term (L_s S_k)_{i,s_i} of <S_k, L_s S_k>.
+//            values, summed in FP64 and stored once in the graph's dtype; plus the
+//            per-row term (L_s S_k)_{i,s_i} of <S_k, L_s S_k>.
 //   finish : one workgroup reduces all partials in a fixed order, forms g_k, E(U_k),
 //            q_k = <D, Hess E D> and the step size (Armijo in closed form, since E is
 //            quadratic: E(U) - E(U + aD) = a g - a^2 q / 2), the stop decision, and
@@ -271,7 +275,8 @@ struct GraphView {
     const int32_t *rp, *ci;
     const T *a;
     const int32_t *lab;
-    T *U, *P, *Q;
+    T *U, *Q;
+    double *P;        // L_s U carried by linearity, FP64 for both dtypes
     uint8_t *s0, *s1;
     uint8_t *s4;      // vertices of the current iteration, two per byte (written for the sorted pass)
     uint16_t *nv;     // per CSR entry, the last evaluated vertex of its column (large-K kernels)
@@ -297,7 +302,7 @@ struct TileRef {
 // A block owns tile `tile` (kRowBlock consecutive rows).  Their U, P and Q rows form
 // contiguous runs of rows*K elements, moved between HBM and LDS with coalesced accesses;
 // each thread then works on one row out of LDS.  Partials are stored transposed:
-// row_part[j * nb_row + tile].  Dynamic LDS: 3 * kRowBlock * K * sizeof(T).
+// row_part[j * nb_row + tile].  Dynamic LDS: kRowBlock * K * (2 sizeof(T) + 8).
 template <typename T, typename ST, int KB>
 __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile, const int apply_only)
 {
@@ -305,7 +310,7 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
     const int32_t K = gv.K;
     const int32_t *__restrict__ lab = gv.lab;
     T *__restrict__ U = gv.U;
-    T *__restrict__ P = gv.P;
+    double *__restrict__ P = gv.P;
     const T *__restrict__ Q = gv.Q;
     ST *__restrict__ s0 = gv.s0;
     ST *__restrict__ s1 = gv.s1;
@@ -321,41 +326,47 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
     const double alpha = ctl->alpha;
     const SolveParams sp = ctl->sp;
     extern __shared__ unsigned char lds_raw[];
-    T *lu = reinterpret_cast<T *>(lds_raw);
-    T *lp = lu + kRowBlock * K;
-    T *lq = lp + kRowBlock * K;
+    double *lp = reinterpret_cast<double *>(lds_raw);
+    T *lu = reinterpret_cast<T *>(lp + kRowBlock * K);
+    T *lq = lu + kRowBlock * K;
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)tile * kRowBlock;
     const int rows = (int)min((int64_t)kRowBlock, n - r0);
     const int cnt = rows * K;
     const int64_t base = r0 * K;
-    // The block's run of rows*K elements starts on a 16-byte boundary (256*K*sizeof(T) is a
-    // multiple of 16); full blocks move it with 16-byte vectors, the ragged last block with
+    // The block's runs of rows*K elements start on 16-byte boundaries (256*K*sizeof(T) is a
+    // multiple of 16); full blocks move them with 16-byte vectors, the ragged last block with
     // scalars.  All loads are issued before the LDS stores.
-    constexpr int VE = 16 / sizeof(T);                  // elements per 16-byte vector
+    constexpr int VE = 16 / sizeof(T);                  // elements of U or Q per 16-byte vector
     constexpr int VPT = (KB * kRowBlock / VE + kRowBlock - 1) / kRowBlock; // vectors per thread
+    constexpr int VPTP = (KB * kRowBlock / 2 + kRowBlock - 1) / kRowBlock;  // the same for P (FP64)
     const bool full = rows == kRowBlock;
     if (full) {
-        const int nvec = cnt / VE;
+        const int nvec = cnt / VE, nvecp = cnt / 2;
         const v4u *gu = reinterpret_cast<const v4u *>(U + base);
         const v4u *gp = reinterpret_cast<const v4u *>(P + base);
         const v4u *gq = reinterpret_cast<const v4u *>(Q + base);
-        v4u vu[VPT], vp[VPT], vq[VPT];
+        v4u vu[VPT], vp[VPTP], vq[VPT];
 #pragma unroll
         for (int m = 0; m < VPT; ++m) {
             const int v = min(tid + m * kRowBlock, nvec - 1);
             vu[m] = __builtin_nontemporal_load(gu + v);
-            vp[m] = __builtin_nontemporal_load(gp + v);
             vq[m] = __builtin_nontemporal_load(gq + v); // Q is only used when an update is pending (every iteration but the first)
         }
+#pragma unroll
+        for (int m = 0; m < VPTP; ++m) vp[m] = __builtin_nontemporal_load(gp + min(tid + m * kRowBlock, nvecp - 1));
 #pragma unroll
         for (int m = 0; m < VPT; ++m) {
             const int v = tid + m * kRowBlock;
             if (v < nvec) {
                 reinterpret_cast<v4u *>(lu)[v] = vu[m];
-                reinterpret_cast<v4u *>(lp)[v] = vp[m];
                 reinterpret_cast<v4u *>(lq)[v] = vq[m];
             }
+        }
+#pragma unroll
+        for (int m = 0; m < VPTP; ++m) {
+            const int v = tid + m * kRowBlock;
+            if (v < nvecp) reinterpret_cast<v4u *>(lp)[v] = vp[m];
         }
     } else {
         for (int q = tid; q < cnt; q += kRowBlock) {
@@ -373,12 +384,12 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
     if (tid < rows) {
         const int64_t i = r0 + tid;
         T *ur = lu + tid * K;
-        T *pr = lp + tid * K;
+        double *pr = lp + tid * K;
         double u[KB], p[KB];
 #pragma unroll
         for (int c = 0; c < KB; ++c) {
             u[c] = c < K ? (double)ur[c] : 0.0;
-            p[c] = c < K ? (double)pr[c] : 0.0;
+            p[c] = c < K ? pr[c] : 0.0;
         }
         bool binary = true;
 #pragma unroll
@@ -391,8 +402,8 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
 #pragma unroll
             for (int c = 0; c < KB; ++c) {
                 if (c < K) {
-                    p[c] = (double)(T)(om * p[c] + alpha * (double)qr[c]);
-                    pr[c] = (T)p[c];
+                    p[c] = om * p[c] + alpha * (double)qr[c];
+                    pr[c] = p[c];
                 }
             }
             // a row whose direction d_i = e_{s_i} - u_i is zero (a binary row kept by the
@@ -484,16 +495,18 @@ __device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile,
     __syncthreads();
     if (pending) {
         if (full) {
-            const int nvec = cnt / VE;
+            const int nvec = cnt / VE, nvecp = cnt / 2;
             v4u *gu = reinterpret_cast<v4u *>(U + base);
             v4u *gp = reinterpret_cast<v4u *>(P + base);
 #pragma unroll
             for (int m = 0; m < VPT; ++m) {
                 const int v = tid + m * kRowBlock;
-                if (v < nvec) {
-                    __builtin_nontemporal_store(reinterpret_cast<const v4u *>(lu)[v], gu + v);
-                    __builtin_nontemporal_store(reinterpret_cast<const v4u *>(lp)[v], gp + v);
-                }
+                if (v < nvec) __builtin_nontemporal_store(reinterpret_cast<const v4u *>(lu)[v], gu + v);
+            }
+#pragma unroll
+            for (int m = 0; m < VPTP; ++m) {
+                const int v = tid + m * kRowBlock;
+                if (v < nvecp) __builtin_nontemporal_store(reinterpret_cast<const v4u *>(lp)[v], gp + v);
             }
         } else {
             for (int q = tid; q < cnt; q += kRowBlock) {
@@ -543,9 +556,9 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
     const int64_t i = r0 + tid;
     const int32_t b = has_row ? rp[i] : 0, e = has_row ? rp[i + 1] : 0;
     const int32_t t_begin = rp[r0], t_end = rp[r0 + rows];
-    T acc[KB];
+    double acc[KB];
 #pragma unroll
-    for (int c = 0; c < KB; ++c) acc[c] = (T)0;
+    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
     constexpr int PER = LT / kRowBlock;
     for (int32_t t0 = t_begin; t0 < t_end; t0 += LT) {
         const int cnt = (int)min((int32_t)LT, t_end - t0);
@@ -578,22 +591,22 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
             int32_t p = pb;
             for (; p + 4 <= pe; p += 4) {
                 int32_t sj[4];
-                T v[4];
+                double v[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     sj[u] = (int32_t)ls[p + u - t0];
-                    v[u] = lv[p + u - t0];
+                    v[u] = (double)lv[p + u - t0];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? v[u] : (T)0;
+                    for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? v[u] : 0.0;
             }
             for (; p < pe; ++p) {
                 const int32_t sj = (int32_t)ls[p - t0];
-                const T v = lv[p - t0];
+                const double v = (double)lv[p - t0];
 #pragma unroll
-                for (int c = 0; c < KB; ++c) acc[c] += (c == sj) ? v : (T)0;
+                for (int c = 0; c < KB; ++c) acc[c] += (c == sj) ? v : 0.0;
             }
         }
     }
@@ -603,7 +616,7 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
 #pragma unroll
         for (int c = 0; c < KB; ++c) {
             if (c < K) {
-                const T v = acc[c] + ((diag_one && c == si) ? (T)1 : (T)0);
+                const T v = (T)(acc[c] + ((diag_one && c == si) ? 1.0 : 0.0));
                 lq[tid * K + c] = v;
                 if (c == si) own = (double)v;
             }
@@ -714,9 +727,9 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
     double own = 0.0;
     for (int r = tid; r < rows; r += kSortedThreads) {
         const int rb = rp[r0 + r] - e0, re = rp[r0 + r + 1] - e0;
-        T acc[KB];
+        double acc[KB];
 #pragma unroll
-        for (int c = 0; c < KB; ++c) acc[c] = (T)0;
+        for (int c = 0; c < KB; ++c) acc[c] = 0.0;
         // the row's values in batches of 8, then 4, then singly: each batch's loads are in
         // flight together (a row has about 24 entries on the large SBM: three batches)
         int p = rb;
@@ -731,7 +744,7 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
 #pragma unroll
             for (int u = 0; u < 8; ++u)
 #pragma unroll
-                for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? v[u] : (T)0;
+                for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? (double)v[u] : 0.0;
         }
         for (; p + 4 <= re; p += 4) {
             T v[4];
@@ -744,20 +757,20 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? v[u] : (T)0;
+                for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? (double)v[u] : 0.0;
         }
         for (; p < re; ++p) {
-            const T v = a[e0 + p];
+            const double v = (double)a[e0 + p];
             const int32_t sj = (int32_t)llab[p];
 #pragma unroll
-            for (int c = 0; c < KB; ++c) acc[c] += (c == sj) ? v : (T)0;
+            for (int c = 0; c < KB; ++c) acc[c] += (c == sj) ? v : 0.0;
         }
         const int32_t si = (int32_t)s[r0 + r];
         T *__restrict__ qr = Q + (int64_t)(r0 + r) * K;
 #pragma unroll
         for (int c = 0; c < KB; ++c) {
             if (c < K) {
-                const T v = acc[c] + ((diag_one && c == si) ? (T)1 : (T)0);
+                const T v = (T)(acc[c] + ((diag_one && c == si) ? 1.0 : 0.0));
                 qr[c] = v;
                 if (c == si) own += (double)v;
             }
@@ -919,17 +932,21 @@ __device__ __forceinline__ void init_body(const GraphView<T> &gv, const T *__res
     }
 }
 
-// P = c U + A U (A the stored CSR values, c = 1 for L_s, 0 for a user operator) for the
-// rows of tile `tile`: the tile's column indices and values are staged through LDS with
-// coalesced loads, and each thread sums its row in CSR order in FP64, gathering the K-wide
-// rows u_j.  The result depends on nothing but the row, so it is the same in every launch
-// shape.  K <= KB.
+// Row i of L U for the rows of tile `tile` (one row per thread, acc in FP64).  L is I + A
+// (kind W: A the stored scaled values, the identity implicit) or A itself (kind L).  The
+// tile's column indices and values are staged through LDS with coalesced loads; each
+// thread then sums its row in CSR order, with the identity's term u_i taken at the
+// diagonal's place in that order (where a self-loop's entry a_ii stands, as (1 + a_ii) u_i;
+// else before the first larger column), the order of a CSR loop over the explicit operator.
+// UN neighbour rows are loaded before they are summed, so that UN gathers are in flight per
+// thread.  The result depends on nothing but the row.  K <= KB.
 template <typename T, int KB>
-__device__ __forceinline__ void spmm_body(const GraphView<T> &gv, const T *__restrict__ Uin, T *__restrict__ Pout,
-                                          const int tile)
+__device__ __forceinline__ void spmm_rows(const GraphView<T> &gv, const T *__restrict__ Uin, const int tile,
+                                          double (&acc)[KB])
 {
     __shared__ int32_t lc[kLabelTile];
     __shared__ T lv[kLabelTile];
+    constexpr int UN = KB <= 8 ? 4 : 2;
     const int32_t K = gv.K;
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)tile * kRowBlock;
@@ -938,9 +955,29 @@ __device__ __forceinline__ void spmm_body(const GraphView<T> &gv, const T *__res
     const int64_t i = r0 + tid;
     const int32_t b = has_row ? gv.rp[i] : 0, e = has_row ? gv.rp[i + 1] : 0;
     const int32_t t_begin = gv.rp[r0], t_end = gv.rp[r0 + rows];
-    double acc[KB];
+    const T *__restrict__ ui = Uin + (has_row ? i : 0) * K;
+    bool diag_due = gv.diag_one != 0; // the identity's term is still to be added
 #pragma unroll
     for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    // one entry (column j, value v, gathered row uj) of the row, in order
+    auto take = [&](const int32_t j, const double v, const T *uj) {
+        if (diag_due && j >= (int32_t)i) {
+            diag_due = false;
+            if (j == (int32_t)i) { // a self-loop: (1 + a_ii) u_i
+                const double w = 1.0 + v;
+#pragma unroll
+                for (int c = 0; c < KB; ++c)
+                    if (c < K) acc[c] += w * (double)uj[c];
+                return;
+            }
+#pragma unroll
+            for (int c = 0; c < KB; ++c)
+                if (c < K) acc[c] += (double)ui[c];
+        }
+#pragma unroll
+        for (int c = 0; c < KB; ++c)
+            if (c < K) acc[c] += v * (double)uj[c];
+    };
     constexpr int PER = kLabelTile / kRowBlock;
     for (int32_t t0 = t_begin; t0 < t_end; t0 += kLabelTile) {
         const int cnt = (int)min((int32_t)kLabelTile, t_end - t0);
@@ -964,21 +1001,43 @@ __device__ __forceinline__ void spmm_body(const GraphView<T> &gv, const T *__res
         __syncthreads();
         if (has_row) {
             const int32_t pb = max(b, t0), pe = min(e, t0 + cnt);
-            for (int32_t p = pb; p < pe; ++p) {
-                const T *uj = Uin + (int64_t)lc[p - t0] * K;
-                const double v = (double)lv[p - t0];
+            int32_t p = pb;
+            for (; p + UN <= pe; p += UN) {
+                int32_t j[UN];
+                T uu[UN][KB];
 #pragma unroll
-                for (int c = 0; c < KB; ++c)
-                    if (c < K) acc[c] += v * (double)uj[c];
+                for (int u = 0; u < UN; ++u) {
+                    j[u] = lc[p + u - t0];
+#pragma unroll
+                    for (int c = 0; c < KB; ++c) uu[u][c] = c < K ? Uin[(int64_t)j[u] * K + c] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < UN; ++u) take(j[u], (double)lv[p + u - t0], uu[u]);
+            }
+            for (; p < pe; ++p) {
+                const int32_t j = lc[p - t0];
+                take(j, (double)lv[p - t0], Uin + (int64_t)j * K);
             }
         }
     }
-    if (has_row) {
-        const T *ui = Uin + i * K;
+    if (has_row && diag_due) // every column of the row precedes i
 #pragma unroll
         for (int c = 0; c < KB; ++c)
-            if (c < K) Pout[i * K + c] = (T)(gv.diag_one ? (double)ui[c] + acc[c] : acc[c]);
-    }
+            if (c < K) acc[c] += (double)ui[c];
+}
+
+// P = L U for the rows of tile `tile`, stored as PT.
+template <typename T, int KB, typename PT>
+__device__ __forceinline__ void spmm_body(const GraphView<T> &gv, const T *__restrict__ Uin, PT *__restrict__ Pout,
+                                          const int tile)
+{
+    double acc[KB];
+    spmm_rows<T, KB>(gv, Uin, tile, acc);
+    const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x;
+    if (i < gv.n)
+#pragma unroll
+        for (int c = 0; c < KB; ++c)
+            if (c < gv.K) Pout[i * gv.K + c] = (PT)acc[c];
 }
 
 template <typename T>
@@ -996,10 +1055,10 @@ static __global__ void __launch_bounds__(kRowBlock) k_init_u_batch(const GraphVi
     init_body<T>(views[r.graph], U0s ? U0s[r.graph] : nullptr, r.tile);
 }
 
-template <typename T, int KB>
-static __global__ void __launch_bounds__(kRowBlock) k_spmm(GraphView<T> gv, const T *__restrict__ Uin, T *__restrict__ Pout)
+template <typename T, int KB, typename PT>
+static __global__ void __launch_bounds__(kRowBlock) k_spmm(GraphView<T> gv, const T *__restrict__ Uin, PT *__restrict__ Pout)
 {
-    spmm_body<T, KB>(gv, Uin, Pout, blockIdx.x);
+    spmm_body<T, KB, PT>(gv, Uin, Pout, blockIdx.x);
 }
 
 // batched L_s U_0 -> P at the start of a batched solve
@@ -1009,7 +1068,7 @@ static __global__ void __launch_bounds__(kRowBlock) k_spmm_batch(const GraphView
 {
     const TileRef r = refs[blockIdx.x];
     const GraphView<T> &gv = views[r.graph];
-    spmm_body<T, KB>(gv, gv.U, gv.P, r.tile);
+    spmm_body<T, KB, double>(gv, gv.U, gv.P, r.tile);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1064,27 +1123,33 @@ static __global__ void __launch_bounds__(kFinishThreads) k_finish(const double *
     finish_body(row_part, nb_row, lab_part, nb_lab, ctl);
 }
 
-// Terms of E(U) (eq. gl_vv2) from their definitions given P = L U, for the rows of tile
-// `tile`: <u,P>, sum u(1-u), sum omega_i ||uhat_i - u_i||^2; stored at part[j * nb_row + tile].
-template <typename T>
-__device__ __forceinline__ void energy_body(const GraphView<T> &gv, const T *__restrict__ U, const T *__restrict__ P,
-                                            double omega0, double *__restrict__ part, const int tile)
+// Terms of E(U) (eq. gl_vv2) from their definitions for the rows of tile `tile`: row i of
+// P = L U is formed in FP64 (spmm_rows) and used at once, never stored; then <u_i, P_i>,
+// sum u(1-u) and omega_i ||uhat_i - u_i||^2; block sums stored at part[j * stride + tile].
+template <typename T, int KB>
+__device__ __forceinline__ void energy_body(const GraphView<T> &gv, const T *__restrict__ U, double omega0,
+                                            double *__restrict__ part, int64_t stride, const int tile)
 {
+    double p[KB];
+    spmm_rows<T, KB>(gv, U, tile, p);
     double acc[3] = {0.0, 0.0, 0.0};
     const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x;
     if (i < gv.n) {
         const int32_t y = gv.lab[i];
-        for (int32_t c = 0; c < gv.K; ++c) {
-            const double u = (double)U[i * gv.K + c];
-            acc[0] += u * (double)P[i * gv.K + c];
-            acc[1] += u * (1.0 - u);
-            if (y >= 0) {
-                const double e = (c == y ? 1.0 : 0.0) - u;
-                acc[2] += omega0 * e * e;
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+            if (c < gv.K) {
+                const double u = (double)U[i * gv.K + c];
+                acc[0] += u * p[c];
+                acc[1] += u * (1.0 - u);
+                if (y >= 0) {
+                    const double e = (c == y ? 1.0 : 0.0) - u;
+                    acc[2] += omega0 * e * e;
+                }
             }
         }
     }
-    block_sum_store_strided<3>(acc, part + tile, gv.nb_row);
+    block_sum_store_strided<3>(acc, part + tile, stride);
 }
 
 // E = 1/2 <U, L U> + (1/eps) sum u(1-u) + 1/2 sum omega ||uhat - u||^2 from the tile partials.
@@ -1111,11 +1176,11 @@ __device__ __forceinline__ void energy_sum_body(const double *__restrict__ part,
     }
 }
 
-template <typename T>
-static __global__ void __launch_bounds__(kRowBlock) k_energy(GraphView<T> gv, const T *__restrict__ U, const T *__restrict__ P,
-                                                       double omega0, double *__restrict__ part)
+template <typename T, int KB>
+static __global__ void __launch_bounds__(kRowBlock) k_energy(GraphView<T> gv, const T *__restrict__ U, double omega0,
+                                                       double *__restrict__ part)
 {
-    energy_body<T>(gv, U, P, omega0, part, blockIdx.x);
+    energy_body<T, KB>(gv, U, omega0, part, gv.nb_row, blockIdx.x);
 }
 
 static __global__ void __launch_bounds__(kFinishThreads) k_energy_sum(const double *__restrict__ part, int nb,
@@ -1124,24 +1189,14 @@ static __global__ void __launch_bounds__(kFinishThreads) k_energy_sum(const doub
     energy_sum_body(part, nb, inv_eps, out);
 }
 
-// batched objective of the final iterates: P = L U goes to Q (free after the solve), the
-// tile partials to row_part
+// batched objective of the final iterates: tile partials of E to row_part
 template <typename T, int KB>
-static __global__ void __launch_bounds__(kRowBlock) k_spmm_to_q_batch(const GraphView<T> *__restrict__ views,
-                                                                const TileRef *__restrict__ refs)
-{
-    const TileRef r = refs[blockIdx.x];
-    const GraphView<T> &gv = views[r.graph];
-    spmm_body<T, KB>(gv, gv.U, gv.Q, r.tile);
-}
-
-template <typename T>
 static __global__ void __launch_bounds__(kRowBlock) k_energy_batch(const GraphView<T> *__restrict__ views,
                                                              const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
     const GraphView<T> &gv = views[r.graph];
-    energy_body<T>(gv, gv.U, gv.Q, gv.ctl->sp.omega0, gv.row_part, r.tile);
+    energy_body<T, KB>(gv, gv.U, gv.ctl->sp.omega0, gv.row_part, gv.nb_row, r.tile);
 }
 
 // one workgroup per graph: objective and a copy of the control block
@@ -1150,7 +1205,7 @@ static __global__ void __launch_bounds__(kFinishThreads) k_collect_batch(const G
                                                                   double *__restrict__ E, Ctl *__restrict__ ctls)
 {
     const GraphView<T> &gv = views[blockIdx.x];
-    energy_sum_body(gv.row_part, gv.nb_row, gv.ctl->sp.inv_eps, E + blockIdx.x);
+    energy_sum_body(gv.row_part, gv.nb_big > 0 ? gv.nb_big : gv.nb_row, gv.ctl->sp.inv_eps, E + blockIdx.x);
     if (threadIdx.x == 0) ctls[blockIdx.x] = *gv.ctl;
 }
 

@@ -9,9 +9,10 @@
 //    so every row of U and P is read and written with coalesced accesses, and the
 //    GLMO's lowest-index argmin and the per-row sums are wavefront reductions;
 //  * Q = L_s S is never stored: S is one-hot, so the row (L_s S_{k-1})_i has at most
-//    deg_i + 1 non-zeros, and the row kernel of iteration k rebuilds it from the row's
-//    values and its neighbours' vertices s_{k-1} just before the update
-//    P_k = (1 - a) P_{k-1} + a Q_{k-1}.  That saves writing and reading an n x K array;
+//    deg_i + 1 non-zeros, and the row kernel of iteration k rebuilds it (FP64 sums, rounded
+//    to the graph's dtype as the small-K label pass stores Q) from the row's values and its
+//    neighbours' vertices s_{k-1} just before the update P_k = (1 - a) P_{k-1} + a Q_{k-1}
+//    (P in FP64).  That saves writing and reading an n x K array;
 //  * the label pass forms the per-row term Q_{i,s_i} of <S, L_s S> (the sum of the row's
 //    values over neighbours that share its vertex, plus the diagonal), which does not
 //    depend on K, and stores each entry's neighbour vertex (nv, 2 bytes per entry), so
@@ -106,15 +107,16 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
         const int64_t i = rbase + t;
         if (i >= n) break; // uniform across the wavefront
         T *__restrict__ Ui = gv.U + i * K;
-        T *__restrict__ Pi = gv.P + i * K;
-        // u and p are held at storage precision (every value is rounded to T anyway) and
-        // widened to FP64 where they are used
-        T u[MC], p[MC];
+        double *__restrict__ Pi = gv.P + i * K;
+        // u is held at storage precision (every value is rounded to T anyway) and widened to
+        // FP64 where it is used; p is FP64 (the carried L_s U)
+        T u[MC];
+        double p[MC];
 #pragma unroll
         for (int m = 0; m < MC; ++m) {
             const int c = lane + 64 * m;
             u[m] = c < K ? Ui[c] : (T)0;
-            p[m] = c < K ? Pi[c] : (T)0;
+            p[m] = c < K ? Pi[c] : 0.0;
         }
         bool bl = true;
 #pragma unroll
@@ -126,9 +128,9 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
             // Q_{k-1} row i: values of the row summed per neighbour vertex, in CSR order.  The
             // row's entries are loaded one per lane (64 at a time) with their vertices, then
             // taken in order from the lanes that hold them.
-            T q[MC];
+            double q[MC];
 #pragma unroll
-            for (int m = 0; m < MC; ++m) q[m] = (T)0;
+            for (int m = 0; m < MC; ++m) q[m] = 0.0;
             const int32_t e0 = __shfl(md_b, t, 64), e1 = __shfl(md_e, t, 64);
             for (int32_t c0 = e0; c0 < e1; c0 += 64) {
                 const int cnt = min(64, e1 - c0);
@@ -140,7 +142,7 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
                 }
                 for (int x = 0; x < cnt; ++x) {
                     const int32_t sj = __shfl(sj_l, x, 64);
-                    const T v = __shfl(v_l, x, 64);
+                    const double v = (double)__shfl(v_l, x, 64);
                     if ((sj & 63) == lane) {
 #pragma unroll
                         for (int m = 0; m < MC; ++m)
@@ -151,14 +153,15 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
             if (gv.diag_one && (spi & 63) == lane) {
 #pragma unroll
                 for (int m = 0; m < MC; ++m)
-                    if (m == (spi >> 6)) q[m] += (T)1;
+                    if (m == (spi >> 6)) q[m] += 1.0;
             }
             const double om = 1.0 - alpha;
 #pragma unroll
             for (int m = 0; m < MC; ++m) {
                 const int c = lane + 64 * m;
                 if (c < K) {
-                    p[m] = (T)(om * (double)p[m] + alpha * (double)q[m]);
+                    // Q_{k-1} rounded to the graph's dtype, as the small-K label pass stores it
+                    p[m] = om * p[m] + alpha * (double)(T)q[m];
                     Pi[c] = p[m];
                 }
             }
@@ -189,7 +192,7 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
             auto grad = [&](const int m, const int c) -> double {
                 const double uc = (double)u[m];
                 const double fid = om_i != 0.0 ? om_i * (((c == y) ? 1.0 : 0.0) - uc) : 0.0;
-                return (double)p[m] + sp.inv_eps * (1.0 - 2.0 * uc) - fid;
+                return p[m] + sp.inv_eps * (1.0 - 2.0 * uc) - fid;
             };
             int32_t s;
             if (binary && sp.lmo == 0) {
@@ -225,7 +228,7 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
             for (int m = 0; m < MC; ++m) {
                 const int c = lane + 64 * m;
                 if (c < K) {
-                    const double uc = (double)u[m], pc = (double)p[m];
+                    const double uc = (double)u[m], pc = p[m];
                     const double d = (c == s ? 1.0 : 0.0) - uc;
                     gap -= grad(m, c) * d;
                     up += uc * pc;
@@ -291,14 +294,14 @@ __device__ __forceinline__ void label_big_body(const GraphView<T> &gv, const int
     double own = 0.0;
     if (i < gv.n) {
         const int32_t si = (int32_t)s[i];
-        T acc = (T)0;
+        double acc = 0.0;
         const int32_t e0 = gv.rp[i], e1 = gv.rp[i + 1];
         for (int32_t e = e0; e < e1; ++e) {
             const uint16_t sj = s[gv.ci[e]];
             gv.nv[e] = sj;
-            if ((int32_t)sj == si) acc += gv.a[e];
+            if ((int32_t)sj == si) acc += (double)gv.a[e];
         }
-        own = (double)(acc + (gv.diag_one ? (T)1 : (T)0));
+        own = (double)(T)(acc + (gv.diag_one ? 1.0 : 0.0));
     }
     if (threadIdx.x < 64) { // the whole first wavefront
 #pragma unroll
@@ -311,38 +314,150 @@ __device__ __forceinline__ void label_big_body(const GraphView<T> &gv, const int
     block_sum_store_strided<1>(v, gv.lab_part + tile, gv.nb_row);
 }
 
-// P = L_s U for large K: a wavefront per row, each lane accumulates its classes over the
-// row's entries in CSR order in FP64 (the same arithmetic as spmm_body).
-template <typename T, int MC>
-__device__ __forceinline__ void spmm_big_body(const GraphView<T> &gv, const T *__restrict__ Uin, T *__restrict__ Pout,
-                                              const int tile)
+// Row i of L U for large K, one wavefront per row, each lane accumulating its classes over
+// the row's entries in CSR order in FP64, with the identity's term at the diagonal's place
+// (the order and arithmetic of spmm_rows).  Four neighbour rows are loaded before they are
+// summed.  `fn(i, acc)` receives each finished row (acc[m] is class lane + 64 m).
+template <typename T, int MC, typename Fn>
+__device__ __forceinline__ void spmm_big_rows(const GraphView<T> &gv, const T *__restrict__ Uin, const int tile,
+                                              Fn &&fn)
 {
     const int32_t K = gv.K;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t rbase = (int64_t)tile * kBigRowsPerBlock + (int64_t)wid * kBigRowsPerWave;
     for (int t = 0; t < kBigRowsPerWave; ++t) {
         const int64_t i = rbase + t;
-        if (i >= gv.n) break;
+        if (i >= gv.n) break; // uniform across the wavefront
         double acc[MC];
 #pragma unroll
         for (int m = 0; m < MC; ++m) acc[m] = 0.0;
+        const T *__restrict__ ui = Uin + i * K;
+        bool diag_due = gv.diag_one != 0;
+        auto take = [&](const int32_t j, const double v, const T (&uj)[MC]) {
+            if (diag_due && j >= (int32_t)i) {
+                diag_due = false;
+                if (j == (int32_t)i) {
+                    const double w = 1.0 + v;
+#pragma unroll
+                    for (int m = 0; m < MC; ++m) acc[m] += w * (double)uj[m];
+                    return;
+                }
+#pragma unroll
+                for (int m = 0; m < MC; ++m) {
+                    const int c = lane + 64 * m;
+                    acc[m] += c < K ? (double)ui[c] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < MC; ++m) acc[m] += v * (double)uj[m];
+        };
         const int32_t e0 = gv.rp[i], e1 = gv.rp[i + 1];
-        for (int32_t e = e0; e < e1; ++e) {
-            const T *__restrict__ uj = Uin + (int64_t)gv.ci[e] * K;
-            const double v = (double)gv.a[e];
+        int32_t e = e0;
+        constexpr int UN = 4;
+        for (; e + UN <= e1; e += UN) {
+            int32_t j[UN];
+            T uu[UN][MC];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                j[u] = gv.ci[e + u];
+#pragma unroll
+                for (int m = 0; m < MC; ++m) {
+                    const int c = lane + 64 * m;
+                    uu[u][m] = c < K ? Uin[(int64_t)j[u] * K + c] : (T)0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UN; ++u) take(j[u], (double)gv.a[e + u], uu[u]);
+        }
+        for (; e < e1; ++e) {
+            const int32_t j = gv.ci[e];
+            T uj[MC];
 #pragma unroll
             for (int m = 0; m < MC; ++m) {
                 const int c = lane + 64 * m;
-                if (c < K) acc[m] += v * (double)uj[c];
+                uj[m] = c < K ? Uin[(int64_t)j * K + c] : (T)0;
             }
+            take(j, (double)gv.a[e], uj);
         }
-        const T *__restrict__ ui = Uin + i * K;
+        if (diag_due)
+#pragma unroll
+            for (int m = 0; m < MC; ++m) {
+                const int c = lane + 64 * m;
+                acc[m] += c < K ? (double)ui[c] : 0.0;
+            }
+        fn(i, acc);
+    }
+}
+
+// P = L U for large K, stored as PT.
+template <typename T, int MC, typename PT>
+__device__ __forceinline__ void spmm_big_body(const GraphView<T> &gv, const T *__restrict__ Uin, PT *__restrict__ Pout,
+                                              const int tile)
+{
+    const int lane = threadIdx.x & 63;
+    spmm_big_rows<T, MC>(gv, Uin, tile, [&](const int64_t i, const double (&acc)[MC]) {
 #pragma unroll
         for (int m = 0; m < MC; ++m) {
             const int c = lane + 64 * m;
-            if (c < K) Pout[i * K + c] = (T)(gv.diag_one ? (double)ui[c] + acc[m] : acc[m]);
+            if (c < gv.K) Pout[i * gv.K + c] = (PT)acc[m];
         }
+    });
+}
+
+// Terms of E(U) for large K (the quantities of energy_body): each wavefront forms its rows of
+// L U (spmm_big_rows) and sums the row's terms across lanes; block sums stored at
+// part[j * stride + tile], with the blocks of the large-K row kernel.
+template <typename T, int MC>
+__device__ __forceinline__ void energy_big_body(const GraphView<T> &gv, const T *__restrict__ U, double omega0,
+                                                double *__restrict__ part, int64_t stride, const int tile)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double wacc[3] = {0.0, 0.0, 0.0};
+    spmm_big_rows<T, MC>(gv, U, tile, [&](const int64_t i, const double (&p)[MC]) {
+        const int32_t y = gv.lab[i];
+        double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < MC; ++m) {
+            const int c = lane + 64 * m;
+            if (c < gv.K) {
+                const double u = (double)U[i * gv.K + c];
+                t[0] += u * p[m];
+                t[1] += u * (1.0 - u);
+                if (y >= 0) {
+                    const double e = (c == y ? 1.0 : 0.0) - u;
+                    t[2] += omega0 * e * e;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) wacc[j] += wave_sum(t[j]);
+    });
+    __shared__ double red[kBigThreads / 64][3];
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) red[wid][j] = wacc[j];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double v = 0.0;
+        for (int w = 0; w < kBigThreads / 64; ++w) v += red[w][threadIdx.x];
+        part[threadIdx.x * stride + tile] = v;
     }
+}
+
+template <typename T, int MC>
+static __global__ void __launch_bounds__(kBigThreads) k_energy_big(GraphView<T> gv, const T *__restrict__ U,
+                                                                   double omega0, double *__restrict__ part)
+{
+    energy_big_body<T, MC>(gv, U, omega0, part, gv.nb_big, blockIdx.x);
+}
+
+template <typename T, int MC>
+static __global__ void __launch_bounds__(kBigThreads) k_energy_big_batch(const GraphView<T> *__restrict__ views,
+                                                                         const TileRef *__restrict__ refs)
+{
+    const TileRef r = refs[blockIdx.x];
+    const GraphView<T> &gv = views[r.graph];
+    energy_big_body<T, MC>(gv, gv.U, gv.ctl->sp.omega0, gv.row_part, gv.nb_big, r.tile);
 }
 
 template <typename T, int MC>
@@ -357,11 +472,11 @@ static __global__ void __launch_bounds__(kRowBlock) k_label_big(GraphView<T> gv)
     label_big_body<T>(gv, blockIdx.x);
 }
 
-template <typename T, int MC>
+template <typename T, int MC, typename PT>
 static __global__ void __launch_bounds__(kBigThreads) k_spmm_big(GraphView<T> gv, const T *__restrict__ Uin,
-                                                                 T *__restrict__ Pout)
+                                                                 PT *__restrict__ Pout)
 {
-    spmm_big_body<T, MC>(gv, Uin, Pout, blockIdx.x);
+    spmm_big_body<T, MC, PT>(gv, Uin, Pout, blockIdx.x);
 }
 
 // Batched forms: workgroup -> (graph, tile) through the TileRef table, the same bodies on
@@ -384,14 +499,14 @@ static __global__ void __launch_bounds__(kRowBlock) k_label_big_batch(const Grap
     label_big_body<T>(views[r.graph], r.tile);
 }
 
-// P = L_s U (to_q = 0, start of a solve) or Q = L_s U (to_q = 1, objective of the result)
+// P = L_s U at the start of a batched solve
 template <typename T, int MC>
 static __global__ void __launch_bounds__(kBigThreads) k_spmm_big_batch(const GraphView<T> *__restrict__ views,
-                                                                       const TileRef *__restrict__ refs, int to_q)
+                                                                       const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
     const GraphView<T> &gv = views[r.graph];
-    spmm_big_body<T, MC>(gv, gv.U, to_q ? gv.Q : gv.P, r.tile);
+    spmm_big_body<T, MC, double>(gv, gv.U, gv.P, r.tile);
 }
 
 } // namespace gfw

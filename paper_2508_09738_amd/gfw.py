@@ -7,7 +7,6 @@ calls raise.
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 
 import numpy as np
@@ -373,7 +372,3 @@ def check_params(prm: Params, K: int) -> int:
 
 def last_error() -> str:
     return lib().gfw_last_error().decode()
-
-
-def inv_eps(eps: float) -> float:
-    return 0.0 if math.isinf(eps) else 1.0 / eps

@@ -111,7 +111,45 @@ def np_of(t):
     return t.detach().cpu().numpy()
 
 
-def lockstep(prob, dtype, ks, lmo=O.LMO_GREEDY, ls=O.LS_ARMIJO, u_tol=None, label="", label_path=None):
+def oracle_trajectory(prob, ks, lmo=O.LMO_GREEDY, ls=O.LS_ARMIJO, parallel=False):
+    """The oracle's iterates U_k for every k in ks (tol disabled), each run continued from the
+    previous one: the oracle's state between iterations is U alone (it forms L U afresh each
+    iteration), so chaining gives the same iterates as runs from U_0.  parallel uses the
+    OpenMP timing build, which returns the serial build's iterates bit for bit."""
+    L = O.operator_for(prob.graph)
+    Uhat, _ = O.fidelity(prob.n, prob.K, prob.labelled_idx, prob.labels, prob.omega0)
+    out, U, at = {}, Uhat.copy(), 0
+    for k in sorted(set(ks)):
+        if k > at:
+            U = O.solve(L, prob.K, prob.labelled_idx, prob.labels, eps=prob.eps, omega0=prob.omega0, max_iter=k - at,
+                        tol=-1.0, lmo_mode=lmo, ls=ls, U0=U, parallel=parallel)["U"]
+            at = k
+        out[k] = U.copy()
+    return out
+
+
+# Near-tie band of the lockstep GLMO check, relative to max_c |G_ic| of the row: rows whose
+# oracle margin (second-smallest minus smallest G over the candidates) lies inside it may
+# take another minimiser; elsewhere the vertices must be identical.  FP32 carries about 7
+# significant digits.  In FP64 the GPU forms L U with the oracle's operations in the
+# oracle's order (the same rounding, no contraction), and the gradient likewise, so its
+# vertices must equal the oracle's on every row, ties included: no band.
+NEAR_TIE_REL = {gfw.F32: 1e-5, gfw.F64: 0.0}
+
+
+# Bound on the rows per lockstep iteration whose GLMO vertex differs from the oracle's (each
+# of them a near-tie), as a fraction of the rows: FP32 near-ties within 1e-5 are common on
+# image grids, whose weights take few distinct values.
+MAX_DIFF_FRAC = {gfw.F32: 1e-2, gfw.F64: 0.0}
+MAX_DIFF_SLACK = {gfw.F32: 4, gfw.F64: 0}
+
+
+def lockstep(prob, dtype, ks, lmo=O.LMO_GREEDY, ls=O.LS_ARMIJO, u_tol=None, label="", label_path=None,
+             osfw=False, traj_parallel=False, max_diff_frac=None):
+    """One GPU iteration from each oracle iterate U_k (k in ks) against one oracle iteration
+    from the same point.  Rows where the GPU chose another GLMO vertex must be near-ties
+    (inside NEAR_TIE_REL[dtype]) with a GPU vertex that is a minimiser up to that band, and
+    their number per iteration is bounded by max_diff_frac of the rows (plus 4)."""
     L = O.operator_for(prob.graph)
     G = gpu_graph(prob.graph, prob.K, prob.labelled_idx, prob.labels, dtype)
     if label_path is not None:
@@ -121,46 +159,50 @@ def lockstep(prob, dtype, ks, lmo=O.LMO_GREEDY, ls=O.LS_ARMIJO, u_tol=None, labe
     # FP64 objectives: a sequential sum of the n*K per-entry terms (the oracle's) may be off by
     # up to (n*K) * 2^-53 relative to the exact sum, so the tolerance is at least that bound
     e_rel = 1e-6 if dtype == gfw.F32 else max(1e-12, prob.n * prob.K * 2.0 ** -53)
+    band = NEAR_TIE_REL[dtype]
+    max_diff_frac = MAX_DIFF_FRAC[dtype] if max_diff_frac is None else max_diff_frac
     excluded_rows = 0
     excluded_iters = 0
+    traj = oracle_trajectory(prob, ks, lmo=lmo, ls=ls, parallel=traj_parallel)
     for k in ks:
         say(f"[gpu] lockstep {label} dtype={dtype} k={k}")
-        if k == 0:
-            Uk = Uhat.copy()
-        else:
-            Uk = O.solve(L, prob.K, prob.labelled_idx, prob.labels, eps=prob.eps, omega0=prob.omega0, max_iter=k,
-                         tol=-1.0, lmo_mode=lmo, ls=ls)["U"]
+        Uk = traj[k]
         Ut = torch_u(Uk, dtype)
         Uk_in = np_of(Ut).astype(np.float64)  # what the GPU starts from
         ro = O.solve(L, prob.K, prob.labelled_idx, prob.labels, eps=prob.eps, omega0=prob.omega0, max_iter=1,
-                     tol=-1.0, lmo_mode=lmo, ls=ls, U0=Uk_in, record_s=True)
+                     tol=-1.0, lmo_mode=lmo, ls=ls, U0=Uk_in, record_s=True, osfw=osfw)
         rg = gfw.solve(ctx(), G, gfw.params(eps=prob.eps, omega0=prob.omega0, max_iter=1, tol=-1.0, lmo=lmo, ls=ls,
-                                            U0=Ut), want_s=True, want_history=True)
+                                            one_shot=osfw, U0=Ut), want_s=True, want_history=True)
         # objective and gap of U_k
         assert rg["E"][0] == pytest.approx(ro["E"][0], rel=e_rel)
         assert rg["g"][0] == pytest.approx(ro["g"][0], rel=1e-5 if dtype == gfw.F32 else 1e-10, abs=1e-9)
         # GLMO vertices: exact outside near-ties; inside, the GPU's choice must be near-optimal
         Gk = O.gradient(L, Uk_in, Uhat, omega, prob.eps)
         margin = glmo_margin(Uk_in, Gk, lmo)
-        scale = np.abs(Gk).max(axis=1)
-        near = margin <= 1e-5 * np.maximum(scale, 1e-300)
+        scale = np.maximum(np.abs(Gk).max(axis=1), 1e-300)
+        near = margin <= band * scale
         s_g, s_o = np_of(rg["s"]), ro["s"][0]
         assert np.all(s_g[~near] == s_o[~near]), f"GLMO mismatch outside near-ties at k={k}"
         diff = np.flatnonzero(s_g != s_o)
-        for i in diff:
-            assert Gk[i, s_g[i]] - Gk[i, s_o[i]] <= 1e-5 * max(scale[i], 1e-300)
+        if diff.size:
+            cand = (Uk_in[diff] != 0) if lmo == O.LMO_GREEDY else np.ones((diff.size, prob.K), bool)
+            assert np.all(cand[np.arange(diff.size), s_g[diff]]), "GPU vertex outside the support"
+            assert np.all(Gk[diff, s_g[diff]] - Gk[diff, s_o[diff]] <= band * scale[diff])
+        if diff.size:
+            say(f"[gpu]   k={k}: {diff.size} rows took another minimiser ({int(near.sum())} oracle near-ties)")
+        assert diff.size <= MAX_DIFF_SLACK[dtype] + max_diff_frac * prob.n, f"{diff.size} rows differ at k={k}"
         excluded_rows += int(diff.size)
         if diff.size:
             # the GPU chose other minimisers on near-tie rows: the oracle's iteration with the
             # GPU's vertices is the reference for the rest of the step
             ro = O.solve(L, prob.K, prob.labelled_idx, prob.labels, eps=prob.eps, omega0=prob.omega0, max_iter=1,
-                         tol=-1.0, lmo_mode=lmo, ls=ls, U0=Uk_in, record_s=True, s_first=s_g)
+                         tol=-1.0, lmo_mode=lmo, ls=ls, U0=Uk_in, record_s=True, s_first=s_g, osfw=osfw)
             assert rg["g"][0] == pytest.approx(ro["g"][0], rel=1e-5 if dtype == gfw.F32 else 1e-10, abs=1e-9)
         # step size (exclude Armijo bounds sitting on a power of two)
-        if not armijo_ratio_near_power(ro["g"][0], ro["q"][0]):
+        if osfw or ls != O.LS_ARMIJO or not armijo_ratio_near_power(ro["g"][0], ro["q"][0]):
             assert rg["q"][0] == pytest.approx(ro["q"][0], rel=1e-5 if dtype == gfw.F32 else 1e-9)
-            if ls == O.LS_ARMIJO:
-                assert rg["alpha"][0] == ro["alpha"][0]  # a power of delta: exact
+            if ls == O.LS_ARMIJO or osfw:
+                assert rg["alpha"][0] == ro["alpha"][0]  # a power of delta (1 for the one-shot method): exact
             else:
                 assert rg["alpha"][0] == pytest.approx(ro["alpha"][0], rel=1e-5 if dtype == gfw.F32 else 1e-9)
             Ug = np_of(rg["U"]).astype(np.float64)
@@ -169,5 +211,25 @@ def lockstep(prob, dtype, ks, lmo=O.LMO_GREEDY, ls=O.LS_ARMIJO, u_tol=None, labe
             assert Eg == pytest.approx(ro["objective"], rel=e_rel)
         else:
             excluded_iters += 1
+        if osfw:
+            assert rg["iters"] == ro["iters"] == 1
     say(f"[gpu] lockstep {label}: near-tie rows differing {excluded_rows}, iterations excluded {excluded_iters}")
     assert excluded_iters <= len(ks) // 2
+    return excluded_rows
+
+
+def oracle_sensitivity(prob, seeds=(0, 1), parallel=True):
+    """How far the oracle's own free-running objective moves under perturbations of rounding
+    alone: the same problem with its nodes renumbered (a different FP64 evaluation order) and
+    the same problem with U stored in FP32 after every update.  Returns (oracle result,
+    largest relative |E - E'| / |E|).  Oracle only: no GPU result enters it."""
+    r0 = O.solve_problem(prob, parallel=parallel)
+    ren = 0.0
+    for s in seeds:
+        p2, _ = relabelled(prob, s)
+        r = O.solve_problem(p2, parallel=parallel)
+        ren = max(ren, abs(r["objective"] - r0["objective"]) / abs(r0["objective"]))
+    r = O.solve_problem(prob, parallel=parallel, store_f32=True)
+    f32 = abs(r["objective"] - r0["objective"]) / abs(r0["objective"])
+    say(f"[oracle] sensitivity of the objective: renumbered nodes {ren:.3e}, U stored in FP32 {f32:.3e}")
+    return r0, max(ren, f32)

@@ -84,3 +84,84 @@ def test_batch_with_many_classes_equals_alone_bitwise():
         np.testing.assert_array_equal(_np(a["U"]), _np(b["U"]))
         np.testing.assert_array_equal(_np(a["labels"]), _np(b["labels"]))
         assert a["iters"] == b["iters"] and a["objective"] == b["objective"] and a["gap"] == b["gap"]
+
+
+def _inferred_vertices(U_prev, U_next):
+    """The GLMO vertex of every row from one update U_next = (1 - a) U_prev + a e_s: the one
+    column that grows (a binary row kept by the GLMO does not change: its 1)."""
+    d = U_next - U_prev
+    s = np.argmax(d, axis=1)
+    still = ~np.any(d != 0, axis=1)
+    s[still] = np.argmax(U_prev[still], axis=1)
+    return s.astype(np.int32)
+
+
+@pytest.mark.parametrize("dtype", [gfw.F64, gfw.F32])
+def test_batch_members_against_oracle(dtype):
+    """Eight random members of the batch mix (SBMs and 4-neighbour grids, n log-uniform in
+    [2e3, 2e5], K in 3..10) in lockstep with the oracle through one batched call per iterate:
+    every member starts from the oracle's U_k and makes one batched iteration, compared with
+    one oracle iteration (step size, U_{k+1}, objective); rows where the batch took another
+    GLMO vertex must be near-ties, and the oracle is then re-run with the batch's vertices."""
+    from oracle import oracle as O
+
+    from gpu_helpers import MAX_DIFF_FRAC, MAX_DIFF_SLACK, NEAR_TIE_REL, armijo_ratio_near_power, glmo_margin, oracle_trajectory, torch_u
+
+    rng = np.random.default_rng(11)
+    picks = sorted(rng.choice(256, size=8, replace=False).tolist())
+    probs = [configs.batch_member(3, int(i)) for i in picks]
+    say(f"[gpu] batch vs oracle dtype={dtype}: members {picks}, n={[p.n for p in probs]}")
+    Gs = [gpu_graph(p.graph, p.K, p.labelled_idx, p.labels, dtype) for p in probs]
+    Ls = [O.operator_for(p.graph) for p in probs]
+    ks = [0, 5, 40]
+    trajs = [oracle_trajectory(p, ks, parallel=True) for p in probs]
+    band = NEAR_TIE_REL[dtype]
+    u_tol = 1e-12 if dtype == gfw.F64 else 1e-5
+    for k in ks:
+        say(f"[gpu] batch vs oracle k={k}")
+        U0s = [torch_u(t[k], dtype) for t in trajs]
+        prms = [gfw.params(eps=p.eps, omega0=p.omega0, max_iter=1, tol=-1.0, U0=u) for p, u in zip(probs, U0s)]
+        out = gfw.solve_batched(ctx(), Gs, prms)
+        for p, L, u0, r in zip(probs, Ls, U0s, out):
+            Uk = _np(u0).astype(np.float64)
+            Ug = _np(r["U"]).astype(np.float64)
+            ro = O.solve(L, p.K, p.labelled_idx, p.labels, eps=p.eps, omega0=p.omega0, max_iter=1, tol=-1.0,
+                         U0=Uk, record_s=True)
+            s_g = _inferred_vertices(Uk, Ug)
+            diff = np.flatnonzero(s_g != ro["s"][0])
+            if diff.size:
+                Uhat, omega = O.fidelity(p.n, p.K, p.labelled_idx, p.labels, p.omega0)
+                Gk = O.gradient(L, Uk, Uhat, omega, p.eps)
+                scale = np.maximum(np.abs(Gk).max(axis=1), 1e-300)
+                assert np.all(glmo_margin(Uk, Gk)[diff] <= band * scale[diff]), "non-tie vertex differs"
+                say(f"[gpu]   member n={p.n}: {diff.size} rows took another minimiser")
+                assert diff.size <= MAX_DIFF_SLACK[dtype] + MAX_DIFF_FRAC[dtype] * p.n
+                ro = O.solve(L, p.K, p.labelled_idx, p.labels, eps=p.eps, omega0=p.omega0, max_iter=1, tol=-1.0,
+                             U0=Uk, record_s=True, s_first=s_g)
+            if armijo_ratio_near_power(ro["g"][0], ro["q"][0]):
+                continue
+            assert r["alpha_last"] == ro["alpha"][0]
+            assert np.abs(Ug - ro["U"]).max() <= u_tol
+            e_rel = 1e-6 if dtype == gfw.F32 else max(1e-12, p.n * p.K * 2.0 ** -53)
+            assert r["objective"] == pytest.approx(ro["objective"], rel=e_rel)
+
+
+def test_batch_free_running_member_against_oracle_f64():
+    """One member of the batch mix solved to its stop (300 iterations or gap 1e-6) inside a
+    batch, in FP64, against the oracle's free-running solve: iterations, labels, objective."""
+    from oracle import oracle as O
+
+    from gpu_helpers import oracle_sensitivity
+
+    probs = [configs.batch_member(3, i) for i in (17, 40, 41)]
+    say(f"[gpu] batch free-running f64: n={[p.n for p in probs]}")
+    Gs = [gpu_graph(p.graph, p.K, p.labelled_idx, p.labels, gfw.F64) for p in probs]
+    out = gfw.solve_batched(ctx(), Gs, gfw.params(eps=50.0, omega0=1000.0, max_iter=300, tol=1e-6))
+    p, r = probs[0], out[0]
+    ro, sens = oracle_sensitivity(p)
+    dE = abs(r["objective"] - ro["objective"]) / abs(ro["objective"])
+    agree = np.mean(_np(r["labels"]) == ro["labels"])
+    say(f"[gpu] batch member 17 (n={p.n}, K={p.K}): iters {r['iters']}/{ro['iters']}, agreement {agree:.5f}, "
+        f"rel dE {dE:.3e} (oracle sensitivity {sens:.3e})")
+    assert agree >= 0.999
+    assert dE <= max(1e-6, 1.5 * sens)

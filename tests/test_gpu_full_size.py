@@ -14,7 +14,7 @@ from oracle import oracle as O
 from paper_2508_09738_amd import gfw
 from synth import configs, graphs
 
-from gpu_helpers import ctx, gpu_graph, lockstep, np_of, say, torch_u
+from gpu_helpers import ctx, gpu_graph, lockstep, np_of, oracle_sensitivity, say, torch_u
 
 pytestmark = pytest.mark.gpu
 
@@ -29,9 +29,13 @@ def sbm_large():
 
 
 def test_full_size_sbm_lockstep(sbm_large):
+    """Lockstep on the whole large SBM at iterates 0, 2, 20 and 50.  On this input the
+    unlabelled rows tie exactly at U_0 (89% of the nodes have no labelled neighbour), take
+    class 0 by the lowest-index rule and drift towards it; the later iterates check the
+    path on rows that are far from uniform."""
     prob, G = sbm_large
     say("[gpu] full size: large SBM lockstep")
-    lockstep(prob, gfw.F32, [0, 2], label="sbm_large")
+    lockstep(prob, gfw.F32, [0, 2, 20, 50], label="sbm_large", traj_parallel=True)
 
 
 def test_full_size_graph_replay_equals_per_launch(sbm_large):
@@ -60,15 +64,17 @@ def test_full_size_knn_mixture():
     """The k-NN workload at its full size (70,000 points in 784 dimensions, K = 10, about 1 M
     entries, 500 iterations): lockstep (FP32) at three iterates, then free-running solves
     against the oracle's.  In FP64 the GPU path follows the oracle: the same step sizes and
-    the objective to 1e-12.  In FP32, U and P are rounded to FP32 at every update (relative
-    2^-24 per update); over 500 updates the objective moves by up to sqrt(500) * 2^-24 * 10 =
-    1.3e-5 relative (the factor 10 covers the terms of E and the steps of an update)."""
+    the objective to 1e-12.  In FP32 the objective contract is 1e-6 relative, or 1.5 times the
+    oracle's own sensitivity to rounding where that is larger: the oracle's objective on the
+    same problem with its nodes renumbered, and with U stored in FP32 after every update,
+    moves from its FP64 result by that much (an oracle-only measure)."""
     say("[gpu] full size: k-NN mixture (graph built with blocked products on the GPU)")
     prob = configs.knn_mixture(device="cuda")
-    lockstep(prob, gfw.F32, [0, 100, 400], label="knn70000")
-    ro = O.solve_problem(prob)
+    lockstep(prob, gfw.F32, [0, 100, 400], label="knn70000", traj_parallel=True)
+    ro, sens = oracle_sensitivity(prob)
     acc = np.mean(ro["labels"] == prob.graph.truth)
-    bound = {gfw.F64: 1e-12, gfw.F32: np.sqrt(prob.max_iter) * 2.0 ** -24 * 10}
+    say(f"[gpu] knn70000: oracle sensitivity to rounding {sens:.3e}")
+    bound = {gfw.F64: 1e-12, gfw.F32: max(1e-6, 1.5 * sens)}
     for dt in (gfw.F64, gfw.F32):
         G = gpu_graph(prob.graph, prob.K, prob.labelled_idx, prob.labels, dt)
         rg = gfw.solve(ctx(), G, gfw.params(eps=prob.eps, omega0=prob.omega0, max_iter=prob.max_iter, tol=prob.tol),

@@ -55,6 +55,15 @@ def test_lockstep_large_k(dtype, K):
     lockstep(prob, dtype, [0, 1, 5, 30], label=f"lfr K={K}")
 
 
+@pytest.mark.parametrize("dtype", [gfw.F32, gfw.F64])
+@pytest.mark.parametrize("K", [585, 1024])
+def test_lockstep_large_k_wide_rows(dtype, K):
+    """The widest instantiations of the many-class row kernel: 10 classes per lane (K = 585,
+    the benchmarked many-classes workload) and 16 per lane (K = 1024, the largest K)."""
+    prob = configs.lfr_many_classes(seed=K, n=12 * K, K=K, frac=0.05, max_iter=30)
+    lockstep(prob, dtype, [0, 1, 6], label=f"lfr K={K}")
+
+
 def test_lockstep_large_k_variants_f64():
     prob = configs.lfr_many_classes(seed=7, n=2000, K=70, frac=0.05, max_iter=30)
     lockstep(prob, gfw.F64, [0, 3, 12], lmo=O.LMO_FULL, label="full-lmo K=70")

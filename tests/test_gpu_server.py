@@ -117,3 +117,30 @@ def test_server_many_classes_request_equals_alone():
     for p, rr in zip(small, rs):
         Gp = gpu_graph(p.graph, p.K, p.labelled_idx, p.labels, gfw.F32)
         np.testing.assert_array_equal(rr["U"], _np(gfw.solve(ctx(), Gp, prm)["U"]))
+
+
+def test_served_results_against_oracle():
+    """A sample of the serving mix (8-neighbour grids with scribbles, smaller sides) served
+    together in FP64 and compared with the oracle's free-running solves: labels, iterations
+    and the objective (1e-6 relative, or the oracle's own sensitivity to rounding)."""
+    from oracle import oracle as O
+
+    from gpu_helpers import oracle_sensitivity
+
+    reqs = [configs.serve_request(31, i, sides=(64, 96, 128), Ks=(3, 4, 6)) for i in range(4)]
+    prm = gfw.params(eps=50.0, omega0=1000.0, max_iter=300, tol=1e-6)
+    sv = gfw.Server(ctx(), 1 << 30, 8)
+    try:
+        ts = [sv.submit(p.n, p.K, p.graph.indptr, p.graph.indices, p.graph.data, p.labelled_idx, p.labels, prm,
+                        dtype=gfw.F64) for p in reqs]
+        res = [sv.poll(t) for t in ts]
+    finally:
+        sv.close()
+    for p, r in zip(reqs, res):
+        ro, sens = oracle_sensitivity(p)
+        agree = np.mean(r["labels"] == ro["labels"])
+        dE = abs(r["objective"] - ro["objective"]) / abs(ro["objective"])
+        say(f"[gpu] served n={p.n} K={p.K}: iters {r['iters']}/{ro['iters']}, agreement {agree:.5f}, "
+            f"rel dE {dE:.3e} (oracle sensitivity {sens:.3e})")
+        assert agree >= 0.999
+        assert dE <= max(1e-6, 1.5 * sens)

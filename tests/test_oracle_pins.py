@@ -27,7 +27,7 @@ def _csr(g):
 
 
 def _ev(expr, eps):
-    return eval(expr, {"sqrt": math.sqrt, "eps": eps})
+    return eval(expr, {"sqrt": math.sqrt, "eps": eps, "min": min})
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -105,6 +105,59 @@ def test_worked_example_exact_step_stops_after_one():
     # so g_1 = -(1 - a) <grad E(U_1), D_0> = 0
     assert abs(r["g"][1]) < 1e-14
     assert r["iters"] == 1 and r["stop_reason"] == O.STOP_TOL
+
+
+def test_worked_example_short_step():
+    """Short step (eq. alphabound): alpha_0 = min(1, g_0 / (Lbar ||D_0||^2)) with ||D_0||^2 = 1 on
+    the path; U_1 = (1 - a) U_0 + a S_0 and E_1 = E_0 - a g_0 + a^2 q_0 / 2 (E is quadratic), all
+    closed forms.  Lbar is given (3) or left to the default, whose closed form is
+    rho_max + 2/eps + omega0 with rho_max = 1 + 1/sqrt(2) + 1/2 (largest absolute row sum of L_s)."""
+    gold, L = _path4()
+    c = gold["cases"]["short_eps50"]
+    eps = c["eps"]
+    r = O.solve(L, 2, [0, 3], [0, 1], eps=eps, omega0=1000.0, max_iter=1, tol=1e-6, ls=O.LS_SHORT,
+                lipschitz=c["Lbar_given"], record_s=True)
+    assert list(r["s"][0]) == gold["cases"]["armijo_eps50"]["s0"]
+    assert r["alpha"][0] == pytest.approx(c["alpha0_given"]["value"], rel=1e-15)
+    np.testing.assert_allclose(r["U"], np.array(c["U1_given"]), rtol=0, atol=1e-15)
+    assert r["objective"] == pytest.approx(c["E1_given"]["value"], abs=1e-14)
+    # a Lbar small enough that g_0 / (Lbar ||D_0||^2) > 1 takes the full step
+    r = O.solve(L, 2, [0, 3], [0, 1], eps=eps, omega0=1000.0, max_iter=1, tol=1e-6, ls=O.LS_SHORT, lipschitz=0.5)
+    assert r["alpha"][0] == 1.0
+    # the default Lbar
+    r = O.solve(L, 2, [0, 3], [0, 1], eps=eps, omega0=1000.0, max_iter=1, tol=1e-6, ls=O.LS_SHORT)
+    assert r["alpha"][0] == pytest.approx(c["alpha0_default"]["value"], rel=1e-14)
+    assert O.default_lipschitz(L, eps, 1000.0) == pytest.approx(c["Lbar_default"]["value"], rel=1e-15)
+    assert O.default_lipschitz(L, eps, 0.0) - 2.0 / eps == pytest.approx(c["rho_max"]["value"], rel=1e-15)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_default_lipschitz_bounds_the_hessian(seed):
+    """Prop. 2: the default Lbar (Gershgorin bound rho_max of L_s, plus 2/eps + omega0) is an
+    upper bound of lambda_max(L_s) + 2/eps + omega0, the constant of the proposition; rho_max
+    itself equals the largest absolute row sum computed independently with SciPy."""
+    g = graphs.sbm_by_degree(300, 3, 8.0, 3.0, 50 + seed)
+    L = O.operator_for(g)
+    Ld = csgraph.laplacian(_csr(g).astype(np.float64), normed=True)
+    lam = np.linalg.eigvalsh(Ld.toarray()).max()
+    rho = np.abs(Ld).sum(axis=1).max()
+    eps, om = 50.0, 1000.0
+    Lbar = O.default_lipschitz(L, eps, om)
+    assert Lbar == pytest.approx(rho + 2.0 / eps + om, rel=1e-14)
+    assert Lbar >= lam + 2.0 / eps + om - 1e-12
+
+
+def test_worked_example_osfw_takes_the_vertex():
+    """One-shot FW (Alg. 4) at eps = 50, where Armijo would take alpha_0 = 1/2: U_1 = S_0 (rows
+    (1,0), (1,0), (0,1), (0,1)), E_1 = 2 - sqrt(2), one update and no further iteration."""
+    gold, L = _path4()
+    c = gold["cases"]["osfw_eps50"]
+    r = O.solve(L, 2, [0, 3], [0, 1], eps=c["eps"], omega0=1000.0, max_iter=10, tol=1e-6, osfw=True)
+    assert r["alpha"][0] == c["alpha0"]
+    np.testing.assert_array_equal(r["U"], np.array(c["U1"]))
+    assert r["objective"] == pytest.approx(c["E1"]["value"], abs=1e-14)
+    assert r["iters"] == c["iters"] and np.isnan(r["E"][1])
+    assert list(r["labels"]) == [0, 0, 1, 1]
 
 
 def test_worked_example_one_shot_small_eps():
