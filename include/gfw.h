@@ -228,6 +228,20 @@ GFW_API gfw_status_t gfw_solve_batched(gfw_context_t ctx, int32_t count, const g
 GFW_API gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm, const void *U,
                            double *E_host, void *stream);
 
+/*
+ * E(U) as gfw_objective computes it (the same kernels, the same result bit for bit), for
+ * callers that cannot allocate memory: code under HIP graph capture, serving loops and
+ * harnesses that forbid allocation.  Allocates nothing and does not synchronise: the result
+ * goes to the DEVICE double *E_dev, ordered on `stream`.  Its block partials live in a fixed
+ * scratch array of 3 x 65536 doubles (1.5 MiB) that the library holds on each device it
+ * runs on until the process ends; graphs needing more partial blocks than that (n above
+ * 16,777,216 for K <= 16, above 524,288 for K > 16) get GFW_E_UNSUPPORTED before any launch.
+ * Every call on a device shares that device's array: calls that overlap on one device (on
+ * different streams, or from different threads) race and must be serialised by the caller.
+ */
+GFW_API gfw_status_t gfw_objective_noalloc(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm, const void *U,
+                                   double *E_dev, void *stream);
+
 /* P = L_s U (the graph-Laplacian times n x K product of eq. gradgl_vv2g); DEVICE U, P. */
 GFW_API gfw_status_t gfw_spmm(gfw_context_t ctx, gfw_graph_t g, const void *U, void *P, void *stream);
 

@@ -17,6 +17,12 @@
 
 namespace gfw {
 
+// Block partials of gfw_objective_noalloc, [3][kNoAllocMaxBlocks] (1.5 MiB), held by every
+// device the library runs on until the process ends.  Host code never passes this name to a
+// kernel: it uses the device address taken with hipGetSymbolAddress at context creation.
+constexpr int kNoAllocMaxBlocks = 65536;
+static __device__ __align__(256) double scratch[3 * kNoAllocMaxBlocks];
+
 static thread_local char g_last_error[512] = "";
 
 void set_error(const char *fmt, ...)
@@ -1165,6 +1171,14 @@ gfw_status_t gfw_context_create(gfw_context_t *ctx, int device)
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
+    // the scratch array of gfw_objective_noalloc on this device, taken with the device current
+    hipError_t e2 = hipSetDevice(device);
+    if (e2 == hipSuccess) e2 = hipGetSymbolAddress((void **)&c->noalloc_scratch, HIP_SYMBOL(gfw::scratch));
+    if (e2 != hipSuccess || !c->noalloc_scratch) {
+        delete c;
+        return fail(GFW_E_HIP, "hipGetSymbolAddress of the objective scratch failed on device %d: %s", device,
+                    hipGetErrorString(e2));
+    }
     *ctx = c;
     return GFW_OK;
 }
@@ -1257,6 +1271,27 @@ gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t 
     GFW_HIP_TRY(hipSetDevice(ctx->device));
     return g->dtype == GFW_F32 ? objective_impl<float>(g, prm, (const float *)U, E_host, (hipStream_t)stream)
                                : objective_impl<double>(g, prm, (const double *)U, E_host, (hipStream_t)stream);
+}
+
+gfw_status_t gfw_objective_noalloc(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm, const void *U,
+                                   double *E_dev, void *stream)
+{
+    if (!ctx || !g || !U || !E_dev) return fail(GFW_E_INVALID_ARG, "NULL argument");
+    gfw_status_t s = check_params(prm, g->K);
+    if (s != GFW_OK) return s;
+    const int blocks = g->K > 16 ? g->shape.nb_big : g->shape.nb_row;
+    if (blocks > kNoAllocMaxBlocks)
+        return fail(GFW_E_UNSUPPORTED,
+                    "gfw_objective_noalloc: n = %lld needs %d partial blocks, above its fixed scratch of %d "
+                    "(n <= %lld for K <= 16, n <= %lld for K > 16)",
+                    (long long)g->n, blocks, kNoAllocMaxBlocks, (long long)kNoAllocMaxBlocks * kRowBlock,
+                    (long long)kNoAllocMaxBlocks * kBigRowsPerBlock);
+    if (!ctx->noalloc_scratch) return fail(GFW_E_HIP, "no objective scratch on device %d", ctx->device);
+    GFW_HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    return g->dtype == GFW_F32
+               ? objective_to_device<float>(g, prm, (const float *)U, ctx->noalloc_scratch, E_dev, st)
+               : objective_to_device<double>(g, prm, (const double *)U, ctx->noalloc_scratch, E_dev, st);
 }
 
 gfw_status_t gfw_trace_enable(gfw_context_t ctx, int enable)

@@ -80,6 +80,9 @@ struct gfw_context_s {
     int device = 0;
     int num_cu = 0;
     std::string arch;
+    // device address of the file-scope scratch array of gfw_objective_noalloc on this
+    // context's device (taken once, at context creation, with the device current)
+    double *noalloc_scratch = nullptr;
     // tracing: events bracketing hot-path launches, resolved when the owning call ends
     bool trace = false;       // hot-path launches bracketed by events (no captured iterations)
     uint32_t trace_mask = 0;  // kernel classes timed while tracing (bit k: class k)
