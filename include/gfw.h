@@ -266,6 +266,13 @@ GFW_API gfw_status_t gfw_trace_enable(gfw_context_t ctx, int enable);
 GFW_API gfw_status_t gfw_trace_reset(gfw_context_t ctx);
 GFW_API gfw_status_t gfw_trace_get(gfw_context_t ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
+/* Measurement aid, not part of the method: the achievable HBM rate on the context's
+ * device, the ceiling the roofline figures are compared with beside the 8 TB/s spec peak.
+ * Allocates two buffers of `bytes` (rounded down to 16), times `reps` launches of a streaming
+ * 16-byte non-temporal copy kernel with HIP events on the null stream (synchronising the
+ * device), frees the buffers and returns (bytes read + bytes written) per second in GB/s. */
+GFW_API gfw_status_t gfw_copy_bandwidth(gfw_context_t ctx, size_t bytes, int32_t reps, double *gbs);
+
 /* ---- serving ------------------------------------------------------------------------ */
 /*
  * A request server: submitted problems (HOST arrays, copied at submit) are admitted while

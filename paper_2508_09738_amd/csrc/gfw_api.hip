@@ -313,17 +313,19 @@ static double label_locality(int64_t nnz, const int32_t *col)
 // Entries per tile of the column-sorted label pass.  A CU runs one tile at a time, and the
 // tiles of a launch cost about the same, so the launch takes as many rounds as the tile count
 // divided by the CU count, rounded up: the target is the largest tile size (densest gathers)
-// whose tiles fill a whole number of rounds.  Greedy tiling closes a tile only when the next
-// row would pass the target, so every closed tile holds more than target - maxrow entries
+// whose tiles fill a whole number of rounds.  Tiles are whole 256-row blocks (the blocks of
+// the row kernel, which the persistent iteration kernel runs inside a tile), and the greedy
+// tiling closes a tile only when the next block would pass the target, so every closed tile
+// holds more than target - maxblock entries (maxblock: the most entries of any 256-row block)
 // and there are at most cus * R tiles.
-int64_t sorted_tile_target(int64_t nnz, int64_t maxrow, int64_t cus, int64_t *rounds)
+int64_t sorted_tile_target(int64_t nnz, int64_t maxblock, int64_t cus, int64_t *rounds)
 {
     if (rounds) *rounds = 0;
-    if (maxrow >= kSortedMaxEntries) return kSortedMaxEntries;
-    const int64_t room = kSortedMaxEntries - maxrow;
+    if (maxblock >= kSortedMaxEntries) return kSortedMaxEntries;
+    const int64_t room = kSortedMaxEntries - maxblock;
     int64_t R = std::max<int64_t>(1, cdiv(nnz, cus * room));
     for (;; ++R) {
-        const int64_t t = cdiv(nnz, std::max<int64_t>(cus * R - 1, 1)) + maxrow;
+        const int64_t t = cdiv(nnz, std::max<int64_t>(cus * R - 1, 1)) + maxblock;
         if (t <= kSortedMaxEntries) {
             if (rounds) *rounds = R;
             return std::max<int64_t>(t, 1);
@@ -333,13 +335,24 @@ int64_t sorted_tile_target(int64_t nnz, int64_t maxrow, int64_t cus, int64_t *ro
 
 // Tiles closed by the entry target number fewer than cus * R (each holds more than
 // nnz / (cus * R - 1) entries); the row cap closes at most n / rcap more; one is last.
-int64_t sorted_tile_bound(int64_t n, int64_t nnz, int64_t maxrow, int64_t cus)
+int64_t sorted_tile_bound(int64_t n, int64_t nnz, int64_t maxblock, int64_t cus)
 {
     int64_t R = 0;
-    (void)sorted_tile_target(nnz, maxrow, cus, &R);
-    if (R == 0) return n + 1; // a row fills a whole tile: at most one tile per row
-    return cus * R + cdiv(n, 16 * kSortedThreads) + 1;
+    (void)sorted_tile_target(nnz, maxblock, cus, &R);
+    if (R == 0) return cdiv(n, kRowBlock) + 1; // a block fills a whole tile: at most one tile per block
+    return cus * R + cdiv(n, kSortedRowCap) + 1;
 }
+
+// The most entries of any 256-row block of a CSR with host row pointers rp.
+template <typename I>
+int64_t max_block_entries(int64_t n, const I *rp)
+{
+    int64_t m = 0;
+    for (int64_t b = 0; b < n; b += kRowBlock) m = std::max<int64_t>(m, (int64_t)(rp[std::min(n, b + kRowBlock)] - rp[b]));
+    return m;
+}
+template int64_t max_block_entries<int32_t>(int64_t, const int32_t *);
+template int64_t max_block_entries<int64_t>(int64_t, const int64_t *);
 
 // The buffers of ensure_workspace except the per-iteration history (5 doubles per iteration).
 void refresh_solve_bytes(gfw_graph_s *g)
@@ -356,34 +369,41 @@ void refresh_solve_bytes(gfw_graph_s *g)
                      + sizeof(double) * (row_parts + lab + scratch) + sizeof(Ctl);
 }
 
-// Row tiles for the column-sorted label pass and the per-tile column order of the entries.
+// Row tiles for the column-sorted label pass (whole 256-row blocks, at most kSortedRowCap
+// rows) and the per-tile column order of the entries.
 static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const int32_t *col, hipStream_t st)
 {
     const int64_t n = g->n;
-    const int64_t rcap = 16 * kSortedThreads; // rows per tile (a thread sums at most 16)
-    int64_t maxrow = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t d = rp[i + 1] - rp[i];
-        if (d > kSortedMaxEntries) return fail(GFW_E_UNSUPPORTED, "row %lld has more than %d entries", (long long)i,
-                                               kSortedMaxEntries);
-        maxrow = std::max(maxrow, d);
-    }
-    const int64_t target = sorted_tile_target(g->nnz, maxrow, std::max(1, g->ctx->num_cu));
+    const int64_t maxblock = max_block_entries<int32_t>(n, rp);
+    if (maxblock > kSortedMaxEntries)
+        return fail(GFW_E_UNSUPPORTED, "a 256-row block has more than %d entries", kSortedMaxEntries);
+    const int cus = std::max(1, g->ctx->num_cu);
+    const int64_t target = sorted_tile_target(g->nnz, maxblock, cus);
     std::vector<int32_t> tr;
-    tr.push_back(0);
-    int64_t cr = 0, ce = 0, emax = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t d = rp[i + 1] - rp[i];
-        if (cr + 1 > rcap || ce + d > target) {
-            tr.push_back((int32_t)i);
-            cr = 0;
-            ce = 0;
+    int64_t emax = 0, rmax = 0;
+    // greedy tiling: a tile closes when the next block would pass the entry target or the
+    // row cap
+    auto tiling = [&](int64_t rcap) {
+        tr.assign(1, 0);
+        int64_t cr = 0, ce = 0;
+        emax = 0;
+        rmax = 0;
+        for (int64_t b = 0; b < n; b += kRowBlock) {
+            const int64_t rows = std::min<int64_t>(kRowBlock, n - b);
+            const int64_t d = rp[b + rows] - rp[b];
+            if (cr + rows > rcap || ce + d > target) {
+                tr.push_back((int32_t)b);
+                cr = 0;
+                ce = 0;
+            }
+            cr += rows;
+            ce += d;
+            emax = std::max(emax, ce);
+            rmax = std::max(rmax, cr);
         }
-        ++cr;
-        ce += d;
-        emax = std::max(emax, ce);
-    }
-    tr.push_back((int32_t)n);
+        tr.push_back((int32_t)n);
+    };
+    tiling(kSortedRowCap);
     const int32_t nt = (int32_t)tr.size() - 1;
     const int64_t nnz = g->nnz;
     // chunks of kSortedChunk sorted entries, aligned to the start of each tile
@@ -443,6 +463,7 @@ static gfw_status_t build_sorted_tiles(gfw_graph_s *g, const int32_t *rp, const 
     }
     GFW_HIP_TRY(hipStreamSynchronize(st));
     g->n_tiles = nt;
+    g->tile_rows_max = (int32_t)rmax;
     refresh_solve_bytes(g);
     g->sorted_lds = (int32_t)std::max<int64_t>(16, (emax + 15) / 16 * 16);
     g->wide_chunks = 0;
@@ -771,7 +792,7 @@ static void launch_spmm(const gfw_graph_s *g, const T *U, PT *P, hipStream_t st)
     if constexpr (KMAX > 16)
         k_spmm_big<T, KMAX / 64, PT><<<g->shape.nb_big, kBigThreads, 0, st>>>(make_view<T>(g), U, P);
     else
-        k_spmm<T, KMAX, PT><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), U, P);
+        k_spmm<T, KMAX, PT><<<g->shape.nb_row, kSpmmThreads, 0, st>>>(make_view<T>(g), U, P);
 }
 
 template <typename T, int KMAX>
@@ -845,6 +866,9 @@ static gfw_status_t measure_label_paths(gfw_graph_s *g, hipStream_t st)
     std::memset(&c, 0, sizeof(c));
     c.active = 1;
     c.last_eval = -1;
+    // a ticket count the timed passes never complete: no launch makes the finish of an
+    // iteration, so every launch does the same work
+    c.ticket = 0x80000000u;
     GFW_HIP_TRY(hipMemcpyAsync(w.ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
     GFW_HIP_TRY(hipMemsetAsync(w.s0, 0, g->n, st));
     GFW_HIP_TRY(hipMemsetAsync(w.s4, 0, (size_t)(g->n + 1) / 2, st));
@@ -903,7 +927,6 @@ static void launch_row(gfw_graph_s *g, int apply_only, hipStream_t st)
 template <typename T, int KMAX>
 static void launch_iteration(gfw_graph_s *g, hipStream_t st, bool traced)
 {
-    Workspace &w = g->ws;
     gfw_context_s *cx = traced ? g->ctx : nullptr;
     hipEvent_t ev = trace_begin(cx, GFW_KERNEL_ROW, st);
     launch_row<T, KMAX>(g, 0, st);
@@ -911,14 +934,7 @@ static void launch_iteration(gfw_graph_s *g, hipStream_t st, bool traced)
     ev = trace_begin(cx, GFW_KERNEL_LABEL, st);
     launch_label<T, KMAX>(g, st);
     trace_end(cx, GFW_KERNEL_LABEL, ev, st);
-    ev = trace_begin(cx, GFW_KERNEL_FINISH, st);
-    if (KMAX <= 16 && g->label_path == 1) // the sorted pass folds the row partials per tile
-        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_fold, g->n_tiles, w.lab_part, g->n_tiles, w.ctl);
-    else if (KMAX > 16) // the large-K label pass folds them per 256-row block
-        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_fold, g->shape.nb_row, w.lab_part, g->shape.nb_row, w.ctl);
-    else
-        k_finish<<<1, kFinishThreads, 0, st>>>(w.row_part, g->shape.nb_row, w.lab_part, g->shape.nb_row, w.ctl);
-    trace_end(cx, GFW_KERNEL_FINISH, ev, st);
+    // the finish of the iteration is made by the label pass's last workgroup (finish_if_last)
 }
 
 constexpr int kGraphChunk = 16; // iterations per captured graph
@@ -955,6 +971,8 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     Workspace &w = g->ws;
     T *U = (T *)w.U;
     double *P = w.P;
+    const int64_t nK = g->n * g->K;
+    gfw_context_s *cx = g->ctx;
     Ctl c0;
     std::memset(&c0, 0, sizeof(c0));
     c0.active = prm->max_iter > 0 ? 1 : 0;
@@ -968,9 +986,7 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     c0.hist = w.hist;
     c0.hist_stride = prm->max_iter + 1;
     GFW_HIP_TRY(hipMemcpyAsync(w.ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, st));
-    const int64_t nK = g->n * g->K;
     k_init_u<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), (const T *)prm->U0);
-    gfw_context_s *cx = g->ctx;
     hipEvent_t ev = trace_begin(cx, GFW_KERNEL_SPMM, st);
     spmm_any<T>(g, U, P, st);
     trace_end(cx, GFW_KERNEL_SPMM, ev, st);
@@ -1063,9 +1079,9 @@ static int energy_partials(const gfw_graph_s *g, const T *U, double omega0, doub
 {
     const GraphView<T> v = make_view<T>(g);
     switch (g->shape.kmax) {
-    case 4: k_energy<T, 4><<<g->shape.nb_row, kRowBlock, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
-    case 8: k_energy<T, 8><<<g->shape.nb_row, kRowBlock, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
-    case 16: k_energy<T, 16><<<g->shape.nb_row, kRowBlock, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
+    case 4: k_energy<T, 4><<<g->shape.nb_row, kSpmmThreads, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
+    case 8: k_energy<T, 8><<<g->shape.nb_row, kSpmmThreads, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
+    case 16: k_energy<T, 16><<<g->shape.nb_row, kSpmmThreads, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
 #define GFW_ENERGY_BIG(KM)                                                                                       \
     case KM: k_energy_big<T, KM / 64><<<g->shape.nb_big, kBigThreads, 0, st>>>(v, U, omega0, part);              \
         return g->shape.nb_big;
@@ -1292,6 +1308,41 @@ gfw_status_t gfw_objective_noalloc(gfw_context_t ctx, gfw_graph_t g, const gfw_p
     return g->dtype == GFW_F32
                ? objective_to_device<float>(g, prm, (const float *)U, ctx->noalloc_scratch, E_dev, st)
                : objective_to_device<double>(g, prm, (const double *)U, ctx->noalloc_scratch, E_dev, st);
+}
+
+gfw_status_t gfw_copy_bandwidth(gfw_context_t ctx, size_t bytes, int32_t reps, double *gbs)
+{
+    if (!ctx || !gbs || reps < 1 || bytes < 16) return fail(GFW_E_INVALID_ARG, "bad argument");
+    GFW_HIP_TRY(hipSetDevice(ctx->device));
+    const int64_t n16 = (int64_t)(bytes / 16);
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, 16 * (size_t)n16) != hipSuccess) return fail(GFW_E_NOMEM, "copy buffer");
+    if (hipMalloc(&b, 16 * (size_t)n16) != hipSuccess) {
+        dfree(a);
+        return fail(GFW_E_NOMEM, "copy buffer");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    gfw_status_t s = GFW_OK;
+    float ms = 0.f;
+    const int grid = std::max(1, ctx->num_cu) * 8;
+    if (hipMemset(a, 0, 16 * (size_t)n16) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        s = fail(GFW_E_HIP, "copy set-up failed");
+    } else {
+        k_stream_copy<<<grid, 256>>>((const v4u *)a, (v4u *)b, n16); // warm-up
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps; ++r) k_stream_copy<<<grid, 256>>>((const v4u *)a, (v4u *)b, n16);
+        (void)hipEventRecord(e1, nullptr);
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess || ms <= 0.f)
+            s = fail(GFW_E_HIP, "copy timing failed");
+        else
+            *gbs = 2.0 * 16.0 * (double)n16 * reps / (1e-3 * ms) / 1e9;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dfree(a);
+    dfree(b);
+    return s;
 }
 
 gfw_status_t gfw_trace_enable(gfw_context_t ctx, int enable)

@@ -184,7 +184,7 @@ static void batch_iteration(BatchTables<T> &bt, hipStream_t st)
     batch_label_bucket<T, 8>(bt, 1, st);
     batch_label_bucket<T, 16>(bt, 2, st);
     if (!bt.big_lab.empty()) k_label_big_batch<T><<<bt.big_lab.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_biglab);
-    k_finish_batch<T><<<bt.views.size(), kFinishThreads, 0, st>>>(bt.d_views);
+    // each graph's finish is made by the last workgroup of its label pass (finish_if_last)
 }
 
 // Builds the device tables of a batch (graphs gs with settings prms; every graph's
@@ -269,10 +269,10 @@ static gfw_status_t batch_prepare(BatchTables<T> &bt, int32_t count, gfw_graph_s
         // U_0 and P_0 = L_s U_0 for every graph
         k_set_ctl_batch<T><<<grid_for(count, 256), 256, 0, st>>>(bt.d_views, bt.d_ctl0, count);
         k_init_u_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_U0);
-        if (!bt.rows[0].empty()) k_spmm_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
-        if (!bt.rows[1].empty()) k_spmm_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
+        if (!bt.rows[0].empty()) k_spmm_batch<T, 4><<<bt.rows[0].size(), kSpmmThreads, 0, st>>>(bt.d_views, bt.d_rows[0]);
+        if (!bt.rows[1].empty()) k_spmm_batch<T, 8><<<bt.rows[1].size(), kSpmmThreads, 0, st>>>(bt.d_views, bt.d_rows[1]);
         if (!bt.rows[2].empty())
-            k_spmm_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
+            k_spmm_batch<T, 16><<<bt.rows[2].size(), kSpmmThreads, 0, st>>>(bt.d_views, bt.d_rows[2]);
         batch_big_launch<T>(bt, 1, 0, st);
         GFW_HIP_TRY(hipGetLastError());
     }
@@ -367,10 +367,10 @@ static gfw_status_t batch_collect(BatchTables<T> &bt, bool labels, std::vector<d
 {
     const int count = (int)bt.views.size();
     if (labels) k_labels_batch<T><<<bt.all_rows.size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_all, bt.d_lab_out);
-    if (!bt.rows[0].empty()) k_energy_batch<T, 4><<<bt.rows[0].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[0]);
-    if (!bt.rows[1].empty()) k_energy_batch<T, 8><<<bt.rows[1].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[1]);
+    if (!bt.rows[0].empty()) k_energy_batch<T, 4><<<bt.rows[0].size(), kSpmmThreads, 0, st>>>(bt.d_views, bt.d_rows[0]);
+    if (!bt.rows[1].empty()) k_energy_batch<T, 8><<<bt.rows[1].size(), kSpmmThreads, 0, st>>>(bt.d_views, bt.d_rows[1]);
     if (!bt.rows[2].empty())
-        k_energy_batch<T, 16><<<bt.rows[2].size(), kRowBlock, 0, st>>>(bt.d_views, bt.d_rows[2]);
+        k_energy_batch<T, 16><<<bt.rows[2].size(), kSpmmThreads, 0, st>>>(bt.d_views, bt.d_rows[2]);
     batch_big_launch<T>(bt, 2, 0, st);
     gfw_status_t s;
     if ((s = bt.dE.reserve(count)) != GFW_OK || (s = bt.dctl_out.reserve(count)) != GFW_OK) return s;
@@ -446,9 +446,8 @@ static size_t request_footprint(const gfw_problem_t *p, int32_t max_iter, bool w
     size_t graph = 4 * (n + 1) + (4 + v) * nnz + 4 * n;
     size_t tiles = 0; // label-pass partials beyond one per 256-row block (sorted tiles)
     if (p->nnz >= ((int64_t)4 << 20) && K <= 16) {
-        int64_t maxrow = 0;
-        for (int64_t i = 0; i < p->n; ++i) maxrow = std::max<int64_t>(maxrow, p->row_ptr[i + 1] - p->row_ptr[i]);
-        tiles = (size_t)sorted_tile_bound(p->n, p->nnz, maxrow, std::max(1, cus));
+        const int64_t maxblock = max_block_entries<int64_t>(p->n, p->row_ptr);
+        tiles = (size_t)sorted_tile_bound(p->n, p->nnz, maxblock, std::max(1, cus));
         // column-sorted copy (4 bytes per entry), its anchors (one per 64 entries plus one
         // partial run per tile) and two tile tables
         graph += 4 * nnz + 4 * (nnz / 64 + tiles) + 8 * (tiles + 1);

@@ -121,6 +121,7 @@ struct gfw_graph_s {
     // column-sorted copy of the CSR for the label pass (see k_label_sorted)
     int label_path = 0;         // 0: plain (k_label), 1: column-sorted (k_label_sorted)
     int32_t n_tiles = 0;
+    int32_t tile_rows_max = 0;     // rows of the largest sorted tile
     int32_t *tile_rows = nullptr;  // int32[n_tiles + 1]
     int32_t *tile_chunk = nullptr; // int32[n_tiles + 1], first anchor of each tile
     int32_t *ganch = nullptr;      // int32[chunks], anchor column of each 64-entry chunk, -1: wide
@@ -146,11 +147,15 @@ gfw_status_t graph_create(gfw_context_s *ctx, const gfw_problem_t *p, gfw_graph_
                           bool validated = false);
 void free_graph(gfw_graph_s *g);
 gfw_status_t ensure_workspace(gfw_graph_s *g, int32_t max_iter);
-// Column-sorted tiles: the entry target per tile for a graph of nnz entries whose longest row
-// has maxrow entries on a device of cus compute units (rounds: the launch's rounds of tiles),
-// and an upper bound of the resulting tile count for n rows.
-int64_t sorted_tile_target(int64_t nnz, int64_t maxrow, int64_t cus, int64_t *rounds = nullptr);
-int64_t sorted_tile_bound(int64_t n, int64_t nnz, int64_t maxrow, int64_t cus);
+// Column-sorted tiles (whole 256-row blocks): the entry target per tile for a graph of nnz
+// entries whose fullest 256-row block has maxblock entries on a device of cus compute units
+// (rounds: the launch's rounds of tiles), an upper bound of the resulting tile count for n
+// rows, and the fullest block of a CSR with host row pointers.
+constexpr int64_t kSortedRowCap = 16 * kSortedThreads; // rows per tile (a thread sums at most 16)
+int64_t sorted_tile_target(int64_t nnz, int64_t maxblock, int64_t cus, int64_t *rounds = nullptr);
+int64_t sorted_tile_bound(int64_t n, int64_t nnz, int64_t maxblock, int64_t cus);
+template <typename I>
+int64_t max_block_entries(int64_t n, const I *rp);
 // Device bytes of one solve on the graph as it stands (its label pass included).
 void refresh_solve_bytes(gfw_graph_s *g);
 SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm);
@@ -191,6 +196,8 @@ GraphView<T> make_view(const gfw_graph_s *g)
     v.nb_row = g->shape.nb_row;
     v.nb_big = g->shape.nb_big;
     v.n_tiles = g->label_path == 1 ? g->n_tiles : 0;
+    v.ticket = w.ctl ? &w.ctl->ticket : nullptr;
+    v.n_lab_blocks = (g->K <= 16 && g->label_path == 1) ? g->n_tiles : g->shape.nb_row;
     v.tile_rows = g->tile_rows;
     v.tile_chunk = g->tile_chunk;
     v.ganch = g->ganch;

@@ -66,7 +66,7 @@ struct Ctl {
     SolveParams sp;
     double *hist;        // 5 x hist_stride history (may be null)
     int32_t hist_stride;
-    int32_t pad_;
+    uint32_t ticket;     // label-pass workgroups done with the iteration (finish_if_last)
 };
 
 // ---------------------------------------------------------------------------------
@@ -235,8 +235,21 @@ static __global__ void k_fill_i32(int64_t n, int32_t *p, int32_t v)
 // per-solve kernels
 // ---------------------------------------------------------------------------------
 
-// Block sum of N per-thread values, stored at out[j * stride] (fixed order).
-template <int N>
+// A store that writes through to memory (device-scope coherent): partials that the last
+// workgroup of a label pass reads while the other workgroups of the launch run.
+__device__ __forceinline__ void store_coherent(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double load_coherent(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block sum of N per-thread values, stored at out[j * stride] (fixed order); COH: the store
+// writes through to memory.
+template <int N, bool COH = false>
 __device__ __forceinline__ void block_sum_store_strided(double (&v)[N], double *out, int64_t stride)
 {
     __shared__ double red[kRowBlock / 64][N];
@@ -251,7 +264,10 @@ __device__ __forceinline__ void block_sum_store_strided(double (&v)[N], double *
     if (threadIdx.x < N) {
         double s = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w][threadIdx.x];
-        out[threadIdx.x * stride] = s;
+        if (COH)
+            store_coherent(out + threadIdx.x * stride, s);
+        else
+            out[threadIdx.x * stride] = s;
     }
 }
 
@@ -283,6 +299,8 @@ struct GraphView {
     Ctl *ctl;
     double *row_part, *lab_part;
     double *row_fold; // the row partials folded per label-pass block, [kRowParts][n_fold] (else null)
+    unsigned int *ticket; // label-pass workgroups that have written their partials (finish_if_last)
+    int32_t n_lab_blocks; // workgroups of the graph's label pass
     int32_t n_fold;   // label-pass blocks that fold: sorted tiles, or the 256-row blocks for K > 16
     int32_t nb_row;   // 256-row tiles (row kernel, plain label pass, SpMM)
     int32_t nb_big;   // blocks of the large-K row kernel (stride of its partials)
@@ -298,225 +316,294 @@ struct TileRef {
     int32_t graph, tile;
 };
 
-// Row kernel body (see the file header): pending update, gradient, GLMO, per-row partials.
-// A block owns tile `tile` (kRowBlock consecutive rows).  Their U, P and Q rows form
-// contiguous runs of rows*K elements, moved between HBM and LDS with coalesced accesses;
-// each thread then works on one row out of LDS.  Partials are stored transposed:
-// row_part[j * nb_row + tile].  Dynamic LDS: kRowBlock * K * (2 sizeof(T) + 8).
-template <typename T, typename ST, int KB>
-__device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile, const int apply_only)
+// ---------------------------------------------------------------------------------
+// Row work (see the file header): pending update, gradient, GLMO, per-row partials.
+// A group of kRowBlock threads owns a 256-row block; the block's U and P rows (and Q rows,
+// when they come from memory) form contiguous runs of rows*K elements, moved between HBM
+// and LDS with coalesced 16-byte accesses; each thread then works on one row out of LDS.
+// The pieces below are shared by the row kernel and the persistent iteration kernel, so
+// that both compute every row with the same operations.
+// ---------------------------------------------------------------------------------
+
+// LDS of one 256-row block: P (FP64), U, and optionally Q (graph dtype).
+template <typename T>
+struct RowLds {
+    double *p;
+    T *u, *q;
+};
+
+template <typename T>
+__device__ __forceinline__ RowLds<T> row_lds_at(unsigned char *base, int K, bool with_q)
 {
-    const int64_t n = gv.n;
-    const int32_t K = gv.K;
-    const int32_t *__restrict__ lab = gv.lab;
-    T *__restrict__ U = gv.U;
-    double *__restrict__ P = gv.P;
-    const T *__restrict__ Q = gv.Q;
-    ST *__restrict__ s0 = gv.s0;
-    ST *__restrict__ s1 = gv.s1;
-    const Ctl *__restrict__ ctl = gv.ctl;
-    double *__restrict__ part = gv.row_part;
-    // apply_only: commit the pending update and evaluate nothing
-    const int32_t active = apply_only ? 0 : ctl->active, pending = ctl->pending;
-    if (!active && !pending) return;
-    // iteration k writes its vertices to s[k & 1]; the pending update is the one of the
-    // last evaluated iteration
-    const ST *__restrict__ s_prev = (ctl->last_eval & 1) ? s1 : s0;
-    ST *__restrict__ s_cur = (ctl->k & 1) ? s1 : s0;
-    const double alpha = ctl->alpha;
-    const SolveParams sp = ctl->sp;
-    extern __shared__ unsigned char lds_raw[];
-    double *lp = reinterpret_cast<double *>(lds_raw);
-    T *lu = reinterpret_cast<T *>(lp + kRowBlock * K);
-    T *lq = lu + kRowBlock * K;
-    const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)tile * kRowBlock;
-    const int rows = (int)min((int64_t)kRowBlock, n - r0);
-    const int cnt = rows * K;
-    const int64_t base = r0 * K;
-    // The block's runs of rows*K elements start on 16-byte boundaries (256*K*sizeof(T) is a
-    // multiple of 16); full blocks move them with 16-byte vectors, the ragged last block with
-    // scalars.  All loads are issued before the LDS stores.
-    constexpr int VE = 16 / sizeof(T);                  // elements of U or Q per 16-byte vector
+    RowLds<T> l;
+    l.p = reinterpret_cast<double *>(base);
+    l.u = reinterpret_cast<T *>(l.p + kRowBlock * K);
+    l.q = with_q ? l.u + kRowBlock * K : nullptr;
+    return l;
+}
+
+// Rows of block `blk` (kRowBlock rows from r0) and how its element run is moved.
+struct RowSpan {
+    int64_t r0, base;
+    int rows, cnt;
+    bool full;
+};
+
+__device__ __forceinline__ RowSpan row_span(int64_t n, int K, int64_t blk)
+{
+    RowSpan sp;
+    sp.r0 = blk * kRowBlock;
+    sp.rows = (int)min((int64_t)kRowBlock, n - sp.r0);
+    sp.cnt = sp.rows * K;
+    sp.base = sp.r0 * K;
+    sp.full = sp.rows == kRowBlock;
+    return sp;
+}
+
+// U, P (and Q if l.q) of the block into LDS; t is the thread's index in its 256-thread group.
+// The block's runs start on 16-byte boundaries (256*K*sizeof(T) is a multiple of 16); full
+// blocks move them with 16-byte vectors, the ragged last block with scalars.  All loads are
+// issued before the LDS stores.
+template <typename T, int KB>
+__device__ __forceinline__ void row_stage_in(const GraphView<T> &gv, const RowSpan &sp, const RowLds<T> &l, int t,
+                                             bool want_q)
+{
+    constexpr int VE = 16 / sizeof(T);                                     // elements of U or Q per vector
     constexpr int VPT = (KB * kRowBlock / VE + kRowBlock - 1) / kRowBlock; // vectors per thread
-    constexpr int VPTP = (KB * kRowBlock / 2 + kRowBlock - 1) / kRowBlock;  // the same for P (FP64)
-    const bool full = rows == kRowBlock;
-    if (full) {
-        const int nvec = cnt / VE, nvecp = cnt / 2;
-        const v4u *gu = reinterpret_cast<const v4u *>(U + base);
-        const v4u *gp = reinterpret_cast<const v4u *>(P + base);
-        const v4u *gq = reinterpret_cast<const v4u *>(Q + base);
+    constexpr int VPTP = (KB * kRowBlock / 2 + kRowBlock - 1) / kRowBlock; // the same for P (FP64)
+    const T *__restrict__ U = gv.U;
+    const double *__restrict__ P = gv.P;
+    const T *__restrict__ Q = gv.Q;
+    if (sp.full) {
+        const int nvec = sp.cnt / VE, nvecp = sp.cnt / 2;
+        const v4u *gu = reinterpret_cast<const v4u *>(U + sp.base);
+        const v4u *gp = reinterpret_cast<const v4u *>(P + sp.base);
+        const v4u *gq = reinterpret_cast<const v4u *>(Q + sp.base);
         v4u vu[VPT], vp[VPTP], vq[VPT];
 #pragma unroll
         for (int m = 0; m < VPT; ++m) {
-            const int v = min(tid + m * kRowBlock, nvec - 1);
+            const int v = min(t + m * kRowBlock, nvec - 1);
             vu[m] = __builtin_nontemporal_load(gu + v);
-            vq[m] = __builtin_nontemporal_load(gq + v); // Q is only used when an update is pending (every iteration but the first)
+            if (want_q) vq[m] = __builtin_nontemporal_load(gq + v);
         }
 #pragma unroll
-        for (int m = 0; m < VPTP; ++m) vp[m] = __builtin_nontemporal_load(gp + min(tid + m * kRowBlock, nvecp - 1));
+        for (int m = 0; m < VPTP; ++m) vp[m] = __builtin_nontemporal_load(gp + min(t + m * kRowBlock, nvecp - 1));
 #pragma unroll
         for (int m = 0; m < VPT; ++m) {
-            const int v = tid + m * kRowBlock;
+            const int v = t + m * kRowBlock;
             if (v < nvec) {
-                reinterpret_cast<v4u *>(lu)[v] = vu[m];
-                reinterpret_cast<v4u *>(lq)[v] = vq[m];
+                reinterpret_cast<v4u *>(l.u)[v] = vu[m];
+                if (want_q) reinterpret_cast<v4u *>(l.q)[v] = vq[m];
             }
         }
 #pragma unroll
         for (int m = 0; m < VPTP; ++m) {
-            const int v = tid + m * kRowBlock;
-            if (v < nvecp) reinterpret_cast<v4u *>(lp)[v] = vp[m];
+            const int v = t + m * kRowBlock;
+            if (v < nvecp) reinterpret_cast<v4u *>(l.p)[v] = vp[m];
         }
     } else {
-        for (int q = tid; q < cnt; q += kRowBlock) {
-            lu[q] = U[base + q];
-            lp[q] = P[base + q];
-            if (pending) lq[q] = Q[base + q];
+        for (int q = t; q < sp.cnt; q += kRowBlock) {
+            l.u[q] = U[sp.base + q];
+            l.p[q] = P[sp.base + q];
+            if (want_q) l.q[q] = Q[sp.base + q];
         }
     }
-    __syncthreads();
+}
 
+// U and P of the block back to HBM from LDS.
+template <typename T, int KB>
+__device__ __forceinline__ void row_stage_out(const GraphView<T> &gv, const RowSpan &sp, const RowLds<T> &l, int t)
+{
+    constexpr int VE = 16 / sizeof(T);
+    constexpr int VPT = (KB * kRowBlock / VE + kRowBlock - 1) / kRowBlock;
+    constexpr int VPTP = (KB * kRowBlock / 2 + kRowBlock - 1) / kRowBlock;
+    T *__restrict__ U = gv.U;
+    double *__restrict__ P = gv.P;
+    if (sp.full) {
+        const int nvec = sp.cnt / VE, nvecp = sp.cnt / 2;
+        v4u *gu = reinterpret_cast<v4u *>(U + sp.base);
+        v4u *gp = reinterpret_cast<v4u *>(P + sp.base);
+#pragma unroll
+        for (int m = 0; m < VPT; ++m) {
+            const int v = t + m * kRowBlock;
+            if (v < nvec) __builtin_nontemporal_store(reinterpret_cast<const v4u *>(l.u)[v], gu + v);
+        }
+#pragma unroll
+        for (int m = 0; m < VPTP; ++m) {
+            const int v = t + m * kRowBlock;
+            if (v < nvecp) __builtin_nontemporal_store(reinterpret_cast<const v4u *>(l.p)[v], gp + v);
+        }
+    } else {
+        for (int q = t; q < sp.cnt; q += kRowBlock) {
+            U[sp.base + q] = l.u[q];
+            P[sp.base + q] = l.p[q];
+        }
+    }
+}
+
+// Per-iteration values every row needs (read once from the control block).
+struct RowStep {
+    int32_t active, pending;
+    double alpha;
+    SolveParams sp;
+};
+
+// One row i: the pending update U, P <- (1-a)(U, P) + a (e_s_prev, q) (q = row i of
+// Q_{k-1}), then, when the iteration is evaluated, the gradient (eq. gradgl_vv2g), the GLMO
+// vertex (Section 4, stored to s_cur) and the row's partials.  ur / pr: the row in LDS.
+template <typename T, typename ST, int KB>
+__device__ __forceinline__ void row_one(const GraphView<T> &gv, const RowStep &st, const int64_t i, T *ur, double *pr,
+                                        const T (&q)[KB], const int32_t sp_i, ST *__restrict__ s_cur,
+                                        double (&acc)[kRowParts], int32_t &s_row)
+{
+    const int32_t K = gv.K;
+    const double alpha = st.alpha;
+    const SolveParams &sp = st.sp;
+    // u is held in the graph's dtype (its values are exactly those of U) and p in FP64
+    T u[KB];
+    double p[KB];
+#pragma unroll
+    for (int c = 0; c < KB; ++c) {
+        u[c] = c < K ? ur[c] : (T)0;
+        p[c] = c < K ? pr[c] : 0.0;
+    }
+    bool binary = true;
+#pragma unroll
+    for (int c = 0; c < KB; ++c)
+        if (c < K && !(u[c] == (T)0 || u[c] == (T)1)) binary = false;
+    if (st.pending) {
+        const double om = 1.0 - alpha;
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+            if (c < K) {
+                p[c] = om * p[c] + alpha * (double)q[c];
+                pr[c] = p[c];
+            }
+        }
+        // a row whose direction d_i = e_{s_i} - u_i is zero (a binary row kept by the
+        // GLMO) is left exactly as it is; every other row moves to (1-a) u + a e_s
+        T at_s = (T)0;
+#pragma unroll
+        for (int c = 0; c < KB; ++c)
+            if (c == sp_i) at_s = u[c];
+        if (!(binary && at_s == (T)1)) {
+#pragma unroll
+            for (int c = 0; c < KB; ++c) {
+                if (c < K) {
+                    u[c] = (T)(om * (double)u[c] + (c == sp_i ? alpha : 0.0));
+                    ur[c] = u[c];
+                }
+            }
+            binary = true;
+#pragma unroll
+            for (int c = 0; c < KB; ++c)
+                if (c < K && !(u[c] == (T)0 || u[c] == (T)1)) binary = false;
+        }
+    }
+    if (!st.active) return;
+    const int32_t y = gv.lab[i];
+    const double om_i = y >= 0 ? sp.omega0 : 0.0;
+    // gradient entry of class c (eq. gradgl_vv2g), formed where it is used
+    auto grad = [&](const int c) -> double {
+        const double uc = (double)u[c];
+        const double uhat = (c == y) ? 1.0 : 0.0;
+        const double fid = om_i != 0.0 ? om_i * (uhat - uc) : 0.0;
+        return p[c] + sp.inv_eps * (1.0 - 2.0 * uc) - fid;
+    };
+    int32_t s = 0;
+    if (binary && sp.lmo == 0) {
+        // the GLMO keeps a binary row: its vertex is the position of its 1
+#pragma unroll
+        for (int c = KB - 1; c >= 0; --c)
+            if (c < K && u[c] == (T)1) s = c;
+    } else {
+        double best = 0.0;
+        int32_t bi = -1;
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+            if (c < K && (sp.lmo == 1 || u[c] != (T)0)) {
+                const double gc = grad(c);
+                if (bi < 0 || gc < best) {
+                    best = gc;
+                    bi = c;
+                }
+            }
+        }
+        s = bi < 0 ? 0 : bi;
+    }
+    s_cur[i] = (ST)s;
+    s_row = s;
+    double gap = 0.0, up = 0.0, dd = 0.0, pen = 0.0, fid = 0.0, ps = 0.0;
+#pragma unroll
+    for (int c = 0; c < KB; ++c) {
+        if (c < K) {
+            const double uc = (double)u[c];
+            const double d = (c == s ? 1.0 : 0.0) - uc;
+            gap -= grad(c) * d;
+            up += uc * p[c];
+            dd += d * d;
+            pen += uc * (1.0 - uc);
+            if (c == s) ps = p[c];
+            if (om_i != 0.0) {
+                const double e = (y == c ? 1.0 : 0.0) - uc;
+                fid += e * e;
+            }
+        }
+    }
+    acc[PART_GAP] = gap;
+    acc[PART_E] = 0.5 * up + sp.inv_eps * pen + 0.5 * (om_i * fid);
+    acc[PART_CURV] = up - 2.0 * ps - 2.0 * sp.inv_eps * dd + om_i * dd;
+    acc[PART_DD] = dd;
+    acc[PART_NB] = binary ? 0.0 : 1.0;
+}
+
+// Vertices of rows 2m, 2m + 1 packed into byte m of s4 (low nibble = even row) for the
+// column-sorted label pass; r0 is a multiple of 256, so row pairs are lane pairs.
+__device__ __forceinline__ void pack_s4(uint8_t *s4, int64_t r0, int rows, int t, int32_t s_row)
+{
+    const int32_t s_next = __shfl_down(s_row, 1);
+    if (t < rows && !(t & 1)) s4[(r0 + t) >> 1] = (uint8_t)(s_row | ((t + 1 < rows ? s_next : 0) << 4));
+}
+
+// Row kernel body: block `tile` of 256 rows, one thread per row.  Partials are stored
+// transposed: row_part[j * nb_row + tile].  Dynamic LDS: kRowBlock * K * (2 sizeof(T) + 8).
+template <typename T, typename ST, int KB>
+__device__ __forceinline__ void row_body(const GraphView<T> &gv, const int tile, const int apply_only)
+{
+    const Ctl *__restrict__ ctl = gv.ctl;
+    RowStep st;
+    st.active = apply_only ? 0 : ctl->active;
+    st.pending = ctl->pending;
+    if (!st.active && !st.pending) return;
+    st.alpha = ctl->alpha;
+    st.sp = ctl->sp;
+    // iteration k writes its vertices to s[k & 1]; the pending update is the one of the
+    // last evaluated iteration
+    const ST *__restrict__ s_prev = reinterpret_cast<const ST *>((ctl->last_eval & 1) ? gv.s1 : gv.s0);
+    ST *__restrict__ s_cur = reinterpret_cast<ST *>((ctl->k & 1) ? gv.s1 : gv.s0);
+    extern __shared__ unsigned char lds_raw[];
+    const RowLds<T> l = row_lds_at<T>(lds_raw, gv.K, true);
+    const int tid = threadIdx.x;
+    const RowSpan sp = row_span(gv.n, gv.K, tile);
+    row_stage_in<T, KB>(gv, sp, l, tid, st.pending != 0); // Q is used when an update is pending
+    __syncthreads();
     double acc[kRowParts];
 #pragma unroll
     for (int j = 0; j < kRowParts; ++j) acc[j] = 0.0;
     int32_t s_row = 0;
-    if (tid < rows) {
-        const int64_t i = r0 + tid;
-        T *ur = lu + tid * K;
-        double *pr = lp + tid * K;
-        double u[KB], p[KB];
+    if (tid < sp.rows) {
+        const int64_t i = sp.r0 + tid;
+        T q[KB];
 #pragma unroll
-        for (int c = 0; c < KB; ++c) {
-            u[c] = c < K ? (double)ur[c] : 0.0;
-            p[c] = c < K ? pr[c] : 0.0;
-        }
-        bool binary = true;
-#pragma unroll
-        for (int c = 0; c < KB; ++c)
-            if (c < K && !(u[c] == 0.0 || u[c] == 1.0)) binary = false;
-        if (pending) {
-            const int32_t sp_i = (int32_t)s_prev[i];
-            const T *qr = lq + tid * K;
-            const double om = 1.0 - alpha;
-#pragma unroll
-            for (int c = 0; c < KB; ++c) {
-                if (c < K) {
-                    p[c] = om * p[c] + alpha * (double)qr[c];
-                    pr[c] = p[c];
-                }
-            }
-            // a row whose direction d_i = e_{s_i} - u_i is zero (a binary row kept by the
-            // GLMO) is left exactly as it is; every other row moves to (1-a) u + a e_s
-            double at_s = 0.0;
-#pragma unroll
-            for (int c = 0; c < KB; ++c)
-                if (c == sp_i) at_s = u[c];
-            if (!(binary && at_s == 1.0)) {
-#pragma unroll
-                for (int c = 0; c < KB; ++c) {
-                    if (c < K) {
-                        u[c] = (double)(T)(om * u[c] + (c == sp_i ? alpha : 0.0));
-                        ur[c] = (T)u[c];
-                    }
-                }
-                binary = true;
-#pragma unroll
-                for (int c = 0; c < KB; ++c)
-                    if (c < K && !(u[c] == 0.0 || u[c] == 1.0)) binary = false;
-            }
-        }
-        if (active) {
-            const int32_t y = lab[i];
-            const double om_i = y >= 0 ? sp.omega0 : 0.0;
-            double g[KB];
-#pragma unroll
-            for (int c = 0; c < KB; ++c) {
-                if (c < K) {
-                    const double uhat = (c == y) ? 1.0 : 0.0;
-                    const double fid = om_i != 0.0 ? om_i * (uhat - u[c]) : 0.0;
-                    g[c] = p[c] + sp.inv_eps * (1.0 - 2.0 * u[c]) - fid;
-                } else {
-                    g[c] = 0.0;
-                }
-            }
-            int32_t s = 0;
-            if (binary && sp.lmo == 0) {
-                // the GLMO keeps a binary row: its vertex is the position of its 1
-#pragma unroll
-                for (int c = KB - 1; c >= 0; --c)
-                    if (c < K && u[c] == 1.0) s = c;
-            } else {
-                double best = 0.0;
-                int32_t bi = -1;
-#pragma unroll
-                for (int c = 0; c < KB; ++c) {
-                    if (c < K && (sp.lmo == 1 || u[c] != 0.0)) {
-                        if (bi < 0 || g[c] < best) {
-                            best = g[c];
-                            bi = c;
-                        }
-                    }
-                }
-                s = bi < 0 ? 0 : bi;
-            }
-            s_cur[i] = (ST)s;
-            s_row = s;
-            double gap = 0.0, up = 0.0, dd = 0.0, pen = 0.0, fid = 0.0, ps = 0.0;
-#pragma unroll
-            for (int c = 0; c < KB; ++c) {
-                if (c < K) {
-                    const double d = (c == s ? 1.0 : 0.0) - u[c];
-                    gap -= g[c] * d;
-                    up += u[c] * p[c];
-                    dd += d * d;
-                    pen += u[c] * (1.0 - u[c]);
-                    if (c == s) ps = p[c];
-                    if (om_i != 0.0) {
-                        const double e = (y == c ? 1.0 : 0.0) - u[c];
-                        fid += e * e;
-                    }
-                }
-            }
-            acc[PART_GAP] = gap;
-            acc[PART_E] = 0.5 * up + sp.inv_eps * pen + 0.5 * (om_i * fid);
-            acc[PART_CURV] = up - 2.0 * ps - 2.0 * sp.inv_eps * dd + om_i * dd;
-            acc[PART_DD] = dd;
-            acc[PART_NB] = binary ? 0.0 : 1.0;
-        }
+        for (int c = 0; c < KB; ++c) q[c] = (st.pending && c < gv.K) ? l.q[tid * gv.K + c] : (T)0;
+        const int32_t sp_i = st.pending ? (int32_t)s_prev[i] : 0;
+        row_one<T, ST, KB>(gv, st, i, l.u + tid * gv.K, l.p + tid * gv.K, q, sp_i, s_cur, acc, s_row);
     }
-    // graphs on the column-sorted label pass also get the vertices packed two per byte
-    // (rows 2m and 2m+1 in the low and high nibble; r0 is even, so pairs are lane pairs)
-    if (KB <= 16 && gv.n_tiles > 0 && active) {
-        const int32_t s_next = __shfl_down(s_row, 1);
-        if (tid < rows && !(tid & 1))
-            gv.s4[(r0 + tid) >> 1] = (uint8_t)(s_row | ((tid + 1 < rows ? s_next : 0) << 4));
-    }
+    if (KB <= 16 && gv.n_tiles > 0 && st.active) pack_s4(gv.s4, sp.r0, sp.rows, tid, s_row);
     __syncthreads();
-    if (pending) {
-        if (full) {
-            const int nvec = cnt / VE, nvecp = cnt / 2;
-            v4u *gu = reinterpret_cast<v4u *>(U + base);
-            v4u *gp = reinterpret_cast<v4u *>(P + base);
-#pragma unroll
-            for (int m = 0; m < VPT; ++m) {
-                const int v = tid + m * kRowBlock;
-                if (v < nvec) __builtin_nontemporal_store(reinterpret_cast<const v4u *>(lu)[v], gu + v);
-            }
-#pragma unroll
-            for (int m = 0; m < VPTP; ++m) {
-                const int v = tid + m * kRowBlock;
-                if (v < nvecp) __builtin_nontemporal_store(reinterpret_cast<const v4u *>(lp)[v], gp + v);
-            }
-        } else {
-            for (int q = tid; q < cnt; q += kRowBlock) {
-                U[base + q] = lu[q];
-                P[base + q] = lp[q];
-            }
-        }
-    }
-    if (!active) return;
-    block_sum_store_strided<kRowParts>(acc, part + tile, gv.nb_row);
+    if (st.pending) row_stage_out<T, KB>(gv, sp, l, tid);
+    if (!st.active) return;
+    block_sum_store_strided<kRowParts>(acc, gv.row_part + tile, gv.nb_row);
 }
 
 // Label pass body (plain): Q = L_s S for the one-hot S given by s (a per-row histogram of
@@ -543,7 +630,7 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
     T *__restrict__ Q = gv.Q;
     const Ctl *__restrict__ ctl = gv.ctl;
     double *__restrict__ part = gv.lab_part;
-    if (!ctl->active) return;
+    if (!ctl->active) return label_inactive(gv, tile);
     const ST *__restrict__ s = (ctl->k & 1) ? s1 : s0;
     __shared__ ST ls[LT];
     __shared__ T lv[LT];
@@ -627,7 +714,8 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
     const int64_t base = r0 * K;
     for (int q = tid; q < cntq; q += kRowBlock) Q[base + q] = lq[q];
     double v[1] = {own};
-    block_sum_store_strided<1>(v, part + tile, gv.nb_row);
+    block_sum_store_strided<1, true>(v, part + tile, gv.nb_row);
+    finish_if_last(gv, gv.row_part, gv.nb_row, gv.lab_part, gv.nb_row);
 }
 
 // Column-sorted label pass body: the same Q = L_s S and per-tile partial as label_body, for
@@ -654,50 +742,38 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
 // (which the column order and the packed labels reduce), and the row walks of phase 2 wait
 // on their values; both keep several loads in flight per thread (16 sorted entries per
 // gather batch, row values in batches of 8).
-template <typename T, typename ST, int KB>
-__device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const int tile)
+// The pieces of the column-sorted pass, shared with the persistent iteration kernel.
+// Step 0: the row kernel's partials of a fixed slice of 256-row blocks, folded into this
+// tile's entry of row_fold, so that the finish reads n_tiles partials instead of nb_row: the
+// first wavefront loads them (lane order) and sorted_finish sums them (a wavefront tree).
+template <typename T>
+__device__ __forceinline__ void sorted_fold_load(const GraphView<T> &gv, const int tile, double (&fold)[kRowParts])
 {
-    static_assert(KB <= 16, "packed labels hold K <= 16");
-    const int32_t K = gv.K;
-    const int32_t *__restrict__ rp = gv.rp;
-    const int32_t *__restrict__ tile_rows = gv.tile_rows;
-    const uint32_t *__restrict__ gword = gv.gword;
-    const int32_t *__restrict__ ci = gv.ci;
-    const T *__restrict__ a = gv.a;
-    const int diag_one = gv.diag_one;
-    const uint8_t *__restrict__ s4 = gv.s4;
-    T *__restrict__ Q = gv.Q;
-    const Ctl *__restrict__ ctl = gv.ctl;
-    double *__restrict__ part = gv.lab_part;
-    if (!ctl->active) return;
-    const ST *__restrict__ s = (ctl->k & 1) ? gv.s1 : gv.s0;
-    extern __shared__ unsigned char lds_raw[];
-    uint8_t *llab = lds_raw; // [entries of the tile]
-    const int tid = threadIdx.x;
-    const int32_t r0 = tile_rows[tile], r1 = tile_rows[tile + 1];
-    const int32_t e0 = rp[r0], e1 = rp[r1];
-    const int E = e1 - e0;
-    const int rows = r1 - r0;
-
-    // 0. the row kernel's partials of a fixed slice of 256-row blocks, folded into this tile's
-    //    entry of row_fold so that the finish reads n_tiles partials instead of nb_row: the
-    //    first wavefront loads them here and sums them (lane order, then a wavefront tree) at
-    //    the end
     const int nbr = gv.nb_row, ntl = gv.n_tiles;
     const int fb0 = (int)((int64_t)tile * nbr / ntl), fb1 = (int)((int64_t)(tile + 1) * nbr / ntl);
-    double fold[kRowParts];
 #pragma unroll
     for (int j = 0; j < kRowParts; ++j) fold[j] = 0.0;
-    if (tid < 64)
-        for (int b = fb0 + tid; b < fb1; b += 64)
+    if (threadIdx.x < 64)
+        for (int b = fb0 + (int)threadIdx.x; b < fb1; b += 64)
 #pragma unroll
             for (int j = 0; j < kRowParts; ++j) fold[j] += gv.row_part[(int64_t)j * nbr + b];
+}
 
-    // 1. gather labels in column order, scatter them to CSR positions in LDS
+// Step 1: the labels of the tile's entries gathered in column order and scattered to their
+// CSR offsets in LDS (llab).  G sorted entries per thread per batch.
+template <typename T, int G>
+__device__ __forceinline__ void sorted_gather(const GraphView<T> &gv, const int tile, uint8_t *llab)
+{
     static_assert(kSortedThreads % kSortedChunk == 0 && kSortedChunk == 64, "a wavefront reads one chunk");
+    const int tid = threadIdx.x;
+    const int32_t r0 = gv.tile_rows[tile], r1 = gv.tile_rows[tile + 1];
+    const int32_t e0 = gv.rp[r0], e1 = gv.rp[r1];
+    const int E = e1 - e0;
+    const uint32_t *__restrict__ gword = gv.gword;
+    const int32_t *__restrict__ ci = gv.ci;
+    const uint8_t *__restrict__ s4 = gv.s4;
     const int32_t *__restrict__ anch = gv.ganch + gv.tile_chunk[tile];
     const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63); // first entry of the wavefront's chunk
-    constexpr int G = 16; // sorted entries per thread per batch (n = 2 M SBM: 4, 8, 16 took 143, 128, 124 us)
     for (int b = 0; b < E; b += G * kSortedThreads) {
         uint32_t ww[G];
         int32_t an[G];
@@ -721,63 +797,66 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
             if (b + tid + m * kSortedThreads < E)
                 llab[ww[m] & kSortedOffsetMask] = (uint8_t)((ss[m] >> ((cc[m] & 1) << 2)) & 15u);
     }
-    __syncthreads();
+}
 
-    // 2. one row at a time per thread: rows r0 + tid + j * kSortedThreads
-    double own = 0.0;
-    for (int r = tid; r < rows; r += kSortedThreads) {
-        const int rb = rp[r0 + r] - e0, re = rp[r0 + r + 1] - e0;
-        double acc[KB];
+// Step 2 for one row (local index r in the tile): the histogram of its neighbours' labels
+// weighted by the stored values, in CSR order, FP64 sums; q receives row r of Q = L_s S
+// rounded to the graph's dtype (the identity's 1 added to the row's own vertex si).  The
+// row's values are loaded in batches of 8, then 4, then singly (a row has about 24 entries
+// on the large SBM: three batches), each batch's loads in flight together.
+template <typename T, int KB>
+__device__ __forceinline__ void sorted_row(const GraphView<T> &gv, const int32_t e0, const int rb, const int re,
+                                           const uint8_t *llab, const int32_t si, T (&q)[KB])
+{
+    const T *__restrict__ a = gv.a;
+    double acc[KB];
 #pragma unroll
-        for (int c = 0; c < KB; ++c) acc[c] = 0.0;
-        // the row's values in batches of 8, then 4, then singly: each batch's loads are in
-        // flight together (a row has about 24 entries on the large SBM: three batches)
-        int p = rb;
-        for (; p + 8 <= re; p += 8) {
-            T v[8];
-            int32_t sj[8];
+    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    int p = rb;
+    for (; p + 8 <= re; p += 8) {
+        T v[8];
+        int32_t sj[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                v[u] = a[e0 + p + u];
-                sj[u] = (int32_t)llab[p + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? (double)v[u] : 0.0;
+        for (int u = 0; u < 8; ++u) {
+            v[u] = a[e0 + p + u];
+            sj[u] = (int32_t)llab[p + u];
         }
-        for (; p + 4 <= re; p += 4) {
-            T v[4];
-            int32_t sj[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                v[u] = a[e0 + p + u];
-                sj[u] = (int32_t)llab[p + u];
-            }
+        for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? (double)v[u] : 0.0;
-        }
-        for (; p < re; ++p) {
-            const double v = (double)a[e0 + p];
-            const int32_t sj = (int32_t)llab[p];
-#pragma unroll
-            for (int c = 0; c < KB; ++c) acc[c] += (c == sj) ? v : 0.0;
-        }
-        const int32_t si = (int32_t)s[r0 + r];
-        T *__restrict__ qr = Q + (int64_t)(r0 + r) * K;
-#pragma unroll
-        for (int c = 0; c < KB; ++c) {
-            if (c < K) {
-                const T v = (T)(acc[c] + ((diag_one && c == si) ? 1.0 : 0.0));
-                qr[c] = v;
-                if (c == si) own += (double)v;
-            }
-        }
+            for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? (double)v[u] : 0.0;
     }
-    // fixed-order block sum (16 waves)
+    for (; p + 4 <= re; p += 4) {
+        T v[4];
+        int32_t sj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = a[e0 + p + u];
+            sj[u] = (int32_t)llab[p + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? (double)v[u] : 0.0;
+    }
+    for (; p < re; ++p) {
+        const double v = (double)a[e0 + p];
+        const int32_t sj = (int32_t)llab[p];
+#pragma unroll
+        for (int c = 0; c < KB; ++c) acc[c] += (c == sj) ? v : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < KB; ++c) q[c] = (T)(acc[c] + ((gv.diag_one && c == si) ? 1.0 : 0.0));
+}
+
+// Step 3: the tile's partial of <S, L_s S> (each thread's sum over its rows, wavefront trees,
+// then the 16 wavefronts in order) to lab_part[tile], and the folded row partials to row_fold.
+template <typename T>
+__device__ __forceinline__ void sorted_finish(const GraphView<T> &gv, const int tile, double own,
+                                              double (&fold)[kRowParts])
+{
     __shared__ double red[kSortedThreads / 64];
+    const int tid = threadIdx.x;
     own = wave_sum(own);
     if ((tid & 63) == 0) red[tid >> 6] = own;
     if (tid < 64) { // the whole first wavefront
@@ -785,119 +864,180 @@ __device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const 
         for (int j = 0; j < kRowParts; ++j) fold[j] = wave_sum(fold[j]);
         if (tid == 0)
 #pragma unroll
-            for (int j = 0; j < kRowParts; ++j) gv.row_fold[(int64_t)j * ntl + tile] = fold[j];
+            for (int j = 0; j < kRowParts; ++j) store_coherent(gv.row_fold + (int64_t)j * gv.n_tiles + tile, fold[j]);
     }
     __syncthreads();
     if (tid == 0) {
         double t = 0.0;
         for (int w = 0; w < kSortedThreads / 64; ++w) t += red[w];
-        part[tile] = t;
+        store_coherent(gv.lab_part + tile, t);
     }
 }
 
-// Finish body: fixed-order reduction of the partials, gap, objective, curvature, step size,
-// stop test and history entry of one graph.  row_part is [kRowParts][nb_row], lab_part is
-// [nb_lab].  One workgroup of kFinishThreads threads per graph.
-__device__ __forceinline__ void finish_body(const double *__restrict__ row_part, int nb_row,
-                                            const double *__restrict__ lab_part, int nb_lab, Ctl *__restrict__ ctl)
+// Column-sorted label pass body: steps 0-3 for tile `tile`; Q rows go to memory.
+template <typename T, typename ST, int KB>
+__device__ __forceinline__ void label_sorted_body(const GraphView<T> &gv, const int tile)
 {
-    if (!ctl->active) {
-        if (threadIdx.x == 0) ctl->pending = 0;
-        return;
+    static_assert(KB <= 16, "packed labels hold K <= 16");
+    const Ctl *__restrict__ ctl = gv.ctl;
+    if (!ctl->active) return label_inactive(gv, tile);
+    const ST *__restrict__ s = (ctl->k & 1) ? gv.s1 : gv.s0;
+    extern __shared__ unsigned char lds_raw[];
+    uint8_t *llab = lds_raw; // [entries of the tile]
+    const int tid = threadIdx.x;
+    const int32_t r0 = gv.tile_rows[tile], r1 = gv.tile_rows[tile + 1];
+    const int32_t e0 = gv.rp[r0];
+    const int rows = r1 - r0;
+    double fold[kRowParts];
+    sorted_fold_load<T>(gv, tile, fold);
+    constexpr int G = 16; // sorted entries per thread per batch (n = 2 M SBM: 4, 8, 16 took 143, 128, 124 us)
+    sorted_gather<T, G>(gv, tile, llab);
+    __syncthreads();
+    // one row at a time per thread: rows r0 + tid + j * kSortedThreads
+    double own = 0.0;
+    for (int r = tid; r < rows; r += kSortedThreads) {
+        const int rb = gv.rp[r0 + r] - e0, re = gv.rp[r0 + r + 1] - e0;
+        const int32_t si = (int32_t)s[r0 + r];
+        T q[KB];
+        sorted_row<T, KB>(gv, e0, rb, re, llab, si, q);
+        T *__restrict__ qr = gv.Q + (int64_t)(r0 + r) * gv.K;
+#pragma unroll
+        for (int c = 0; c < KB; ++c) {
+            if (c < gv.K) {
+                qr[c] = q[c];
+                if (c == si) own += (double)q[c];
+            }
+        }
     }
+    sorted_finish<T>(gv, tile, own, fold);
+    finish_if_last(gv, gv.row_fold, gv.n_tiles, gv.lab_part, gv.n_tiles);
+}
+
+// Finish: fixed-order reduction of the partials, gap, objective, curvature, step size,
+// stop test and history entry of one graph.  row_part is [kRowParts][nb_row], lab_part is
+// [nb_lab].  finish_sums reduces them in the order of kFinishThreads threads (thread v sums
+// partials v, v + 512, ... four at a time; wavefront trees; the eight wavefronts in order),
+// whatever the size of the workgroup running it: a workgroup of 256 threads takes the 512
+// sums two per thread, one of 1024 threads leaves half its threads idle.  Every thread must
+// call it (it holds a barrier); the totals land in t on thread 0.
+__device__ __forceinline__ void finish_sums(const double *row_part, int nb_row, const double *lab_part, int nb_lab,
+                                            double (&t)[kRowParts + 1])
+{
     __shared__ double red[kFinishThreads / 64][kRowParts + 1];
-    double v[kRowParts + 1];
+    const int lane = threadIdx.x & 63;
+    for (int vt = threadIdx.x; vt < kFinishThreads; vt += blockDim.x) { // uniform per wavefront
+        double v[kRowParts + 1];
 #pragma unroll
-    for (int j = 0; j <= kRowParts; ++j) v[j] = 0.0;
-    // four block partials per thread and quantity in flight
-    constexpr int CH = 4;
-    for (int b0 = 0; b0 < nb_row; b0 += CH * kFinishThreads) {
-        double x[kRowParts][CH];
+        for (int j = 0; j <= kRowParts; ++j) v[j] = 0.0;
+        // four block partials per thread and quantity in flight
+        constexpr int CH = 4;
+        for (int b0 = 0; b0 < nb_row; b0 += CH * kFinishThreads) {
+            double x[kRowParts][CH];
 #pragma unroll
-        for (int j = 0; j < kRowParts; ++j)
+            for (int j = 0; j < kRowParts; ++j)
 #pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int b = b0 + threadIdx.x + c * kFinishThreads;
-                x[j][c] = b < nb_row ? row_part[(int64_t)j * nb_row + b] : 0.0;
+                for (int c = 0; c < CH; ++c) {
+                    const int b = b0 + vt + c * kFinishThreads;
+                    x[j][c] = b < nb_row ? load_coherent(row_part + (int64_t)j * nb_row + b) : 0.0;
+                }
+#pragma unroll
+            for (int j = 0; j < kRowParts; ++j)
+#pragma unroll
+                for (int c = 0; c < CH; ++c) v[j] += x[j][c];
+        }
+        for (int b0 = 0; b0 < nb_lab; b0 += 4 * kFinishThreads) {
+            double x[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int b = b0 + vt + c * kFinishThreads;
+                x[c] = b < nb_lab ? load_coherent(lab_part + b) : 0.0;
             }
 #pragma unroll
-        for (int j = 0; j < kRowParts; ++j)
-#pragma unroll
-            for (int c = 0; c < CH; ++c) v[j] += x[j][c];
-    }
-    for (int b0 = 0; b0 < nb_lab; b0 += 4 * kFinishThreads) {
-        double x[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int b = b0 + threadIdx.x + c * kFinishThreads;
-            x[c] = b < nb_lab ? lab_part[b] : 0.0;
+            for (int c = 0; c < 4; ++c) v[kRowParts] += x[c];
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[kRowParts] += x[c];
+        for (int j = 0; j <= kRowParts; ++j) v[j] = wave_sum(v[j]);
+        if (lane == 0)
+#pragma unroll
+            for (int j = 0; j <= kRowParts; ++j) red[vt >> 6][j] = v[j];
     }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j <= kRowParts; ++j) v[j] = wave_sum(v[j]);
-    if (lane == 0)
-#pragma unroll
-        for (int j = 0; j <= kRowParts; ++j) red[wid][j] = v[j];
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    double t[kRowParts + 1];
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int j = 0; j <= kRowParts; ++j) {
-        double s = 0.0;
-        for (int w = 0; w < kFinishThreads / 64; ++w) s += red[w][j];
-        t[j] = s;
-    }
-    const SolveParams sp = ctl->sp;
-    double *hist = ctl->hist;
-    const int hist_stride = ctl->hist_stride;
-    const int k = ctl->k;
-    ctl->last_eval = k;
-    const double g = t[PART_GAP];
-    const double E = t[PART_E];
+        for (int j = 0; j <= kRowParts; ++j) {
+            double x = 0.0;
+            for (int w = 0; w < kFinishThreads / 64; ++w) x += red[w][j];
+            t[j] = x;
+        }
+}
+
+// The decision of iteration k from the totals: g_k, E(U_k), q_k, the step size and whether
+// a step is taken (no step: g_k <= tol, or a NaN).
+struct Decision {
+    double g, E, q, alpha;
+    bool step;
+    int32_t stop_reason; // when no step: 1 tol, 2 numeric
+};
+
+__device__ __forceinline__ Decision finish_decide(const double (&t)[kRowParts + 1], const SolveParams &sp,
+                                                  int32_t one_shot)
+{
+    Decision d;
+    d.g = t[PART_GAP];
+    d.E = t[PART_E];
     // q = <D, L D> - (2/eps)||D||^2 + sum omega_i ||d_i||^2 with
     // <D, L D> = <S, L S> - 2 <S, L U> + <U, L U> (L symmetric).  ||D||^2 is exactly 0 iff
     // D = 0, and then q is exactly 0 (the assembled form would leave a rounding residue).
-    const double q = t[PART_DD] == 0.0 ? 0.0 : t[kRowParts] + t[PART_CURV];
-    ctl->gap = g;
-    ctl->E_last = E;
-    double alpha = __builtin_nan("");
-    bool step = true;
-    if (!(g == g) || !(E == E)) {
-        ctl->stop_reason = 2;
-        step = false;
-    } else if (sp.tol >= 0.0 && g <= sp.tol) {
-        ctl->stop_reason = 1;
-        step = false;
+    d.q = t[PART_DD] == 0.0 ? 0.0 : t[kRowParts] + t[PART_CURV];
+    d.alpha = __builtin_nan("");
+    d.step = true;
+    d.stop_reason = 0;
+    if (!(d.g == d.g) || !(d.E == d.E)) {
+        d.stop_reason = 2;
+        d.step = false;
+    } else if (sp.tol >= 0.0 && d.g <= sp.tol) {
+        d.stop_reason = 1;
+        d.step = false;
     }
-    if (step) {
-        if (ctl->one_shot) {
-            alpha = 1.0;
+    if (d.step) {
+        if (one_shot) {
+            d.alpha = 1.0;
         } else if (sp.ls == 0) {
-            alpha = 1.0;
+            double alpha = 1.0;
             for (int j = 0; j <= 1074; ++j) {
-                const double dec = alpha * g - 0.5 * alpha * alpha * q;
-                if (dec >= sp.gamma * alpha * g) break;
+                const double dec = alpha * d.g - 0.5 * alpha * alpha * d.q;
+                if (dec >= sp.gamma * alpha * d.g) break;
                 alpha *= sp.delta;
             }
+            d.alpha = alpha;
         } else if (sp.ls == 1) {
-            alpha = q <= 0.0 ? 1.0 : fmin(1.0, g / q);
+            d.alpha = d.q <= 0.0 ? 1.0 : fmin(1.0, d.g / d.q);
         } else {
-            alpha = fmin(1.0, g / (sp.lipschitz * t[PART_DD]));
+            d.alpha = fmin(1.0, d.g / (sp.lipschitz * t[PART_DD]));
         }
     }
+    return d;
+}
+
+// The control block and history after the decision of iteration k (one thread).
+__device__ __forceinline__ void finish_commit(Ctl *ctl, const int k, const Decision &d, const double nonbinary)
+{
+    double *hist = ctl->hist;
+    const int hist_stride = ctl->hist_stride;
+    ctl->last_eval = k;
+    ctl->gap = d.g;
+    ctl->E_last = d.E;
+    if (!d.step) ctl->stop_reason = d.stop_reason;
     if (hist) {
-        hist[0 * hist_stride + k] = E;
-        hist[1 * hist_stride + k] = g;
-        hist[2 * hist_stride + k] = step ? q : __builtin_nan("");
-        hist[3 * hist_stride + k] = alpha;
-        hist[4 * hist_stride + k] = t[PART_NB];
+        hist[0 * hist_stride + k] = d.E;
+        hist[1 * hist_stride + k] = d.g;
+        hist[2 * hist_stride + k] = d.step ? d.q : __builtin_nan("");
+        hist[3 * hist_stride + k] = d.alpha;
+        hist[4 * hist_stride + k] = nonbinary;
     }
-    if (step) {
-        ctl->alpha = alpha;
-        ctl->alpha_last = alpha;
+    if (d.step) {
+        ctl->alpha = d.alpha;
+        ctl->alpha_last = d.alpha;
         ctl->pending = 1;
         ctl->iters = k + 1;
         ctl->k = k + 1;
@@ -908,6 +1048,45 @@ __device__ __forceinline__ void finish_body(const double *__restrict__ row_part,
         ctl->active = 0;
         ctl->iters = k;
     }
+}
+
+// The finish folded into a label pass: every workgroup of the graph's pass, once its partials
+// are in memory, takes a ticket; the one that takes the last ticket (all partials of the
+// iteration written) makes the finish of the iteration and resets the counter for the next.
+// The label-pass partials are written through to memory (store_coherent) by the thread that
+// takes the ticket, which waits for its stores to complete first; the finish reads every
+// partial from memory (load_coherent), past the caches of its XCD, so the partials of
+// workgroups on other XCDs are seen without a cache-wide fence.  (The row kernel's partials
+// come from an earlier launch.)  Every thread of the workgroup must call it.  The result does
+// not depend on which workgroup is last.
+template <typename T>
+__device__ __forceinline__ void finish_if_last(const GraphView<T> &gv, const double *row_part, int nb_row,
+                                               const double *lab_part, int nb_lab)
+{
+    __shared__ int last;
+    __syncthreads(); // the workgroup's partials are written
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_s_waitcnt(0); // this thread's partial stores have completed
+        const unsigned int ticket = atomicAdd(gv.ticket, 1u);
+        last = ticket + 1u == (unsigned int)gv.n_lab_blocks;
+    }
+    __syncthreads();
+    if (!last) return;
+    double t[kRowParts + 1];
+    finish_sums(row_part, nb_row, lab_part, nb_lab, t);
+    if (threadIdx.x != 0) return;
+    Ctl *ctl = gv.ctl;
+    const Decision d = finish_decide(t, ctl->sp, ctl->one_shot);
+    finish_commit(ctl, ctl->k, d, t[PART_NB]);
+    *gv.ticket = 0u;
+}
+
+// A label pass of an iteration that is not evaluated (the solve has stopped): the update of
+// the last evaluated iteration has just been made by the row kernel, so nothing is pending.
+template <typename T>
+__device__ __forceinline__ void label_inactive(const GraphView<T> &gv, const int tile)
+{
+    if (tile == 0 && threadIdx.x == 0) gv.ctl->pending = 0;
 }
 
 // U_0 = Uhat (labelled rows one-hot, others 1/K; Section 5.1), or a copy of U0, for the rows
@@ -932,112 +1111,106 @@ __device__ __forceinline__ void init_body(const GraphView<T> &gv, const T *__res
     }
 }
 
-// Row i of L U for the rows of tile `tile` (one row per thread, acc in FP64).  L is I + A
-// (kind W: A the stored scaled values, the identity implicit) or A itself (kind L).  The
-// tile's column indices and values are staged through LDS with coalesced loads; each
-// thread then sums its row in CSR order, with the identity's term u_i taken at the
-// diagonal's place in that order (where a self-loop's entry a_ii stands, as (1 + a_ii) u_i;
-// else before the first larger column), the order of a CSR loop over the explicit operator.
-// UN neighbour rows are loaded before they are summed, so that UN gathers are in flight per
-// thread.  The result depends on nothing but the row.  K <= KB.
+// Row i of L U for the rows of tile `tile` (kRowBlock consecutive rows), FP64 sums.  L is
+// I + A (kind W: A the stored scaled values, the identity implicit) or A itself (kind L).
+// kSpmmLanes lanes share a row: lane l of the row holds classes l, l + 4, l + 8, l + 12, so
+// that the lanes of a row gather one contiguous run of its neighbour's row of U.  Every lane
+// walks all of the row's entries in CSR order (index and value read by the row's lanes
+// together), with the identity's term u_i taken at the diagonal's place in that order (where
+// a self-loop's entry a_ii stands, as (1 + a_ii) u_i; else before the first larger column):
+// the order of a CSR loop over the explicit operator, so each class's sum rounds as that loop
+// does.  UN entries are loaded before they are summed.  The result depends on nothing but the
+// row.  K <= KB.
+constexpr int kSpmmLanes = 4;
+constexpr int kSpmmThreads = kRowBlock * kSpmmLanes;
+
 template <typename T, int KB>
 __device__ __forceinline__ void spmm_rows(const GraphView<T> &gv, const T *__restrict__ Uin, const int tile,
-                                          double (&acc)[KB])
+                                          double (&acc)[KB / kSpmmLanes])
 {
-    __shared__ int32_t lc[kLabelTile];
-    __shared__ T lv[kLabelTile];
-    constexpr int UN = KB <= 8 ? 4 : 2;
+    constexpr int MC = KB / kSpmmLanes; // classes per lane
+    constexpr int UN = 4;
     const int32_t K = gv.K;
-    const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)tile * kRowBlock;
-    const int rows = (int)min((int64_t)kRowBlock, gv.n - r0);
-    const bool has_row = tid < rows;
-    const int64_t i = r0 + tid;
-    const int32_t b = has_row ? gv.rp[i] : 0, e = has_row ? gv.rp[i + 1] : 0;
-    const int32_t t_begin = gv.rp[r0], t_end = gv.rp[r0 + rows];
-    const T *__restrict__ ui = Uin + (has_row ? i : 0) * K;
-    bool diag_due = gv.diag_one != 0; // the identity's term is still to be added
+    const int l = threadIdx.x % kSpmmLanes;
+    const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x / kSpmmLanes;
 #pragma unroll
-    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
-    // one entry (column j, value v, gathered row uj) of the row, in order
-    auto take = [&](const int32_t j, const double v, const T *uj) {
+    for (int m = 0; m < MC; ++m) acc[m] = 0.0;
+    if (i >= gv.n) return;
+    const T *__restrict__ ui = Uin + i * K;
+    bool diag_due = gv.diag_one != 0; // the identity's term is still to be added
+    auto take = [&](const int32_t j, const double v, const T (&uj)[MC]) {
         if (diag_due && j >= (int32_t)i) {
             diag_due = false;
             if (j == (int32_t)i) { // a self-loop: (1 + a_ii) u_i
                 const double w = 1.0 + v;
 #pragma unroll
-                for (int c = 0; c < KB; ++c)
-                    if (c < K) acc[c] += w * (double)uj[c];
+                for (int m = 0; m < MC; ++m) acc[m] += w * (double)uj[m];
                 return;
             }
 #pragma unroll
-            for (int c = 0; c < KB; ++c)
-                if (c < K) acc[c] += (double)ui[c];
+            for (int m = 0; m < MC; ++m) {
+                const int c = l + kSpmmLanes * m;
+                if (c < K) acc[m] += (double)ui[c];
+            }
         }
 #pragma unroll
-        for (int c = 0; c < KB; ++c)
-            if (c < K) acc[c] += v * (double)uj[c];
+        for (int m = 0; m < MC; ++m) acc[m] += v * (double)uj[m];
     };
-    constexpr int PER = kLabelTile / kRowBlock;
-    for (int32_t t0 = t_begin; t0 < t_end; t0 += kLabelTile) {
-        const int cnt = (int)min((int32_t)kLabelTile, t_end - t0);
-        int32_t jj[PER];
-        T vv[PER];
+    const int32_t e0 = gv.rp[i], e1 = gv.rp[i + 1];
+    int32_t e = e0;
+    for (; e + UN <= e1; e += UN) {
+        int32_t j[UN];
+        double v[UN];
+        T uu[UN][MC];
 #pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int q = min(tid + m * kRowBlock, cnt - 1);
-            jj[m] = gv.ci[t0 + q];
-            vv[m] = gv.a[t0 + q];
+        for (int u = 0; u < UN; ++u) {
+            j[u] = gv.ci[e + u];
+            v[u] = (double)gv.a[e + u];
         }
-        __syncthreads(); // the previous sub-tile has been consumed
 #pragma unroll
-        for (int m = 0; m < PER; ++m) {
-            const int q = tid + m * kRowBlock;
-            if (q < cnt) {
-                lc[q] = jj[m];
-                lv[q] = vv[m];
+        for (int u = 0; u < UN; ++u)
+#pragma unroll
+            for (int m = 0; m < MC; ++m) {
+                const int c = l + kSpmmLanes * m;
+                uu[u][m] = c < K ? Uin[(int64_t)j[u] * K + c] : (T)0;
             }
-        }
-        __syncthreads();
-        if (has_row) {
-            const int32_t pb = max(b, t0), pe = min(e, t0 + cnt);
-            int32_t p = pb;
-            for (; p + UN <= pe; p += UN) {
-                int32_t j[UN];
-                T uu[UN][KB];
 #pragma unroll
-                for (int u = 0; u < UN; ++u) {
-                    j[u] = lc[p + u - t0];
-#pragma unroll
-                    for (int c = 0; c < KB; ++c) uu[u][c] = c < K ? Uin[(int64_t)j[u] * K + c] : (T)0;
-                }
-#pragma unroll
-                for (int u = 0; u < UN; ++u) take(j[u], (double)lv[p + u - t0], uu[u]);
-            }
-            for (; p < pe; ++p) {
-                const int32_t j = lc[p - t0];
-                take(j, (double)lv[p - t0], Uin + (int64_t)j * K);
-            }
-        }
+        for (int u = 0; u < UN; ++u) take(j[u], v[u], uu[u]);
     }
-    if (has_row && diag_due) // every column of the row precedes i
+    for (; e < e1; ++e) {
+        const int32_t j = gv.ci[e];
+        T uj[MC];
 #pragma unroll
-        for (int c = 0; c < KB; ++c)
-            if (c < K) acc[c] += (double)ui[c];
+        for (int m = 0; m < MC; ++m) {
+            const int c = l + kSpmmLanes * m;
+            uj[m] = c < K ? Uin[(int64_t)j * K + c] : (T)0;
+        }
+        take(j, (double)gv.a[e], uj);
+    }
+    if (diag_due) // every column of the row precedes i
+#pragma unroll
+        for (int m = 0; m < MC; ++m) {
+            const int c = l + kSpmmLanes * m;
+            if (c < K) acc[m] += (double)ui[c];
+        }
 }
 
-// P = L U for the rows of tile `tile`, stored as PT.
+// P = L U for the rows of tile `tile`, stored as PT.  kSpmmThreads threads.
 template <typename T, int KB, typename PT>
 __device__ __forceinline__ void spmm_body(const GraphView<T> &gv, const T *__restrict__ Uin, PT *__restrict__ Pout,
                                           const int tile)
 {
-    double acc[KB];
+    constexpr int MC = KB / kSpmmLanes;
+    double acc[MC];
     spmm_rows<T, KB>(gv, Uin, tile, acc);
-    const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x;
+    const int l = threadIdx.x % kSpmmLanes;
+    const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x / kSpmmLanes;
     if (i < gv.n)
 #pragma unroll
-        for (int c = 0; c < KB; ++c)
-            if (c < gv.K) Pout[i * gv.K + c] = (PT)acc[c];
+        for (int m = 0; m < MC; ++m) {
+            const int c = l + kSpmmLanes * m;
+            if (c < gv.K) Pout[i * gv.K + c] = (PT)acc[m];
+        }
 }
 
 template <typename T>
@@ -1056,14 +1229,14 @@ static __global__ void __launch_bounds__(kRowBlock) k_init_u_batch(const GraphVi
 }
 
 template <typename T, int KB, typename PT>
-static __global__ void __launch_bounds__(kRowBlock) k_spmm(GraphView<T> gv, const T *__restrict__ Uin, PT *__restrict__ Pout)
+static __global__ void __launch_bounds__(kSpmmThreads) k_spmm(GraphView<T> gv, const T *__restrict__ Uin, PT *__restrict__ Pout)
 {
     spmm_body<T, KB, PT>(gv, Uin, Pout, blockIdx.x);
 }
 
 // batched L_s U_0 -> P at the start of a batched solve
 template <typename T, int KB>
-static __global__ void __launch_bounds__(kRowBlock) k_spmm_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kSpmmThreads) k_spmm_batch(const GraphView<T> *__restrict__ views,
                                                            const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
@@ -1116,31 +1289,28 @@ static __global__ void __launch_bounds__(kSortedThreads) k_label_sorted_batch(co
     label_sorted_body<T, ST, KB>(views[r.graph], r.tile);
 }
 
-static __global__ void __launch_bounds__(kFinishThreads) k_finish(const double *__restrict__ row_part, int nb_row,
-                                                           const double *__restrict__ lab_part, int nb_lab,
-                                                           Ctl *__restrict__ ctl)
-{
-    finish_body(row_part, nb_row, lab_part, nb_lab, ctl);
-}
-
 // Terms of E(U) (eq. gl_vv2) from their definitions for the rows of tile `tile`: row i of
-// P = L U is formed in FP64 (spmm_rows) and used at once, never stored; then <u_i, P_i>,
-// sum u(1-u) and omega_i ||uhat_i - u_i||^2; block sums stored at part[j * stride + tile].
+// P = L U is formed in FP64 (spmm_rows, kSpmmLanes lanes per row) and used at once, never
+// stored; then <u_i, P_i>, sum u(1-u) and omega_i ||uhat_i - u_i||^2; block sums (fixed order:
+// wavefront trees, then wavefronts in order) stored at part[j * stride + tile].
 template <typename T, int KB>
 __device__ __forceinline__ void energy_body(const GraphView<T> &gv, const T *__restrict__ U, double omega0,
                                             double *__restrict__ part, int64_t stride, const int tile)
 {
-    double p[KB];
+    constexpr int MC = KB / kSpmmLanes;
+    double p[MC];
     spmm_rows<T, KB>(gv, U, tile, p);
     double acc[3] = {0.0, 0.0, 0.0};
-    const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x;
+    const int l = threadIdx.x % kSpmmLanes;
+    const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x / kSpmmLanes;
     if (i < gv.n) {
         const int32_t y = gv.lab[i];
 #pragma unroll
-        for (int c = 0; c < KB; ++c) {
+        for (int m = 0; m < MC; ++m) {
+            const int c = l + kSpmmLanes * m;
             if (c < gv.K) {
                 const double u = (double)U[i * gv.K + c];
-                acc[0] += u * p[c];
+                acc[0] += u * p[m];
                 acc[1] += u * (1.0 - u);
                 if (y >= 0) {
                     const double e = (c == y ? 1.0 : 0.0) - u;
@@ -1149,7 +1319,19 @@ __device__ __forceinline__ void energy_body(const GraphView<T> &gv, const T *__r
             }
         }
     }
-    block_sum_store_strided<3>(acc, part + tile, stride);
+    __shared__ double red[kSpmmThreads / 64][3];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[j] = wave_sum(acc[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) red[wid][j] = acc[j];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int w = 0; w < kSpmmThreads / 64; ++w) t += red[w][threadIdx.x];
+        part[threadIdx.x * stride + tile] = t;
+    }
 }
 
 // E = 1/2 <U, L U> + (1/eps) sum u(1-u) + 1/2 sum omega ||uhat - u||^2 from the tile partials.
@@ -1177,7 +1359,7 @@ __device__ __forceinline__ void energy_sum_body(const double *__restrict__ part,
 }
 
 template <typename T, int KB>
-static __global__ void __launch_bounds__(kRowBlock) k_energy(GraphView<T> gv, const T *__restrict__ U, double omega0,
+static __global__ void __launch_bounds__(kSpmmThreads) k_energy(GraphView<T> gv, const T *__restrict__ U, double omega0,
                                                        double *__restrict__ part)
 {
     energy_body<T, KB>(gv, U, omega0, part, gv.nb_row, blockIdx.x);
@@ -1191,7 +1373,7 @@ static __global__ void __launch_bounds__(kFinishThreads) k_energy_sum(const doub
 
 // batched objective of the final iterates: tile partials of E to row_part
 template <typename T, int KB>
-static __global__ void __launch_bounds__(kRowBlock) k_energy_batch(const GraphView<T> *__restrict__ views,
+static __global__ void __launch_bounds__(kSpmmThreads) k_energy_batch(const GraphView<T> *__restrict__ views,
                                                              const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
@@ -1261,17 +1443,6 @@ static __global__ void k_ctl_gather_batch(const GraphView<T> *__restrict__ views
     for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < count; g += gridDim.x * blockDim.x) out[g] = *views[g].ctl;
 }
 
-// one workgroup per graph of the batch
-template <typename T>
-static __global__ void __launch_bounds__(kFinishThreads) k_finish_batch(const GraphView<T> *__restrict__ views)
-{
-    const GraphView<T> &gv = views[blockIdx.x];
-    if (gv.row_fold) // row partials folded by the label pass, one per label-pass block
-        finish_body(gv.row_fold, gv.n_fold, gv.lab_part, gv.n_fold, gv.ctl);
-    else
-        finish_body(gv.row_part, gv.nb_big > 0 ? gv.nb_big : gv.nb_row, gv.lab_part, gv.nb_row, gv.ctl);
-}
-
 // labels_i = lowest-index argmax_c U_ic; s_out = vertex indices of the last GLMO output
 // (-1 when no iteration was evaluated).
 template <typename T, typename ST>
@@ -1316,6 +1487,29 @@ static __global__ void k_max_nonneg(const double *__restrict__ v, int64_t n, uns
         double s = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, red[w]);
         atomicMax(out, (unsigned long long)__double_as_longlong(s));
+    }
+}
+
+// Streaming copy of n16 16-byte vectors (the achievable HBM rate the roofline is compared
+// with): each thread moves CU vectors per step, all loads issued before the stores,
+// non-temporal both ways, grid-stride over the array.
+static __global__ void __launch_bounds__(256) k_stream_copy(const v4u *__restrict__ src, v4u *__restrict__ dst,
+                                                            int64_t n16)
+{
+    constexpr int CU = 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n16; b += stride * CU) {
+        v4u x[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int64_t q = b + u * stride;
+            if (q < n16) x[u] = __builtin_nontemporal_load(src + q);
+        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int64_t q = b + u * stride;
+            if (q < n16) __builtin_nontemporal_store(x[u], dst + q);
+        }
     }
 }
 

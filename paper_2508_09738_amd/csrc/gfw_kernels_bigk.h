@@ -276,7 +276,7 @@ template <typename T>
 __device__ __forceinline__ void label_big_body(const GraphView<T> &gv, const int tile)
 {
     const Ctl *__restrict__ ctl = gv.ctl;
-    if (!ctl->active) return;
+    if (!ctl->active) return label_inactive(gv, tile);
     const uint16_t *__restrict__ s = reinterpret_cast<const uint16_t *>((ctl->k & 1) ? gv.s1 : gv.s0);
     const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x;
     // the row kernel's partials of a fixed slice of its blocks, folded into this block's entry
@@ -308,16 +308,17 @@ __device__ __forceinline__ void label_big_body(const GraphView<T> &gv, const int
         for (int j = 0; j < kRowParts; ++j) fold[j] = wave_sum(fold[j]);
         if (threadIdx.x == 0)
 #pragma unroll
-            for (int j = 0; j < kRowParts; ++j) gv.row_fold[(int64_t)j * nbr + tile] = fold[j];
+            for (int j = 0; j < kRowParts; ++j) store_coherent(gv.row_fold + (int64_t)j * nbr + tile, fold[j]);
     }
     double v[1] = {own};
-    block_sum_store_strided<1>(v, gv.lab_part + tile, gv.nb_row);
+    block_sum_store_strided<1, true>(v, gv.lab_part + tile, gv.nb_row);
+    finish_if_last(gv, gv.row_fold, gv.nb_row, gv.lab_part, gv.nb_row);
 }
 
 // Row i of L U for large K, one wavefront per row, each lane accumulating its classes over
 // the row's entries in CSR order in FP64, with the identity's term at the diagonal's place
-// (the order and arithmetic of spmm_rows).  Four neighbour rows are loaded before they are
-// summed.  `fn(i, acc)` receives each finished row (acc[m] is class lane + 64 m).
+// (the order and arithmetic of spmm_rows).  Four neighbour rows (two for more than four
+// classes per lane) are loaded before they are summed.  `fn(i, acc)` receives each finished row (acc[m] is class lane + 64 m).
 template <typename T, int MC, typename Fn>
 __device__ __forceinline__ void spmm_big_rows(const GraphView<T> &gv, const T *__restrict__ Uin, const int tile,
                                               Fn &&fn)
@@ -353,7 +354,7 @@ __device__ __forceinline__ void spmm_big_rows(const GraphView<T> &gv, const T *_
         };
         const int32_t e0 = gv.rp[i], e1 = gv.rp[i + 1];
         int32_t e = e0;
-        constexpr int UN = 4;
+        constexpr int UN = MC <= 4 ? 4 : 2;
         for (; e + UN <= e1; e += UN) {
             int32_t j[UN];
             T uu[UN][MC];

@@ -30,7 +30,7 @@ EXPORTED = [
     "gfw_context_create", "gfw_context_destroy", "gfw_graph_create", "gfw_graph_destroy", "gfw_graph_footprint",
     "gfw_solve", "gfw_solve_batched", "gfw_objective", "gfw_spmm", "gfw_server_create", "gfw_server_submit",
     "gfw_server_poll", "gfw_server_destroy", "gfw_trace_enable", "gfw_trace_reset", "gfw_trace_get",
-    "gfw_graph_tune", "gfw_graph_query", "gfw_objective_noalloc",
+    "gfw_graph_tune", "gfw_graph_query", "gfw_objective_noalloc", "gfw_copy_bandwidth",
 ]
 TUNE_LABEL_PATH, TUNE_LABEL_PLAIN_NS, TUNE_LABEL_SORTED_NS, TUNE_SORTED_WIDE_CHUNKS = 0, 1, 2, 3
 LABEL_PATH_AUTO, LABEL_PATH_PLAIN, LABEL_PATH_SORTED, LABEL_PATH_MEASURED = 0, 1, 2, 3
@@ -93,6 +93,7 @@ def lib():
         L.gfw_objective.argtypes = [p, p, C.POINTER(Params), p, C.POINTER(C.c_double), p]
         L.gfw_spmm.argtypes = [p, p, p, p, p]
         L.gfw_objective_noalloc.argtypes = [p, p, C.POINTER(Params), p, p, p]
+        L.gfw_copy_bandwidth.argtypes = [p, C.c_size_t, C.c_int32, C.POINTER(C.c_double)]
         L.gfw_server_create.argtypes = [p, C.c_size_t, C.c_int32, C.POINTER(p)]
         L.gfw_server_submit.argtypes = [p, C.POINTER(Problem), C.POINTER(Params), C.POINTER(C.c_uint64)]
         L.gfw_server_poll.argtypes = [p, C.c_uint64, C.c_int, p, p, C.POINTER(Stats)]
@@ -358,6 +359,13 @@ def objective_noalloc(ctx: Context, g: Graph, prm: Params, U, E_dev, stream=None
     the stream, with no allocation and no synchronisation."""
     check(lib().gfw_objective_noalloc(ctx.handle, g.handle, C.byref(prm), U.data_ptr(), E_dev.data_ptr(),
                                       _stream(stream)))
+
+
+def copy_bandwidth(ctx: Context, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """gfw_copy_bandwidth: GB/s (read + write) of the library's streaming copy kernel."""
+    v = C.c_double()
+    check(lib().gfw_copy_bandwidth(ctx.handle, int(nbytes), int(reps), C.byref(v)))
+    return v.value
 
 
 def spmm(ctx: Context, g: Graph, U, stream=None):

@@ -102,11 +102,13 @@ def serve_request(seed: int, i: int, sides=(128, 256, 512, 1024), Ks=(3, 4, 6), 
     return Problem(g, idx, lab, K, "f32", 50.0, 1000.0, 300, 1e-6, f"serve[{i}]")
 
 
-def serve_pool(seed: int, sides=(128, 256, 512, 1024), Ks=(3, 4, 6)) -> list:
-    """One request of every (side, K) pair: drawing uniformly from this pool is drawing side
-    and K uniformly and independently, as the serving mix asks."""
-    return [serve_request(seed, j * len(sides) + i, side=sd, K=k)
-            for j, k in enumerate(Ks) for i, sd in enumerate(sides)]
+def serve_pool(seed: int, sides=(128, 256, 512, 1024), Ks=(3, 4, 6), copies: int = 1) -> list:
+    """`copies` requests of every (side, K) pair, each its own synthetic image and scribbles:
+    drawing uniformly from this pool is drawing side and K uniformly and independently, as the
+    serving mix asks."""
+    pairs = [(sd, k) for k in Ks for sd in sides]
+    return [serve_request(seed, c * len(pairs) + j, side=sd, K=k)
+            for c in range(copies) for j, (sd, k) in enumerate(pairs)]
 
 
 def lfr_many_classes(seed: int = 5, n: int = 100_000, K: int = 585, avg_degree: float = 5.0, mu: float = 0.2,
