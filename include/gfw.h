@@ -168,6 +168,43 @@ GFW_API gfw_status_t gfw_context_destroy(gfw_context_t ctx);
  * checked.  The caller's arrays may be freed when the call returns.
  */
 GFW_API gfw_status_t gfw_graph_create(gfw_context_t ctx, const gfw_problem_t *p, gfw_graph_t *out, void *stream);
+
+/*
+ * Fully connected Gaussian graphs, the image setting of Section 5.1: node i carries a
+ * feature vector x_i in R^d (e.g. the colour of a pixel) and w_ij = exp(-||x_i - x_j||^2 /
+ * (2 sigma^2)) for i != j (the Gaussian similarity of Section 1; no self-loops), so W is
+ * dense.  The library never forms it: each product with L_s = I - D^{-1/2} W D^{-1/2} sums
+ * the weights from the features (the paper uses an NFFT-based fast summation for these
+ * products, Section 5.1).  method: GFW_GAUSS_EXACT forms every weight (O(n^2 K) per product,
+ * FP64 sums, 1 <= d <= 8); GFW_GAUSS_GRID, for 1 <= d <= 3, gathers the points onto a grid of
+ * spacing 0.4 sigma with a Gaussian window, convolves the grid with a Gaussian and
+ * interpolates back, the widths chosen so that the composite kernel is the Gaussian of width
+ * sigma (relative error of each weight about 1e-8; O((n + cells) 20^d K) per product, the
+ * cells spanning the range of the features in steps of 0.4 sigma; GFW_E_UNSUPPORTED when the
+ * grid would exceed 2^28 / K cells), and makes a node whose degree is at most 1e-6 isolated;
+ * GFW_GAUSS_AUTO takes the grid when d <= 3 and its estimated work is below n^2, else the
+ * exact sums.  The graph is then used by
+ * gfw_solve, gfw_objective, gfw_objective_noalloc and gfw_spmm like any other (K <= 16);
+ * gfw_solve_batched and the server return GFW_E_UNSUPPORTED for it.  features: n x d of dtype,
+ * row-major, finite (GFW_E_GRAPH otherwise); sigma > 0 and finite.  Labels as in
+ * gfw_problem_t.  All arrays are HOST or DEVICE as `location` says; copied at creation.
+ */
+typedef enum { GFW_GAUSS_AUTO = 0, GFW_GAUSS_EXACT = 1, GFW_GAUSS_GRID = 2 } gfw_gauss_method_t;
+typedef struct {
+    int64_t n;                   /* nodes, >= 1                                               */
+    int32_t d;                   /* feature dimensions                                        */
+    int32_t K;                   /* classes, 2 <= K <= 16                                     */
+    gfw_dtype_t dtype;           /* dtype of the features and of U                            */
+    gfw_location_t location;
+    const void *features;        /* n x d                                                     */
+    double sigma;                /* width of the Gaussian similarity                          */
+    gfw_gauss_method_t method;
+    int64_t n_labelled;
+    const int32_t *labelled_idx; /* int32[n_labelled], distinct, in [0, n)                    */
+    const int32_t *labels;       /* int32[n_labelled], in [0, K)                              */
+} gfw_gaussian_problem_t;
+GFW_API gfw_status_t gfw_graph_create_gaussian(gfw_context_t ctx, const gfw_gaussian_problem_t *p, gfw_graph_t *out,
+                                       void *stream);
 GFW_API gfw_status_t gfw_graph_destroy(gfw_graph_t g);
 /* Device bytes held by a graph and by one solve on it (workspace). */
 GFW_API gfw_status_t gfw_graph_footprint(gfw_graph_t g, size_t *graph_bytes, size_t *solve_bytes);

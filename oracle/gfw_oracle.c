@@ -63,6 +63,59 @@ int orc_degrees(int64_t n, const int64_t *rp, const int32_t *ci, const double *w
 }
 
 /*
+ * Fully connected Gaussian graph (the Gaussian similarity of Section 1 on every pair, the
+ * image setting of Section 5.1), evaluated from the features x (n x d, row-major) without
+ * storing W: w_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)) for i != j, w_ii = 0.
+ */
+static double gauss_w(const double *x, int64_t d, int64_t i, int64_t j, double sigma)
+{
+    double r2 = 0.0;
+    for (int64_t q = 0; q < d; ++q) {
+        const double df = x[i * d + q] - x[j * d + q];
+        r2 += df * df;
+    }
+    return exp(-r2 / (2.0 * sigma * sigma));
+}
+
+/* Degrees d_i = sum_{j != i} w_ij of the fully connected Gaussian graph (j increasing). */
+int orc_gaussian_degrees(int64_t n, int64_t d, const double *x, double sigma, double *deg)
+{
+    ROW_LOOP
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i) s += gauss_w(x, d, i, j, sigma);
+        deg[i] = s;
+    }
+    return 0;
+}
+
+/*
+ * Rows rows[0..m) of L_s U for the fully connected Gaussian graph, given its degrees:
+ * (L_s U)_i = U_i - d_i^{-1/2} sum_{j != i} w_ij d_j^{-1/2} U_j (j increasing; a node of
+ * degree 0 has d^{-1/2} = 0).  U is n x K, out is m x K.
+ */
+int orc_gaussian_rows(int64_t n, int64_t d, const double *x, double sigma, const double *deg, int32_t K,
+                      const double *U, int64_t m, const int64_t *rows, double *out)
+{
+    ROW_LOOP
+    for (int64_t r = 0; r < m; ++r) {
+        const int64_t i = rows[r];
+        const double di = deg[i] > 0.0 ? 1.0 / sqrt(deg[i]) : 0.0;
+        double *o = out + r * K;
+        for (int32_t c = 0; c < K; ++c) o[c] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dj = deg[j] > 0.0 ? 1.0 / sqrt(deg[j]) : 0.0;
+            const double w = gauss_w(x, d, i, j, sigma) * dj;
+            for (int32_t c = 0; c < K; ++c) o[c] += w * U[j * K + c];
+        }
+        for (int32_t c = 0; c < K; ++c) o[c] = U[i * K + c] - di * o[c];
+    }
+    return 0;
+}
+
+/*
  * Symmetric normalised Laplacian L_s = I - D^{-1/2} W D^{-1/2} as an explicit CSR
  * matrix whose pattern is that of W plus the diagonal (inserted in sorted position
  * when W has no self-loop on that row).  Output buffers must hold nnz(W) + n

@@ -32,6 +32,9 @@ typedef struct {
 } orc_stats_t;
 
 int orc_degrees(int64_t n, const int64_t *rp, const int32_t *ci, const double *w, double *d);
+int orc_gaussian_degrees(int64_t n, int64_t d, const double *x, double sigma, double *deg);
+int orc_gaussian_rows(int64_t n, int64_t d, const double *x, double sigma, const double *deg, int32_t K,
+                      const double *U, int64_t m, const int64_t *rows, double *out);
 int64_t orc_build_sym_laplacian(int64_t n, const int64_t *rp, const int32_t *ci, const double *w,
                                 int64_t *lrp, int32_t *lci, double *lv);
 int orc_spmm(int64_t n, int32_t K, const int64_t *rp, const int32_t *ci, const double *v,

@@ -74,6 +74,8 @@ def lib(parallel: bool = False):
         L.orc_lmo.argtypes = [C.c_int64, C.c_int32, p, p, C.c_int, p]
         L.orc_solve.argtypes = [C.c_int64, C.c_int32, p, p, p, p, p, C.POINTER(_Params), p, p,
                                 C.POINTER(_Stats), p, p, p]
+        L.orc_gaussian_degrees.argtypes = [C.c_int64, C.c_int64, p, C.c_double, p]
+        L.orc_gaussian_rows.argtypes = [C.c_int64, C.c_int64, p, C.c_double, p, C.c_int32, p, C.c_int64, p, p]
         L.orc_threads.restype = C.c_int
         L.orc_threads.argtypes = []
         _libs[path] = L
@@ -137,6 +139,58 @@ def operator_for(graph, kind: str = "W") -> Operator:
     if kind == "W":
         return sym_laplacian(graph.indptr, graph.indices, graph.data)
     return Operator(graph.indptr, graph.indices, graph.data)
+
+
+def gaussian_weights(features, sigma: float):
+    """The fully connected Gaussian graph of the image setting (Section 5.1) with the
+    Gaussian similarity of Section 1 on every pair: w_ij = exp(-||x_i - x_j||^2 / (2 sigma^2))
+    for i != j, no self-loop.  Returns the CSR (indptr, indices, data) of W holding every
+    off-diagonal entry (entries that underflow are kept as zeros).  Dense: small n only."""
+    x = _f64(features)
+    if x.ndim == 1:
+        x = x[:, None]
+    n = x.shape[0]
+    diff = x[:, None, :] - x[None, :, :]
+    r2 = np.sum(diff * diff, axis=2)
+    W = np.exp(-r2 / (2.0 * sigma * sigma))
+    off = ~np.eye(n, dtype=bool)
+    indptr = np.arange(n + 1, dtype=np.int64) * (n - 1)
+    indices = np.nonzero(off)[1].astype(np.int32)
+    return indptr, indices, W[off]
+
+
+def gaussian_degrees(features, sigma: float, parallel: bool = True) -> np.ndarray:
+    """Degrees d_i = sum_{j != i} w_ij of the fully connected Gaussian graph (the C oracle's
+    loop over every pair; the OpenMP build splits the rows only, so it returns the serial
+    build's degrees bit for bit)."""
+    x = _f64(features)
+    if x.ndim == 1:
+        x = x[:, None]
+    x = np.ascontiguousarray(x)
+    n, d = x.shape
+    deg = np.zeros(n)
+    lib(parallel).orc_gaussian_degrees(n, d, _p(x), float(sigma), _p(deg))
+    return deg
+
+
+def gaussian_laplacian_rows(features, sigma: float, U, rows, deg=None, parallel: bool = True) -> np.ndarray:
+    """Rows `rows` of L_s U for the fully connected Gaussian graph at any n, from the
+    definitions of Section 1 (L_s = I - D^{-1/2} W D^{-1/2}, a node of degree 0 has
+    d^{-1/2} = 0), every weight formed where it is used.  deg: the degrees, if known."""
+    x = _f64(features)
+    if x.ndim == 1:
+        x = x[:, None]
+    x = np.ascontiguousarray(x)
+    U = np.ascontiguousarray(_f64(U))
+    n, d = x.shape
+    K = U.shape[1]
+    if deg is None:
+        deg = gaussian_degrees(x, sigma, parallel)
+    deg = np.ascontiguousarray(_f64(deg))
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.zeros((rows.shape[0], K))
+    lib(parallel).orc_gaussian_rows(n, d, _p(x), float(sigma), _p(deg), K, _p(U), rows.shape[0], _p(rows), _p(out))
+    return out
 
 
 def spmm(L: Operator, U: np.ndarray) -> np.ndarray:

@@ -232,6 +232,7 @@ static Shape shape_for(int64_t n, int32_t K)
 void free_graph(gfw_graph_s *g)
 {
     if (!g) return;
+    gauss_free(g->gauss);
     dfree(g->row_ptr);
     dfree(g->col);
     dfree(g->vals);
@@ -800,6 +801,8 @@ static void launch_label(const gfw_graph_s *g, hipStream_t st)
 {
     if constexpr (KMAX > 16) {
         k_label_big<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g));
+    } else if (g->gauss) {
+        gauss_label<T>(g, st);
     } else if (g->label_path == 1) {
         launch_label_sorted<T>(g, st);
     } else {
@@ -890,6 +893,7 @@ static gfw_status_t measure_label_paths(gfw_graph_s *g, hipStream_t st)
 template <typename T, typename PT>
 static void spmm_any(const gfw_graph_s *g, const T *U, PT *P, hipStream_t st)
 {
+    if (g->gauss) return gauss_spmm<T, PT>(g, U, P, st);
     switch (g->shape.kmax) {
 #define GFW_SPMM_CASE(KM) \
     case KM: launch_spmm<T, KM, PT>(g, U, P, st); break;
@@ -1077,6 +1081,7 @@ static gfw_status_t solve_dispatch(gfw_graph_s *g, const gfw_params_t *prm, void
 template <typename T>
 static int energy_partials(const gfw_graph_s *g, const T *U, double omega0, double *part, hipStream_t st)
 {
+    if (g->gauss) return gauss_energy<T>(g, U, omega0, part, st);
     const GraphView<T> v = make_view<T>(g);
     switch (g->shape.kmax) {
     case 4: k_energy<T, 4><<<g->shape.nb_row, kSpmmThreads, 0, st>>>(v, U, omega0, part); return g->shape.nb_row;
@@ -1234,6 +1239,7 @@ gfw_status_t gfw_graph_tune(gfw_graph_t g, gfw_tune_t key, int64_t value)
     if (!g) return fail(GFW_E_INVALID_ARG, "graph is NULL");
     if (key != GFW_TUNE_LABEL_PATH) return fail(GFW_E_INVALID_ARG, "unknown tuning key %d", (int)key);
     if (value < 0 || value > 3) return fail(GFW_E_INVALID_ARG, "label path must be 0, 1, 2 or 3");
+    if (g->gauss) return fail(GFW_E_UNSUPPORTED, "a Gaussian graph has one label pass");
     GFW_HIP_TRY(hipSetDevice(g->ctx->device));
     const int before = g->label_path;
     gfw_status_t s = choose_label_path(g, (int)value, nullptr);

@@ -731,6 +731,7 @@ gfw_status_t gfw_solve_batched(gfw_context_t ctx, int32_t count, const gfw_graph
         if (!graphs[i]) return fail(GFW_E_INVALID_ARG, "graph %d is NULL", i);
         if (graphs[i]->ctx != ctx) return fail(GFW_E_INVALID_ARG, "graph %d belongs to another context", i);
         if (graphs[i]->dtype != graphs[0]->dtype) return fail(GFW_E_UNSUPPORTED, "a batch must share one dtype");
+        if (graphs[i]->gauss) return fail(GFW_E_UNSUPPORTED, "graph %d is a Gaussian graph: solve it alone", i);
         ps[(size_t)i] = shared_params ? prm : prm + i;
         gfw_status_t s = check_params(ps[(size_t)i], graphs[i]->K);
         if (s != GFW_OK) return s;

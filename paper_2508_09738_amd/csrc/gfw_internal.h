@@ -106,6 +106,10 @@ void trace_end(gfw_context_s *c, int kernel, hipEvent_t a, hipStream_t st);
 gfw_status_t trace_flush(gfw_context_s *c, hipStream_t st);
 } // namespace gfw
 
+namespace gfw {
+struct GaussGraph; // the operator of a fully connected Gaussian graph (gfw_gauss.hip)
+} // namespace gfw
+
 struct gfw_graph_s {
     gfw_context_s *ctx = nullptr;
     int64_t n = 0, nnz = 0;
@@ -131,6 +135,7 @@ struct gfw_graph_s {
     double locality = 0.0;        // mean distinct 128-node label lines per 64 consecutive entries
     float label_us[2] = {0, 0};   // measured launch times of the plain and sorted passes (0: not measured)
     int diag_one = 1;           // 1: operator is I + A (kind W); 0: operator is A (kind L)
+    gfw::GaussGraph *gauss = nullptr; // fully connected Gaussian graph (no CSR), else null
     gfw::Shape shape;
     gfw::Workspace ws;
     size_t graph_bytes = 0, solve_bytes = 0;
@@ -168,6 +173,19 @@ inline int64_t fold_blocks(const gfw_graph_s *g)
     if (g->K > 16) return g->shape.nb_row;
     return g->label_path == 1 ? g->n_tiles : 0;
 }
+
+// Fully connected Gaussian graphs (gfw_gauss.hip): creation, release, and the three places
+// where the iteration uses the operator: P = L_s U (stored as PT), the label pass Q = L_s S
+// with its finish, and the block partials of E(U) (returns their count per quantity).
+gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t *p, gfw_graph_s **out,
+                                hipStream_t st);
+void gauss_free(GaussGraph *gg);
+template <typename T, typename PT>
+void gauss_spmm(const gfw_graph_s *g, const T *U, PT *P, hipStream_t st);
+template <typename T>
+void gauss_label(const gfw_graph_s *g, hipStream_t st);
+template <typename T>
+int gauss_energy(const gfw_graph_s *g, const T *U, double omega0, double *part, hipStream_t st);
 
 template <typename T>
 GraphView<T> make_view(const gfw_graph_s *g)

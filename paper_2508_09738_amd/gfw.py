@@ -30,8 +30,9 @@ EXPORTED = [
     "gfw_context_create", "gfw_context_destroy", "gfw_graph_create", "gfw_graph_destroy", "gfw_graph_footprint",
     "gfw_solve", "gfw_solve_batched", "gfw_objective", "gfw_spmm", "gfw_server_create", "gfw_server_submit",
     "gfw_server_poll", "gfw_server_destroy", "gfw_trace_enable", "gfw_trace_reset", "gfw_trace_get",
-    "gfw_graph_tune", "gfw_graph_query", "gfw_objective_noalloc", "gfw_copy_bandwidth",
+    "gfw_graph_tune", "gfw_graph_query", "gfw_objective_noalloc", "gfw_copy_bandwidth", "gfw_graph_create_gaussian",
 ]
+GAUSS_AUTO, GAUSS_EXACT, GAUSS_GRID = 0, 1, 2
 TUNE_LABEL_PATH, TUNE_LABEL_PLAIN_NS, TUNE_LABEL_SORTED_NS, TUNE_SORTED_WIDE_CHUNKS = 0, 1, 2, 3
 LABEL_PATH_AUTO, LABEL_PATH_PLAIN, LABEL_PATH_SORTED, LABEL_PATH_MEASURED = 0, 1, 2, 3
 KERNEL_ROW, KERNEL_LABEL, KERNEL_FINISH, KERNEL_SPMM = 0, 1, 2, 3
@@ -47,6 +48,12 @@ class Problem(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("K", C.c_int32), ("kind", C.c_int), ("dtype", C.c_int),
                 ("location", C.c_int), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("vals", C.c_void_p),
                 ("n_labelled", C.c_int64), ("labelled_idx", C.c_void_p), ("labels", C.c_void_p)]
+
+
+class GaussianProblem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("K", C.c_int32), ("dtype", C.c_int), ("location", C.c_int),
+                ("features", C.c_void_p), ("sigma", C.c_double), ("method", C.c_int), ("n_labelled", C.c_int64),
+                ("labelled_idx", C.c_void_p), ("labels", C.c_void_p)]
 
 
 class Params(C.Structure):
@@ -86,6 +93,7 @@ def lib():
         L.gfw_context_create.argtypes = [C.POINTER(p), C.c_int]
         L.gfw_context_destroy.argtypes = [p]
         L.gfw_graph_create.argtypes = [p, C.POINTER(Problem), C.POINTER(p), p]
+        L.gfw_graph_create_gaussian.argtypes = [p, C.POINTER(GaussianProblem), C.POINTER(p), p]
         L.gfw_graph_destroy.argtypes = [p]
         L.gfw_graph_footprint.argtypes = [p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.gfw_solve.argtypes = [p, p, C.POINTER(Params), p, p, p, C.POINTER(Stats), p, p]
@@ -191,6 +199,33 @@ class Graph:
     def from_host(cls, ctx, n, K, indptr, indices, data, labelled_idx, labels, dtype=F32, kind=GRAPH_W, stream=None):
         pb, keep = host_problem(n, K, indptr, indices, data, labelled_idx, labels, dtype, kind)
         return cls(ctx, pb, keep, stream)
+
+    @classmethod
+    def gaussian(cls, ctx, features, K, sigma, labelled_idx, labels, dtype=F32, method=GAUSS_AUTO, stream=None):
+        """Fully connected Gaussian graph (gfw_graph_create_gaussian) on features (n x d): a
+        host array, or a torch tensor on the device of the graph's dtype."""
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.handle = C.c_void_p()
+        if hasattr(features, "data_ptr") and getattr(features, "is_cuda", False):
+            n, d = int(features.shape[0]), int(features.shape[1])
+            pb = GaussianProblem(n, d, K, dtype, DEVICE, features.data_ptr(), float(sigma), method,
+                                 int(labelled_idx.shape[0]), labelled_idx.data_ptr(), labels.data_ptr())
+            keep = [features, labelled_idx, labels]
+        else:
+            x = np.ascontiguousarray(features, np.float32 if dtype == F32 else np.float64)
+            if x.ndim != 2:
+                raise ValueError("features must be n x d")
+            n, d = x.shape
+            li = np.ascontiguousarray(labelled_idx, np.int32)
+            lb = np.ascontiguousarray(labels, np.int32)
+            pb = GaussianProblem(n, d, K, dtype, HOST, x.ctypes.data, float(sigma), method, int(li.shape[0]),
+                                 li.ctypes.data, lb.ctypes.data)
+            keep = [x, li, lb]
+        self.n, self.K, self.dtype, self.nnz = int(n), int(K), int(dtype), 0
+        check(lib().gfw_graph_create_gaussian(ctx.handle, C.byref(pb), C.byref(self.handle), _stream(stream)))
+        del keep
+        return self
 
     def tune(self, key: int, value: int) -> None:
         check(lib().gfw_graph_tune(self.handle, key, value))

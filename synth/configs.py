@@ -18,6 +18,11 @@ every input is generated from a seed.
   serve_mix    8-neighbour image grids with sides in {128, 256, 512, 1024}, K in {3, 4, 6},
                2% scribble labels; FP32; 300 iterations.
 
+  color_image  fully connected Gaussian graph over the RGB colours of a synthetic K-region
+               image (a stand-in for the paper's colour images, Table 2: n 16.5k-38.2k,
+               K 4-8), sigma = 0.1 on colours in [0, 1]; 2% scribble labels; the paper's
+               image setting eps = 0.1, omega0 = 1e5, one-shot.
+
 Networks use eps = 50 and omega0 = 1000, the values the paper selects for networks in its
 parameter study (Section 5.2).  The image-like grids also use eps = 50: the paper's image
 setting (eps = 0.1, omega0 = 1e5) is its one-shot regime on a fully connected graph, which
@@ -138,3 +143,35 @@ def grown_sbm(seed: int = 6, n_old: int = 3000, n_new: int = 150, K: int = 3, av
     old = Problem(go, idx, lab, K, "f64", 50.0, 1000.0, 300, 1e-6, "grown_sbm(old)")
     full = Problem(g, idx, lab, K, "f64", 50.0, 1000.0, 300, 1e-6, "grown_sbm(full)")
     return old, full
+
+
+@dataclasses.dataclass
+class ImageProblem:
+    """A fully connected Gaussian graph given by node features (no stored edges)."""
+    features: np.ndarray      # float64[n, d]
+    sigma: float
+    labelled_idx: np.ndarray  # int32, sorted
+    labels: np.ndarray        # int32 in [0, K)
+    K: int
+    truth: np.ndarray         # int32[n]
+    dtype: str = "f64"
+    eps: float = 0.1
+    omega0: float = 1e5
+    max_iter: int = 300
+    tol: float = 1e-6
+    one_shot: bool = True
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return self.features.shape[0]
+
+
+def color_image(seed: int = 7, H: int = 196, W: int = 195, K: int = 4, sigma: float = 0.1, frac: float = 0.02,
+                dtype: str = "f64") -> ImageProblem:
+    """The image workload: a synthetic H x W colour image of K regions (196 x 195 = 38,220
+    pixels, K = 4: the size of the largest image of Table 2), its pixels the nodes of a fully
+    connected Gaussian graph on their colours, scribbles on 2% of the pixels."""
+    feats, truth = graphs.color_image(H, W, K, seed)
+    idx, lab = graphs.scribble_labels(truth, H, W, K, frac, seed, stroke_len=8)
+    return ImageProblem(feats, sigma, idx, lab, K, truth, dtype, name=f"color_image({H}x{W},K={K})")

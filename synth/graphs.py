@@ -255,6 +255,27 @@ def region_image(H: int, W: int, K: int, seed: int, noise: float = 0.05) -> tupl
     return img, region.reshape(-1)
 
 
+def color_image(H: int, W: int, K: int, seed: int, noise: float = 0.1, min_sep: float = 0.25) -> tuple:
+    """Synthetic K-region colour image: Voronoi cells of K random seed points, each region one
+    RGB colour drawn in [0.1, 0.9]^3 (redrawn until every pair is min_sep apart), plus
+    Gaussian noise of standard deviation `noise` per channel.  Returns (features float64
+    [H*W, 3], the RGB of each pixel in row-major order, truth int32[H*W])."""
+    rg = rng_for(seed, 6)
+    pts = rg.random((K, 2)) * np.array([H, W])
+    yy, xx = np.mgrid[0:H, 0:W]
+    d2 = (yy[..., None] - pts[:, 0]) ** 2 + (xx[..., None] - pts[:, 1]) ** 2
+    region = np.argmin(d2, axis=2).astype(np.int32).reshape(-1)
+    cols = np.zeros((K, 3))
+    for c in range(K):
+        for _ in range(1000):
+            cand = 0.1 + 0.8 * rg.random(3)
+            if c == 0 or np.min(np.linalg.norm(cols[:c] - cand, axis=1)) >= min_sep:
+                break
+        cols[c] = cand
+    feats = cols[region] + noise * rg.standard_normal((H * W, 3))
+    return feats, region
+
+
 def grid_graph(H: int, W: int, img: np.ndarray, neighbours: int = 4, sigma_i: float = 0.1) -> tuple:
     """4- or 8-neighbour pixel grid with w = exp(-(I_p - I_q)^2 / (2 sigma_i^2))."""
     n = H * W

@@ -1,0 +1,237 @@
+"""Fully connected Gaussian graphs (gfw_graph_create_gaussian): the image setting, where every
+pair of pixels is joined with the Gaussian similarity of their colours and the library sums
+the weights from the features instead of storing them.
+
+Against the oracle's plain definition (every weight formed, FP64): the products with L_s by
+the exact method and by the grid method (within the grid's error bound), lockstep iterations
+of GFW and of the one-shot method, free-running solves in the paper's image setting, the
+image of the largest size of the paper's Table 2 on sampled rows, the objective, and the error
+and edge cases."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_09738_amd import gfw
+from synth import configs, graphs
+
+from gpu_helpers import ctx, lockstep, np_of, say, torch_u
+
+pytestmark = pytest.mark.gpu
+
+# |W V - (W V)_grid| on the inputs below is a few 1e-10 (window and convolution cut at six
+# widths, grid spacing 0.4 sigma); the bound asserted on L_s U entries, which are O(1):
+GRID_ABS = 1e-7
+
+
+def _simplex_rows(n, K, seed):
+    rg = np.random.default_rng(seed)
+    U = rg.random((n, K)) ** 2
+    U[rg.random((n, K)) < 0.3] = 0.0
+    U[np.arange(n), rg.integers(0, K, n)] += 1e-3
+    return U / U.sum(axis=1, keepdims=True)
+
+
+def _dense_L(x, sigma):
+    return O.sym_laplacian(*O.gaussian_weights(x, sigma))
+
+
+def _as_problem(ip):
+    """The oracle's CSR of the fully connected graph of an ImageProblem, as a Problem."""
+    indptr, indices, data = O.gaussian_weights(ip.features, ip.sigma)
+    g = graphs.Graph(ip.n, ip.K, indptr, indices, data, ip.truth)
+    return configs.Problem(g, ip.labelled_idx, ip.labels, ip.K, ip.dtype, ip.eps, ip.omega0, ip.max_iter, ip.tol)
+
+
+def _gpu(ip, dtype, method):
+    return gfw.Graph.gaussian(ctx(), ip.features, ip.K, ip.sigma, ip.labelled_idx, ip.labels, dtype, method)
+
+
+@pytest.mark.parametrize("dtype", [gfw.F64, gfw.F32])
+@pytest.mark.parametrize("d,n,K", [(1, 700, 3), (3, 1537, 5), (5, 900, 16)])
+def test_spmm_exact(dtype, d, n, K):
+    say(f"[gpu] gauss spmm exact dtype={dtype} d={d} n={n} K={K}")
+    rg = np.random.default_rng(d * 7 + n)
+    x = 0.3 * rg.standard_normal((n, d))
+    sigma = 0.25
+    U = _simplex_rows(n, K, n)
+    g = gfw.Graph.gaussian(ctx(), x, K, sigma, np.zeros(0, np.int32), np.zeros(0, np.int32), dtype, gfw.GAUSS_EXACT)
+    Ut = torch_u(U, dtype)
+    xin = x.astype(np.float32).astype(np.float64) if dtype == gfw.F32 else x
+    ref = O.spmm(_dense_L(xin, sigma), np_of(Ut).astype(np.float64))
+    got = np_of(gfw.spmm(ctx(), g, Ut)).astype(np.float64)
+    tol = 1e-12 if dtype == gfw.F64 else 2e-6  # FP64 sums; FP32: the stored result's rounding
+    assert np.abs(got - ref).max() <= tol
+
+
+@pytest.mark.parametrize("d,n,sigma", [(1, 3001, 0.02), (2, 2500, 0.06), (3, 2200, 0.1)])
+def test_spmm_grid_within_its_error_bound(d, n, sigma):
+    say(f"[gpu] gauss spmm grid d={d} n={n} sigma={sigma}")
+    rg = np.random.default_rng(d)
+    x = rg.random((n, d))
+    K = 4
+    U = _simplex_rows(n, K, d + 100)
+    g = gfw.Graph.gaussian(ctx(), x, K, sigma, np.zeros(0, np.int32), np.zeros(0, np.int32), gfw.F64, gfw.GAUSS_GRID)
+    got = np_of(gfw.spmm(ctx(), g, torch_u(U, gfw.F64)))
+    ref = O.spmm(_dense_L(x, sigma), U)
+    err = np.abs(got - ref).max()
+    say(f"[gpu]   grid error {err:.3e}")
+    assert err <= GRID_ABS
+    # the exact method on the same graph agrees with the oracle to rounding
+    ge = gfw.Graph.gaussian(ctx(), x, K, sigma, np.zeros(0, np.int32), np.zeros(0, np.int32), gfw.F64,
+                            gfw.GAUSS_EXACT)
+    assert np.abs(np_of(gfw.spmm(ctx(), ge, torch_u(U, gfw.F64))) - ref).max() <= 1e-12
+
+
+def _small_image(K=4, seed=11, H=36, W=41):
+    return configs.color_image(seed, H, W, K)
+
+
+@pytest.mark.parametrize("method,osfw", [(gfw.GAUSS_EXACT, False), (gfw.GAUSS_EXACT, True),
+                                         (gfw.GAUSS_GRID, False), (gfw.GAUSS_GRID, True)])
+def test_lockstep(method, osfw):
+    ip = _small_image()
+    prob = _as_problem(ip)
+    if not osfw:  # GFW with Armijo steps: the network setting's eps, so that it takes many steps
+        prob.eps, prob.omega0 = 50.0, 1000.0
+    G = _gpu(ip, gfw.F64, method)
+    exact = method == gfw.GAUSS_EXACT
+    # exact: the same weights as the oracle up to rounding (the weights are summed in another
+    # order); grid: within the grid's error
+    op_rel = 1e-12 if exact else 1e-6
+    ks = [0] if osfw else [0, 1, 3, 7, 15]  # the one-shot method stops after its first step
+    lockstep(prob, gfw.F64, ks, G=G, band=op_rel, op_rel=op_rel, u_tol=1e-12 if exact else 1e-6, osfw=osfw,
+             max_diff_frac=0.0 if exact else 1e-3, label=f"gauss method={method} osfw={osfw}")
+
+
+@pytest.mark.parametrize("method", [gfw.GAUSS_EXACT, gfw.GAUSS_GRID])
+@pytest.mark.parametrize("dtype", [gfw.F64, gfw.F32])
+def test_free_running_image_setting(method, dtype):
+    """The paper's image setting (eps = 0.1, omega0 = 1e5, one-shot) to its stop."""
+    ip = _small_image(K=5, seed=12)
+    say(f"[gpu] gauss free-running method={method} dtype={dtype} n={ip.n}")
+    prob = _as_problem(ip)
+    ro = O.solve_problem(prob, osfw=True)
+    G = _gpu(ip, dtype, method)
+    rg_ = gfw.solve(ctx(), G, gfw.params(eps=ip.eps, omega0=ip.omega0, max_iter=ip.max_iter, tol=ip.tol,
+                                         one_shot=True))
+    lab = np_of(rg_["labels"])
+    agree = float(np.mean(lab == ro["labels"]))
+    acc_g, acc_o = float(np.mean(lab == ip.truth)), float(np.mean(ro["labels"] == ip.truth))
+    say(f"[gpu]   iters gpu {rg_['iters']} oracle {ro['iters']}; agreement {agree:.5f}; accuracy gpu {acc_g:.4f} "
+        f"oracle {acc_o:.4f}; E gpu {rg_['objective']:.10e} oracle {ro['objective']:.10e}")
+    # rows whose classes are within rounding of a tie may go either way
+    assert agree >= (0.999 if (method == gfw.GAUSS_EXACT and dtype == gfw.F64) else 0.99)
+    assert acc_g >= acc_o - 0.01
+    e_rel = 1e-6 if (method == gfw.GAUSS_EXACT and dtype == gfw.F64) else 1e-4
+    assert rg_["objective"] == pytest.approx(ro["objective"], rel=e_rel)
+    # every row of the result is a vertex of the simplex (one-shot steps are whole)
+    U = np_of(rg_["U"]).astype(np.float64)
+    assert np.all((U == 0.0) | (U == 1.0)) and np.all(U.sum(1) == 1.0)
+
+
+def test_objective_and_noalloc():
+    import torch
+
+    ip = _small_image(K=3, seed=13, H=30, W=30)
+    prob = _as_problem(ip)
+    L = O.operator_for(prob.graph)
+    Uhat, omega = O.fidelity(ip.n, ip.K, ip.labelled_idx, ip.labels, ip.omega0)
+    U = _simplex_rows(ip.n, ip.K, 5)
+    ref = O.objective(L, U, Uhat, omega, ip.eps)
+    for method in (gfw.GAUSS_EXACT, gfw.GAUSS_GRID):
+        G = _gpu(ip, gfw.F64, method)
+        prm = gfw.params(eps=ip.eps, omega0=ip.omega0)
+        Ut = torch_u(U, gfw.F64)
+        E = gfw.objective(ctx(), G, prm, Ut)
+        E_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gfw.objective_noalloc(ctx(), G, prm, Ut, E_dev)
+        torch.cuda.synchronize()
+        rel = 1e-12 if method == gfw.GAUSS_EXACT else 1e-6
+        assert E == pytest.approx(ref, rel=rel)
+        assert float(E_dev.item()) == E
+
+
+def test_full_size_image_sampled_rows():
+    """196 x 195 = 38,220 pixels, K = 4 (the largest image of Table 2): the solve through the
+    automatically chosen method and through the grid, P = L_s U at the result checked on
+    sampled rows against the oracle's row evaluation, and the segmentation against the truth."""
+    ip = configs.color_image()
+    say(f"[gpu] gauss full size n={ip.n} K={ip.K}")
+    rg = np.random.default_rng(0)
+    unl = np.setdiff1d(np.arange(ip.n), ip.labelled_idx)
+    rows = np.sort(rg.choice(unl, 48, replace=False))
+    # the one-shot method's first step is its result: an unlabelled row takes the class of the
+    # smallest entry of its row of L_s U_0 (the other gradient terms are the same in every
+    # class at U_0 = 1/K; the lowest index among ties)
+    U0, _ = O.fidelity(ip.n, ip.K, ip.labelled_idx, ip.labels, ip.omega0)
+    deg = O.gaussian_degrees(ip.features, ip.sigma)
+    P0 = O.gaussian_laplacian_rows(ip.features, ip.sigma, U0, rows, deg=deg)
+    two = np.sort(P0, axis=1)[:, :2]
+    clear = (two[:, 1] - two[:, 0]) > 1e-9 * np.abs(P0).max(axis=1)
+    for method, tol in ((gfw.GAUSS_AUTO, 1e-11), (gfw.GAUSS_GRID, GRID_ABS)):
+        G = _gpu(ip, gfw.F64, method)
+        r = gfw.solve(ctx(), G, gfw.params(eps=ip.eps, omega0=ip.omega0, max_iter=ip.max_iter, tol=ip.tol,
+                                           one_shot=True))
+        lab = np_of(r["labels"])
+        acc = float(np.mean(lab == ip.truth))
+        say(f"[gpu]   method={method}: iters {r['iters']}, accuracy {acc:.4f}")
+        assert r["iters"] == 1 and np.all(lab[ip.labelled_idx] == ip.labels)
+        assert np.all(lab[rows][clear] == np.argmin(P0, axis=1)[clear])
+        assert acc >= 0.9
+        U = np_of(r["U"])
+        P = np_of(gfw.spmm(ctx(), G, r["U"]))
+        ref = O.gaussian_laplacian_rows(ip.features, ip.sigma, U, rows, deg=deg)
+        assert np.abs(P[rows] - ref).max() <= tol
+
+
+def test_device_features_and_edge_cases():
+    import torch
+
+    rg = np.random.default_rng(9)
+    x = rg.random((500, 3))
+    idx = np.array([3, 10, 400], np.int32)
+    lab = np.array([0, 1, 2], np.int32)
+    gh = gfw.Graph.gaussian(ctx(), x, 3, 0.2, idx, lab, gfw.F64, gfw.GAUSS_EXACT)
+    gd = gfw.Graph.gaussian(ctx(), torch.tensor(x, device="cuda"), 3, 0.2, torch.tensor(idx, device="cuda"),
+                            torch.tensor(lab, device="cuda"), gfw.F64, gfw.GAUSS_EXACT)
+    U = torch_u(_simplex_rows(500, 3, 1), gfw.F64)
+    assert torch.equal(gfw.spmm(ctx(), gh, U), gfw.spmm(ctx(), gd, U))
+    # one node: no edges, degree 0, L_s = I; the solve keeps the label (or 1/K)
+    g1 = gfw.Graph.gaussian(ctx(), np.zeros((1, 2)), 2, 1.0, np.array([0], np.int32), np.array([1], np.int32), gfw.F64)
+    r = gfw.solve(ctx(), g1, gfw.params(max_iter=5))
+    assert np_of(r["labels"]).tolist() == [1]
+    # duplicated points: weight 1 between them
+    xd = np.repeat(rg.random((40, 2)), 2, axis=0)
+    gdup = gfw.Graph.gaussian(ctx(), xd, 2, 0.3, np.zeros(0, np.int32), np.zeros(0, np.int32), gfw.F64,
+                              gfw.GAUSS_EXACT)
+    Ud = _simplex_rows(80, 2, 2)
+    ref = O.spmm(_dense_L(xd, 0.3), Ud)
+    assert np.abs(np_of(gfw.spmm(ctx(), gdup, torch_u(Ud, gfw.F64))) - ref).max() <= 1e-12
+    # d = 8, the exact method's largest
+    x8 = rg.standard_normal((300, 8))
+    g8 = gfw.Graph.gaussian(ctx(), x8, 2, 2.0, np.zeros(0, np.int32), np.zeros(0, np.int32), gfw.F64)
+    U8 = _simplex_rows(300, 2, 3)
+    assert np.abs(np_of(gfw.spmm(ctx(), g8, torch_u(U8, gfw.F64))) - O.spmm(_dense_L(x8, 2.0), U8)).max() <= 1e-12
+
+    def status(fn):
+        with pytest.raises(gfw.GfwError) as e:
+            fn()
+        return e.value.status
+
+    none = np.zeros(0, np.int32)
+    assert status(lambda: gfw.Graph.gaussian(ctx(), x, 3, 0.0, none, none)) == -1  # sigma <= 0
+    bad = x.copy()
+    bad[7, 1] = np.nan
+    assert status(lambda: gfw.Graph.gaussian(ctx(), bad, 3, 0.2, none, none)) == -2  # non-finite feature
+    assert status(lambda: gfw.Graph.gaussian(ctx(), rg.random((50, 4)), 3, 0.2, none, none, gfw.F64,
+                                             gfw.GAUSS_GRID)) == -6  # grid takes d <= 3
+    assert status(lambda: gfw.Graph.gaussian(ctx(), rg.random((50, 9)), 3, 0.2, none, none)) == -6  # d > 8
+    assert status(lambda: gfw.Graph.gaussian(ctx(), x, 17, 0.2, none, none)) == -6  # K > 16
+    assert status(lambda: gfw.Graph.gaussian(ctx(), x, 3, 0.2, np.array([1, 1], np.int32),
+                                             np.array([0, 1], np.int32))) == -3  # repeated label
+    assert status(lambda: gfw.Graph.gaussian(ctx(), x, 3, 0.2, np.array([1], np.int32),
+                                             np.array([3], np.int32))) == -3  # class out of range
+    assert status(lambda: gfw.Graph.gaussian(ctx(), 1e3 * x, 3, 1e-3, none, none, gfw.F64,
+                                             gfw.GAUSS_GRID)) == -6  # grid too large
+    assert status(lambda: gh.tune(gfw.TUNE_LABEL_PATH, gfw.LABEL_PATH_SORTED)) == -6
+    assert status(lambda: gfw.solve_batched(ctx(), [gh], gfw.params())) == -6

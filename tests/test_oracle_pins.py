@@ -606,3 +606,74 @@ def test_warm_start_moves_only_new_rows():
     np.testing.assert_array_equal(r["s"][:r["iters"], :n_old],
                                   np.broadcast_to(r_old["labels"], (r["iters"], n_old)))
     assert np.all(r["U"][n_old:] != U0[n_old:])  # every new row moved
+
+
+# ---------------------------------------------------------------------------
+# Fully connected Gaussian graphs (Section 1's similarity on every pair; Section 5.1)
+# ---------------------------------------------------------------------------
+
+def test_gaussian_weights_closed_form():
+    # points 0, 1, 3 on a line: squared distances 1, 9, 4
+    ip, ix, w = O.gaussian_weights(np.array([[0.0], [1.0], [3.0]]), 1.0)
+    W = sp.csr_matrix((w, ix, ip), shape=(3, 3)).toarray()
+    e_half, e_2, e_9half = 0.6065306597126334, 0.1353352832366127, 0.011108996538242306  # e^-0.5, e^-2, e^-4.5
+    np.testing.assert_allclose(W, [[0, e_half, e_9half], [e_half, 0, e_2], [e_9half, e_2, 0]], rtol=1e-15)
+    # sigma = 2 divides every exponent by 4 (sigma enters squared)
+    ip, ix, w = O.gaussian_weights(np.array([[0.0], [1.0], [3.0]]), 2.0)
+    W = sp.csr_matrix((w, ix, ip), shape=(3, 3)).toarray()
+    np.testing.assert_allclose(W[0, 1], 0.8824969025845955, rtol=1e-15)  # e^-(1/8)
+    np.testing.assert_allclose(W[0, 2], 0.32465246735834974, rtol=1e-15)  # e^-(9/8)
+    # in the plane the squared distance sums the coordinates: (0,0)-(3,4) is at distance 5
+    ip, ix, w = O.gaussian_weights(np.array([[0.0, 0.0], [3.0, 4.0]]), 5.0)
+    np.testing.assert_allclose(w, [0.6065306597126334] * 2, rtol=1e-15)  # e^-(25/50)
+
+
+def test_gaussian_graph_invariants():
+    rg = np.random.default_rng(3)
+    x = rg.standard_normal((50, 3))
+    ip, ix, w = O.gaussian_weights(x, 0.8)
+    W = sp.csr_matrix((w, ix, ip), shape=(50, 50)).toarray()
+    assert np.all(np.diag(W) == 0.0) and np.all(W[~np.eye(50, dtype=bool)] > 0.0)
+    np.testing.assert_array_equal(W, W.T)
+    # a translation of every point leaves W unchanged; a permutation of the points permutes it
+    ip2, ix2, w2 = O.gaussian_weights(x + np.array([5.0, -2.0, 0.25]), 0.8)
+    np.testing.assert_allclose(sp.csr_matrix((w2, ix2, ip2), shape=(50, 50)).toarray(), W, atol=1e-13)
+    perm = rg.permutation(50)
+    ip3, ix3, w3 = O.gaussian_weights(x[perm], 0.8)
+    np.testing.assert_array_equal(sp.csr_matrix((w3, ix3, ip3), shape=(50, 50)).toarray(), W[np.ix_(perm, perm)])
+    # L_s of the graph: D^{1/2} 1 spans its null space, spectrum in [0, 2]
+    L = O.sym_laplacian(ip, ix, w)
+    v = np.sqrt(W.sum(1))[:, None]
+    np.testing.assert_allclose(O.spmm(L, v), 0.0, atol=1e-13)
+    ev = np.linalg.eigvalsh(L.dense())
+    assert ev.min() > -1e-12 and ev.max() < 2.0 + 1e-12
+
+
+def test_gaussian_constant_features_give_the_complete_graph():
+    # w_ij = 1 for every pair: W = J - I, d = n - 1, L_s = I - (J - I) / (n - 1)
+    n = 7
+    ip, ix, w = O.gaussian_weights(np.full((n, 2), 0.3), 0.1)
+    np.testing.assert_array_equal(w, np.ones(n * (n - 1)))
+    L = O.sym_laplacian(ip, ix, w).dense()
+    ref = np.eye(n) - (np.ones((n, n)) - np.eye(n)) / (n - 1)
+    np.testing.assert_allclose(L, ref, atol=1e-15)
+
+
+def test_gaussian_rows_match_the_dense_operator():
+    # the blocked row evaluation against the C oracle's L_s of the dense CSR, on every row
+    rg = np.random.default_rng(4)
+    x = rg.random((300, 3))
+    U = rg.random((300, 4))
+    ip, ix, w = O.gaussian_weights(x, 0.15)
+    ref = O.spmm(O.sym_laplacian(ip, ix, w), U)
+    for parallel in (False, True):
+        got = O.gaussian_laplacian_rows(x, 0.15, U, np.arange(300), parallel=parallel)
+        np.testing.assert_allclose(got, ref, atol=1e-13)
+    np.testing.assert_array_equal(O.gaussian_degrees(x, 0.15, parallel=False), O.gaussian_degrees(x, 0.15))
+    # far clusters: their weights underflow to 0 and L_s splits into the two blocks
+    x2 = np.concatenate([rg.random((20, 2)), 1e3 + rg.random((20, 2))])
+    ip, ix, w = O.gaussian_weights(x2, 0.5)
+    Ld = O.sym_laplacian(ip, ix, w).dense()
+    assert np.all(Ld[:20, 20:] == 0.0) and np.all(Ld[20:, :20] == 0.0)
+    La = O.sym_laplacian(*O.gaussian_weights(x2[:20], 0.5)).dense()
+    np.testing.assert_allclose(Ld[:20, :20], La, atol=1e-15)
