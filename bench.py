@@ -29,6 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -289,6 +290,123 @@ def bench_many_classes(gfw, ctx, steps: int = 3, n: int = 100_000, K: int = 585)
             "accuracy": round(acc, 4)}
 
 
+# FP64 operations per pair of the exact Gaussian product: the squared distance (3 per
+# dimension), the scaling of the exponent (1), the exponential as compiled (range reduction and
+# polynomial: 14 fused multiply-adds counted as 2 each, and 2 other operations) and the
+# accumulation into the KP padded classes (2 each).
+GAUSS_EXP_FLOPS = 30
+
+
+def gauss_pair_flops(d: int, KP: int) -> int:
+    return 3 * d + 1 + GAUSS_EXP_FLOPS + 2 * KP
+
+
+def bench_image(gfw, ctx, reps: int = 10, cpu: bool = True) -> dict:
+    """The image workload: the fully connected Gaussian graph over the RGB colours of a
+    synthetic 196 x 195 = 38,220-pixel, K = 4 image (the size of the largest image of the
+    paper's Table 2), sigma = 0.1, solved in the paper's image setting (eps = 0.1, omega0 =
+    1e5, one-shot), FP32 iterate.  Per method (exact, grid): the mean duration of one product
+    with L_s (HIP events on the stream it runs on), graph set-up and solve wall times, the
+    accuracy; for the exact product the FP64 ALU roofline.  The oracle's product over every row
+    (its OpenMP build) is timed beside it."""
+    import numpy as np
+    import torch
+
+    from synth import configs
+
+    ip = configs.color_image()
+    n, K, d = ip.n, ip.K, ip.features.shape[1]
+    KP = 4 if K <= 4 else 8 if K <= 8 else 16
+    stream = torch.cuda.current_stream()
+    res = {"workload": f"color_image: fully connected Gaussian graph of a synthetic 196x195 RGB image, n={n}, "
+                       f"K={K}, sigma={ip.sigma}, {len(ip.labelled_idx)} scribbled pixels, eps={ip.eps}, "
+                       f"omega0={ip.omega0:g}, one-shot, FP32 iterate"}
+    for name, method in (("exact", gfw.GAUSS_EXACT), ("grid", gfw.GAUSS_GRID)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G = gfw.Graph.gaussian(ctx, ip.features, K, ip.sigma, ip.labelled_idx, ip.labels, gfw.F32, method)
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        U = torch.rand(n, K, device="cuda")
+        U /= U.sum(dim=1, keepdim=True)
+        gfw.spmm(ctx, G, U, stream)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            gfw.spmm(ctx, G, U, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        prod_ms = ev0.elapsed_time(ev1) / reps
+        prm = gfw.params(eps=ip.eps, omega0=ip.omega0, max_iter=ip.max_iter, tol=ip.tol, one_shot=True)
+        gfw.solve(ctx, G, prm, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = gfw.solve(ctx, G, prm, stream=stream)
+        torch.cuda.synchronize()
+        solve_ms = 1e3 * (time.perf_counter() - t0)
+        acc = float(np.mean(r["labels"].cpu().numpy() == ip.truth))
+        ent = {"product_ms": round(prod_ms, 3), "setup_ms": round(setup_ms, 1), "solve_ms": round(solve_ms, 2),
+               "iterations": r["iters"], "accuracy": round(acc, 4)}
+        if method == gfw.GAUSS_EXACT:
+            pairs = n * (n - 1)
+            fl = gauss_pair_flops(d, KP)
+            achieved = pairs * fl / (prod_ms * 1e-3) / 1e12
+            ent["roofline"] = {"bound": "alu", "kernel": "k_gauss_exact (FP64 vector)",
+                               "flops_per_pair": fl, "pairs_per_product": pairs,
+                               "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                               "pairs_per_s": round(pairs / (prod_ms * 1e-3), 1)}
+        res[name] = ent
+        G.close()
+    # a high-resolution image (1024 x 1024 pixels): where the fast summation is for
+    big = configs.color_image(7, 1024, 1024, K)
+    hres = {"workload": f"color_image 1024x1024: n={big.n}, K={K}, sigma={big.sigma}, one-shot, FP32 iterate"}
+    for name, method, reps_b in (("grid", gfw.GAUSS_GRID, 5), ("exact", gfw.GAUSS_EXACT, 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G = gfw.Graph.gaussian(ctx, big.features, K, big.sigma, big.labelled_idx, big.labels, gfw.F32, method)
+        torch.cuda.synchronize()
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        U = torch.rand(big.n, K, device="cuda")
+        U /= U.sum(dim=1, keepdim=True)
+        gfw.spmm(ctx, G, U, stream)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps_b):
+            gfw.spmm(ctx, G, U, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ent = {"product_ms": round(ev0.elapsed_time(ev1) / reps_b, 2), "setup_ms": round(setup_ms, 1)}
+        if method == gfw.GAUSS_GRID:
+            prm = gfw.params(eps=big.eps, omega0=big.omega0, max_iter=big.max_iter, tol=big.tol, one_shot=True)
+            t0 = time.perf_counter()
+            r = gfw.solve(ctx, G, prm, stream=stream)
+            torch.cuda.synchronize()
+            ent["solve_ms"] = round(1e3 * (time.perf_counter() - t0), 1)
+            ent["accuracy"] = round(float(np.mean(r["labels"].cpu().numpy() == big.truth)), 4)
+        hres[name] = ent
+        G.close()
+        log(f"[bench] image 1024x1024 {name}: {json.dumps(ent)}")
+    res["high_resolution"] = hres
+    if cpu:
+        from oracle import oracle as O
+
+        O.build(force=False)
+        U = np.random.default_rng(0).random((n, K))
+        U /= U.sum(axis=1, keepdims=True)
+        t0 = time.perf_counter()
+        deg = O.gaussian_degrees(ip.features, ip.sigma, parallel=True)
+        t_deg = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.gaussian_laplacian_rows(ip.features, ip.sigma, U, np.arange(n), deg=deg, parallel=True)
+        t_rows = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(1e3 * t_rows, 1), "unit": "ms per product with L_s", "cores":
+                               O.threads(True), "kind": "oracle",
+                               "sample": f"one product over all {n} rows (the degrees, {1e3 * t_deg:.0f} ms, "
+                                         "computed beforehand), FP64, OpenMP build of the oracle"}
+    return res
+
+
 def solve_bytes_per_iteration(n: int, nnz: int, K: int, ubytes: int = 4) -> int:
     """Bytes one iteration of the path moves for a graph (FP32 values and U): the label pass
     (row pointers, index + value per entry, labels read, Q written) and the row kernel (U read
@@ -498,6 +616,7 @@ def main() -> int:
     ap.add_argument("--serve", type=int, default=2000,
                     help="measured requests under load in the serving measurement, after 200 warm-up (0: skip)")
     ap.add_argument("--many-classes", type=int, default=1, help="run the many-classes measurement (0: skip)")
+    ap.add_argument("--image", type=int, default=1, help="run the fully connected image measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run only the 1 GiB calibration copies")
     ap.add_argument("--derive-traffic", metavar="DIR", help="write profiles/traffic.json from counter runs in DIR")
     args = ap.parse_args()
@@ -614,6 +733,9 @@ def main() -> int:
     if args.many_classes:
         extra["many_classes"] = bench_many_classes(gfw, ctx)
         log("[bench] many classes: " + json.dumps(extra["many_classes"]))
+    if args.image:
+        extra["image"] = bench_image(gfw, ctx, cpu=not args.no_cpu)
+        log("[bench] image: " + json.dumps(extra["image"]))
     if args.batch > 0:
         extra["batched"] = bench_batched(gfw, ctx, args.batch)
         log("[bench] batched: " + json.dumps(extra["batched"]))

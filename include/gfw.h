@@ -177,11 +177,13 @@ GFW_API gfw_status_t gfw_graph_create(gfw_context_t ctx, const gfw_problem_t *p,
  * the weights from the features (the paper uses an NFFT-based fast summation for these
  * products, Section 5.1).  method: GFW_GAUSS_EXACT forms every weight (O(n^2 K) per product,
  * FP64 sums, 1 <= d <= 8); GFW_GAUSS_GRID, for 1 <= d <= 3, gathers the points onto a grid of
- * spacing 0.4 sigma with a Gaussian window, convolves the grid with a Gaussian and
+ * spacing sigma / 2 with a Gaussian window, convolves the grid with a Gaussian and
  * interpolates back, the widths chosen so that the composite kernel is the Gaussian of width
- * sigma (relative error of each weight about 1e-8; O((n + cells) 20^d K) per product, the
- * cells spanning the range of the features in steps of 0.4 sigma; GFW_E_UNSUPPORTED when the
- * grid would exceed 2^28 / K cells), and makes a node whose degree is at most 1e-6 isolated;
+ * sigma (windows cut at 5 widths: a relative error of about 1e-7 per product; O((n + cells)
+ * 14^d K) per product, the cells spanning the range of the features in steps of sigma / 2;
+ * GFW_E_UNSUPPORTED when the grid would exceed 2^26 / KP cells, KP = K rounded up to 4, 8 or
+ * 16), and makes a node whose degree
+ * is at most 1e-6 isolated;
  * GFW_GAUSS_AUTO takes the grid when d <= 3 and its estimated work is below n^2, else the
  * exact sums.  The graph is then used by
  * gfw_solve, gfw_objective, gfw_objective_noalloc and gfw_spmm like any other (K <= 16);

@@ -16,14 +16,17 @@ namespace gfw {
 struct GaussGraph {
     int method = GFW_GAUSS_EXACT;
     GaussView view{};
+    int32_t kp = 4;              // padded row stride of V, R and the grids: 4, 8 or 16
     int32_t chunks = 1;          // exact method: chunks of the points summed apart
     int64_t chunk = 0;           // points per chunk
     double *x = nullptr;         // n x d features (FP64)
     double *dinv = nullptr;      // n
     int32_t *cell_start = nullptr, *cell_pts = nullptr, *pt_cell = nullptr;
-    double *V = nullptr, *R = nullptr; // n x K
-    double *Rp = nullptr;        // chunks x n x K (exact method, chunks > 1)
-    double *G0 = nullptr, *G1 = nullptr; // ncells x K (grid method)
+    double *V = nullptr, *R = nullptr; // n x kp
+    double *Rp = nullptr;        // chunks x n x kp (exact method, chunks > 1)
+    double *G0 = nullptr, *G1 = nullptr; // ncells x kp (grid method)
+    double *Gp = nullptr;        // kGridWin x ncells x kp: the gather's slices (grid method)
+    double *xs = nullptr, *Vs = nullptr; // n x d features and n x kp V in binned order (grid method)
 };
 
 void gauss_free(GaussGraph *gg)
@@ -39,51 +42,81 @@ void gauss_free(GaussGraph *gg)
     dfree(gg->Rp);
     dfree(gg->G0);
     dfree(gg->G1);
+    dfree(gg->Gp);
+    dfree(gg->xs);
+    dfree(gg->Vs);
     delete gg;
 }
 
-template <int KB>
-static void apply_w_kb(const GaussGraph &gg, int32_t K, const double *V, double *R, const Ctl *ctl, hipStream_t st)
+template <int D, int KP>
+static void apply_exact(const GaussGraph &gg, const double *V, double *R, const Ctl *ctl, hipStream_t st)
 {
     const GaussView &v = gg.view;
-    const int nb = (int)cdiv(v.n, kRowBlock);
-    if (gg.method == GFW_GAUSS_EXACT) {
-        double *out = gg.chunks > 1 ? gg.Rp : R;
-        k_gauss_exact<KB><<<dim3(nb, gg.chunks), kRowBlock, 0, st>>>(v, K, gg.chunk, V, out, ctl);
-        if (gg.chunks > 1)
-            k_gauss_chunks_sum<<<grid_for(v.n * K, 256, 4096), 256, 0, st>>>(v.n * K, gg.chunks, gg.Rp, R, ctl);
-        return;
-    }
-    const int nc = (int)cdiv(v.ncells, kRowBlock);
-    k_grid_gather<KB><<<nc, kRowBlock, 0, st>>>(v, K, V, gg.G0, ctl);
+    double *out = gg.chunks > 1 ? gg.Rp : R;
+    k_gauss_exact<D, KP><<<dim3((unsigned)cdiv(v.n, kRowBlock), gg.chunks), kRowBlock, 0, st>>>(v, gg.chunk, V, out, ctl);
+    if (gg.chunks > 1)
+        k_gauss_chunks_sum<<<grid_for(v.n * KP, 256, 4096), 256, 0, st>>>(v.n * KP, gg.chunks, gg.Rp, R, ctl);
+}
+
+template <int D, int KP>
+static void apply_grid(const GaussGraph &gg, const double *V, double *R, const Ctl *ctl, hipStream_t st)
+{
+    const GaussView &v = gg.view;
+    const unsigned nc = (unsigned)cdiv(v.ncells, kRowBlock);
+    k_grid_bin_v<KP><<<grid_for(v.n * KP, kRowBlock, 4096), kRowBlock, 0, st>>>(v, V, gg.Vs, ctl);
+    k_grid_gather<D, KP><<<dim3(nc, kGridWin), kRowBlock, 0, st>>>(v, gg.Vs, gg.Gp, ctl);
+    k_gauss_chunks_sum<<<grid_for(v.ncells * KP, 256, 8192), 256, 0, st>>>(v.ncells * KP, kGridWin, gg.Gp, gg.G0, ctl);
     const double *in = gg.G0;
     double *out = gg.G1;
-    for (int q = 0; q < v.d; ++q) {
-        k_grid_conv<KB><<<nc, kRowBlock, 0, st>>>(v, K, q, in, out, ctl);
+    for (int q = 0; q < D; ++q) {
+        k_grid_conv<KP><<<nc, kRowBlock, 0, st>>>(v, q, in, out, ctl);
         double *done = out;
         out = const_cast<double *>(in);
         in = done;
     }
-    k_grid_interp<KB><<<nb, kRowBlock, 0, st>>>(v, K, in, V, R, ctl);
+    k_grid_interp<D, KP><<<(unsigned)cdiv(v.n, kRowBlock), kRowBlock, 0, st>>>(v, in, V, R, ctl);
 }
 
-// R = W V for V n x K (FP64, K <= 16).  ctl: the launches do nothing once the solve has
-// stopped (null: they always run).
-static void apply_w(const GaussGraph &gg, int32_t K, const double *V, double *R, const Ctl *ctl, hipStream_t st)
+template <int KP>
+static void apply_w_kp(const GaussGraph &gg, const double *V, double *R, const Ctl *ctl, hipStream_t st)
 {
-    if (K <= 4) apply_w_kb<4>(gg, K, V, R, ctl, st);
-    else if (K <= 8) apply_w_kb<8>(gg, K, V, R, ctl, st);
-    else apply_w_kb<16>(gg, K, V, R, ctl, st);
+    const GaussView &v = gg.view;
+    if (gg.method == GFW_GAUSS_EXACT) {
+        switch (v.d) {
+        case 1: apply_exact<1, KP>(gg, V, R, ctl, st); break;
+        case 2: apply_exact<2, KP>(gg, V, R, ctl, st); break;
+        case 3: apply_exact<3, KP>(gg, V, R, ctl, st); break;
+        default: apply_exact<0, KP>(gg, V, R, ctl, st); break;
+        }
+        return;
+    }
+    switch (v.d) {
+    case 1: apply_grid<1, KP>(gg, V, R, ctl, st); break;
+    case 2: apply_grid<2, KP>(gg, V, R, ctl, st); break;
+    default: apply_grid<3, KP>(gg, V, R, ctl, st); break;
+    }
+}
+
+// R = W V for V n x KP (FP64, KP = 1 or the graph's padded class count).  ctl: the launches
+// do nothing once the solve has stopped (null: they always run).
+static void apply_w(const GaussGraph &gg, int32_t KP, const double *V, double *R, const Ctl *ctl, hipStream_t st)
+{
+    switch (KP) {
+    case 1: apply_w_kp<1>(gg, V, R, ctl, st); break;
+    case 4: apply_w_kp<4>(gg, V, R, ctl, st); break;
+    case 8: apply_w_kp<8>(gg, V, R, ctl, st); break;
+    default: apply_w_kp<16>(gg, V, R, ctl, st); break;
+    }
 }
 
 template <typename T, typename PT>
 void gauss_spmm(const gfw_graph_s *g, const T *U, PT *P, hipStream_t st)
 {
     const GaussGraph &gg = *g->gauss;
-    const int64_t nK = g->n * g->K;
-    k_gauss_scale_u<T><<<grid_for(nK, kRowBlock, 4096), kRowBlock, 0, st>>>(g->n, g->K, gg.dinv, U, gg.V);
-    apply_w(gg, g->K, gg.V, gg.R, nullptr, st);
-    k_gauss_p<T, PT><<<grid_for(nK, kRowBlock, 4096), kRowBlock, 0, st>>>(g->n, g->K, gg.dinv, U, gg.R, P);
+    const int32_t KP = gg.kp;
+    k_gauss_scale_u<T><<<grid_for(g->n * KP, kRowBlock, 4096), kRowBlock, 0, st>>>(g->n, g->K, KP, gg.dinv, U, gg.V);
+    apply_w(gg, KP, gg.V, gg.R, nullptr, st);
+    k_gauss_p<T, PT><<<grid_for(g->n * g->K, kRowBlock, 4096), kRowBlock, 0, st>>>(g->n, g->K, KP, gg.dinv, U, gg.R, P);
 }
 
 template <typename T>
@@ -91,21 +124,21 @@ void gauss_label(const gfw_graph_s *g, hipStream_t st)
 {
     const GaussGraph &gg = *g->gauss;
     const Workspace &w = g->ws;
-    const int64_t nK = g->n * g->K;
-    k_gauss_scale_s<<<grid_for(nK, kRowBlock, 4096), kRowBlock, 0, st>>>(g->n, g->K, gg.dinv, w.s0, w.s1, w.ctl,
-                                                                          gg.V);
-    apply_w(gg, g->K, gg.V, gg.R, w.ctl, st);
-    k_gauss_label<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), gg.dinv, gg.R);
+    const int32_t KP = gg.kp;
+    k_gauss_scale_s<<<grid_for(g->n * KP, kRowBlock, 4096), kRowBlock, 0, st>>>(g->n, KP, gg.dinv, w.s0, w.s1, w.ctl,
+                                                                                 gg.V);
+    apply_w(gg, KP, gg.V, gg.R, w.ctl, st);
+    k_gauss_label<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), KP, gg.dinv, gg.R);
 }
 
 template <typename T>
 int gauss_energy(const gfw_graph_s *g, const T *U, double omega0, double *part, hipStream_t st)
 {
     const GaussGraph &gg = *g->gauss;
-    const int64_t nK = g->n * g->K;
-    k_gauss_scale_u<T><<<grid_for(nK, kRowBlock, 4096), kRowBlock, 0, st>>>(g->n, g->K, gg.dinv, U, gg.V);
-    apply_w(gg, g->K, gg.V, gg.R, nullptr, st);
-    k_gauss_energy<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), gg.dinv, U, gg.R, omega0, part);
+    const int32_t KP = gg.kp;
+    k_gauss_scale_u<T><<<grid_for(g->n * KP, kRowBlock, 4096), kRowBlock, 0, st>>>(g->n, g->K, KP, gg.dinv, U, gg.V);
+    apply_w(gg, KP, gg.V, gg.R, nullptr, st);
+    k_gauss_energy<T><<<g->shape.nb_row, kRowBlock, 0, st>>>(make_view<T>(g), KP, gg.dinv, U, gg.R, omega0, part);
     return g->shape.nb_row;
 }
 
@@ -122,9 +155,9 @@ template int gauss_energy<double>(const gfw_graph_s *, const double *, double, d
 namespace {
 
 // Grid geometry of the fast method for features xh (n x d, d <= 3) and width sigma: the
-// widths of the window and of the convolution (sigma^2 = 2 tau^2 + s^2), spacing, cells
-// covering every point with rw + 2 cells to spare on each side, and the work estimate of one
-// product (visits of a point or cell by a thread).
+// widths of the window and of the convolution (sigma^2 = 2 tau^2 + s^2), the spacing, the
+// convolution's taps, cells covering every point with kGridRW + 2 cells to spare on each side,
+// and the work estimate of one product (point and cell visits by a thread).
 struct GridPlan {
     GaussView v{};
     double work = 0.0;
@@ -136,14 +169,16 @@ GridPlan plan_grid(const std::vector<double> &xh, int64_t n, int d, double sigma
     GaussView &v = gp.v;
     const double tau2 = (1.0 - 1.0 / std::sqrt(2.0)) * sigma * sigma;
     const double s2 = sigma * sigma - 2.0 * tau2;
-    const double tau = std::sqrt(tau2), s = std::sqrt(s2);
-    v.h = 0.4 * sigma;
+    const double s = std::sqrt(s2);
+    v.h = kGridSpacing * sigma;
     v.inv2t2 = 1.0 / (2.0 * tau2);
     v.inv2s2g = 1.0 / (2.0 * s2);
-    v.rw = (int32_t)std::ceil(6.0 * tau / v.h);
-    v.rc = (int32_t)std::ceil(6.0 * s / v.h);
     const double c = v.h * v.h * sigma / (2.0 * M_PI * tau2 * s);
     v.cnorm = std::pow(c, d);
+    for (int t = 0; t <= kGridRC; ++t) {
+        const double dt = v.h * t;
+        v.ctap[t] = std::exp(-dt * dt * v.inv2s2g);
+    }
     for (int q = 0; q < kGridMaxDim; ++q) {
         if (q < d) {
             double lo = xh[(size_t)q], hi = lo;
@@ -151,8 +186,8 @@ GridPlan plan_grid(const std::vector<double> &xh, int64_t n, int d, double sigma
                 lo = std::min(lo, xh[(size_t)(i * d + q)]);
                 hi = std::max(hi, xh[(size_t)(i * d + q)]);
             }
-            v.g0[q] = lo - (v.rw + 2) * v.h;
-            const double span = std::floor((hi - v.g0[q]) / v.h) + v.rw + 4;
+            v.g0[q] = lo - (kGridRW + 2) * v.h;
+            const double span = std::floor((hi - v.g0[q]) / v.h) + kGridRW + 4;
             v.gdim[q] = span < 2e9 ? (int32_t)span : INT32_MAX;
         } else {
             v.g0[q] = 0.0;
@@ -164,8 +199,8 @@ GridPlan plan_grid(const std::vector<double> &xh, int64_t n, int d, double sigma
     v.gstride[2] = (int64_t)v.gdim[0] * v.gdim[1];
     const double cells = (double)v.gdim[0] * (double)v.gdim[1] * (double)v.gdim[2];
     v.ncells = cells < 9e18 ? (int64_t)cells : INT64_MAX;
-    const double win = std::pow(2.0 * v.rw + 2.0, d);
-    gp.work = cells * win + 2.0 * (double)n * win + cells * d * (2.0 * v.rc + 1.0);
+    const double win = std::pow((double)kGridWin, d);
+    gp.work = cells * win / kGridWin + 2.0 * (double)n * win + cells * d * (2.0 * kGridRC + 1.0);
     return gp;
 }
 
@@ -178,8 +213,9 @@ void features_to_f64(const void *src, int64_t count, std::vector<double> &out)
 
 } // namespace
 
-// The largest grid the fast method takes: ncells * K doubles per grid buffer.
-constexpr int64_t kGridMaxElems = int64_t(1) << 28;
+// The largest grid the fast method takes: ncells * KP doubles per grid buffer (the gather's
+// slices take kGridWin such buffers).
+constexpr int64_t kGridMaxElems = int64_t(1) << 26;
 
 gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t *p, gfw_graph_s **out, hipStream_t st)
 {
@@ -227,11 +263,12 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
     int method = p->method;
     GridPlan gp;
     if (method != GFW_GAUSS_EXACT && d <= kGridMaxDim) gp = plan_grid(xh, n, d, p->sigma);
-    const bool grid_fits = d <= kGridMaxDim && gp.v.ncells <= kGridMaxElems / K;
+    const int32_t KP = K <= 4 ? 4 : K <= 8 ? 8 : 16;
+    const bool grid_fits = d <= kGridMaxDim && gp.v.ncells <= kGridMaxElems / KP;
     if (method == GFW_GAUSS_GRID && !grid_fits)
         return fail(GFW_E_UNSUPPORTED, "the grid for sigma = %g over these features has %lld cells (at most %lld for K "
                     "= %d); use the exact method or a larger sigma", p->sigma, (long long)gp.v.ncells,
-                    (long long)(kGridMaxElems / K), K);
+                    (long long)(kGridMaxElems / KP), K);
     if (method == GFW_GAUSS_AUTO)
         method = (grid_fits && gp.work < (double)n * (double)n) ? GFW_GAUSS_GRID : GFW_GAUSS_EXACT;
 
@@ -254,6 +291,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
     if (!g->gauss) return fail(GFW_E_NOMEM, "host allocation failed");
     GaussGraph &gg = *g->gauss;
     gg.method = method;
+    gg.kp = KP;
     size_t bytes = 0;
     auto dalloc = [&](void **ptr, size_t b) -> gfw_status_t {
         hipError_t e = hipMalloc(ptr, std::max<size_t>(b, 16));
@@ -262,7 +300,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
         return GFW_OK;
     };
     gfw_status_t s;
-    const size_t nK = (size_t)n * K;
+    const size_t nK = (size_t)n * KP;
     if ((s = dalloc((void **)&g->lab, 4 * (size_t)n)) != GFW_OK) return s;
     if ((s = dalloc((void **)&gg.x, 8 * xh.size())) != GFW_OK) return s;
     if ((s = dalloc((void **)&gg.dinv, 8 * (size_t)n)) != GFW_OK) return s;
@@ -279,6 +317,9 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
             int64_t lin = 0;
             for (int q = 0; q < d; ++q) {
                 const int cq = (int)std::floor((xh[(size_t)(i * d + q)] - v.g0[q]) / v.h);
+                // every point's window lies inside the grid (the interpolation does not clamp)
+                if (cq - kGridRW < 0 || cq + kGridRW + 1 > v.gdim[q] - 1)
+                    return fail(GFW_E_HIP, "internal: point %lld binned outside the grid", (long long)i);
                 lin += (int64_t)cq * v.gstride[q];
             }
             pc[(size_t)i] = (int32_t)lin;
@@ -290,19 +331,27 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
         if ((s = dalloc((void **)&gg.cell_start, 4 * start.size())) != GFW_OK) return s;
         if ((s = dalloc((void **)&gg.cell_pts, 4 * (size_t)n)) != GFW_OK) return s;
         if ((s = dalloc((void **)&gg.pt_cell, 4 * (size_t)n)) != GFW_OK) return s;
-        if ((s = dalloc((void **)&gg.G0, 8 * (size_t)v.ncells * K)) != GFW_OK) return s;
-        if ((s = dalloc((void **)&gg.G1, 8 * (size_t)v.ncells * K)) != GFW_OK) return s;
+        if ((s = dalloc((void **)&gg.G0, 8 * (size_t)v.ncells * KP)) != GFW_OK) return s;
+        if ((s = dalloc((void **)&gg.G1, 8 * (size_t)v.ncells * KP)) != GFW_OK) return s;
+        if ((s = dalloc((void **)&gg.Gp, 8 * (size_t)v.ncells * KP * kGridWin)) != GFW_OK) return s;
+        if ((s = dalloc((void **)&gg.xs, 8 * xh.size())) != GFW_OK) return s;
+        if ((s = dalloc((void **)&gg.Vs, 8 * nK)) != GFW_OK) return s;
+        std::vector<double> xsh(xh.size());
+        for (int64_t pp = 0; pp < n; ++pp)
+            for (int q = 0; q < d; ++q) xsh[(size_t)(pp * d + q)] = xh[(size_t)((int64_t)pts[(size_t)pp] * d + q)];
+        GFW_HIP_TRY(hipMemcpyAsync(gg.xs, xsh.data(), 8 * xsh.size(), hipMemcpyHostToDevice, st));
+        GFW_HIP_TRY(hipStreamSynchronize(st));
         GFW_HIP_TRY(hipMemcpyAsync(gg.cell_start, start.data(), 4 * start.size(), hipMemcpyHostToDevice, st));
         GFW_HIP_TRY(hipMemcpyAsync(gg.cell_pts, pts.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
         GFW_HIP_TRY(hipMemcpyAsync(gg.pt_cell, pc.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
         GFW_HIP_TRY(hipStreamSynchronize(st)); // the host vectors go out of scope
     } else {
         // chunks of the points summed apart: about 8 waves per SIMD over the rows, each chunk
-        // at least one LDS tile of points
+        // at least 128 points
         const int64_t row_waves = cdiv(n, 64);
         const int64_t want = cdiv(8LL * 4 * std::max(ctx->num_cu, 1), row_waves);
-        int64_t chunks = std::min<int64_t>(std::max<int64_t>(want, 1), 64);
-        gg.chunk = cdiv(cdiv(n, chunks), kGaussTile) * kGaussTile;
+        const int64_t chunks = std::min<int64_t>(std::max<int64_t>(want, 1), 64);
+        gg.chunk = std::max<int64_t>(cdiv(n, chunks), 128);
         gg.chunks = (int32_t)cdiv(n, gg.chunk);
         if (gg.chunks > 1 && (s = dalloc((void **)&gg.Rp, 8 * nK * (size_t)gg.chunks)) != GFW_OK) return s;
     }
@@ -313,6 +362,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
     v.dinv = gg.dinv;
     v.cell_start = gg.cell_start;
     v.cell_pts = gg.cell_pts;
+    v.xs = gg.xs;
     v.pt_cell = gg.pt_cell;
 
     // labels (checked on the device: range, repeats, classes)
@@ -350,7 +400,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
     k_gauss_dinv<<<grid_for(n, 256, 4096), 256, 0, st>>>(n, method == GFW_GAUSS_GRID ? 1e-6 : 0.0, gg.R, gg.dinv);
     apply_w(gg, 1, gg.dinv, gg.R, nullptr, st);
     k_gauss_rho<<<grid_for(n, 256, 4096), 256, 0, st>>>(n, gg.dinv, gg.R, gg.V);
-    double *rmax = gg.R + n; // R holds n K >= 2n doubles
+    double *rmax = gg.R + n; // R holds n KP >= 4n doubles
     const unsigned long long zero64 = 0; // the bit pattern of +0.0
     GFW_HIP_TRY(hipMemcpyAsync(rmax, &zero64, sizeof(zero64), hipMemcpyHostToDevice, st));
     k_max_nonneg<<<(unsigned)std::min<int64_t>(std::max<int64_t>(cdiv(n, 1024), 1), 1024), 256, 0, st>>>(

@@ -15,11 +15,15 @@
 //    window g_tau (each grid cell sums the points binned in the cells around it, in a fixed
 //    order: deterministic, no atomics), convolve the grid with g_s one axis at a time, and
 //    interpolate back at every point with g_tau.  tau^2 = (1 - 1/sqrt 2) sigma^2 makes the
-//    narrowest Gaussian summed on the grid as wide as it can be (0.414 sigma); h = 0.4 sigma
-//    keeps the sampling error of every sum below 1e-9 (trapezoid rule on a Gaussian of width
-//    w: about 2 exp(-2 pi^2 w^2 / h^2)); the windows stop at 6 widths (exp(-18) = 1.5e-8).
+//    narrowest Gaussian summed on the grid as wide as it can be (0.414 sigma).  The grid
+//    spacing h = sigma / 2 and windows cut at 5 widths leave a relative error of about 1e-7
+//    per product (trapezoid rule on a Gaussian of width w: about 2 exp(-2 pi^2 w^2 / h^2),
+//    cut tails exp(-12.5)).  Since h, tau and s are fixed multiples of sigma, so are the
+//    half-widths in cells: kGridRW for the window, kGridRC for the convolution.
 //    The self term (w_ii = 0) is removed by subtracting V_i (the sum gives it weight 1).
-//  For both, L_s V = V - D^{-1/2} W D^{-1/2} V with the degrees d = W 1.
+//  For both, L_s V = V - D^{-1/2} W D^{-1/2} V with the degrees d = W 1.  The n x K blocks
+//  summed (V, R = W V, the grid's G) are stored with a padded row stride KP (1, 4, 8 or 16,
+//  the padding columns zero), so that every kernel's class loop has a compile-time length.
 // ---------------------------------------------------------------------------------
 #pragma once
 
@@ -29,7 +33,11 @@ namespace gfw {
 
 constexpr int kGaussMaxDim = 8;   // feature dimensions of the exact method
 constexpr int kGridMaxDim = 3;    // feature dimensions of the grid method
-constexpr int kGaussTile = 128;   // points staged in LDS per step of the exact method
+constexpr double kGridSpacing = 0.5; // h / sigma
+constexpr double kGridCut = 5.0;     // widths at which the window and the convolution stop
+constexpr int kGridRW = 6;        // ceil(kGridCut tau / h): the window reaches cells c - 6 .. c + 7
+constexpr int kGridRC = 7;        // ceil(kGridCut s / h): the convolution's taps -7 .. 7
+constexpr int kGridWin = 2 * kGridRW + 2; // grid points per dimension in a point's window
 
 struct GaussView {
     int64_t n;
@@ -45,67 +53,62 @@ struct GaussView {
     double h;                    // grid spacing
     double inv2t2, inv2s2g;      // 1 / (2 tau^2), 1 / (2 s^2)
     double cnorm;                // c^d
-    int32_t rw, rc;              // half-widths in cells of the window and of the convolution
+    double ctap[kGridRC + 1];    // g_s(t h), t = 0 .. kGridRC
     const int32_t *cell_start;   // ncells + 1: the points of cell a are cell_pts[cell_start[a] ..)
     const int32_t *cell_pts;
+    const double *xs;            // n x d: the features in binned order (xs[pp] = x[cell_pts[pp]])
     const int32_t *pt_cell;      // n: the linear cell of each point (the binning above, point-wise)
 };
 
 // ---- exact method -------------------------------------------------------------------
 
-// R_i = sum_{j != i} w_ij V_j, one thread per row i.  The points j are split into gridDim.y
-// chunks of `chunk` points (a multiple of kGaussTile), so that a few 10^4 rows still fill the
-// chip; chunk y sums its points in increasing order, staged in LDS kGaussTile at a time, into
-// Rp[y] (n x K).  k_gauss_chunks_sum adds the chunks in increasing order.  K <= KB.
-template <int KB>
-static __global__ void __launch_bounds__(kRowBlock) k_gauss_exact(GaussView gv, int32_t K, int64_t chunk,
-                                                                   const double *__restrict__ V, double *__restrict__ Rp,
-                                                                   const Ctl *__restrict__ ctl)
+// R_i = sum_{j != i} w_ij V_j, one thread per row i, V and R n x KP.  The points j are split
+// into gridDim.y chunks of `chunk` points, so that a few 10^4 rows still fill the chip;
+// chunk y sums its points in increasing order into Rp[y], and k_gauss_chunks_sum adds the
+// chunks in increasing order.  Every thread of a workgroup visits the same point j at the
+// same time, so x_j and V_j are uniform: they are read with scalar loads and broadcast from
+// scalar registers (no LDS staging).  D = d for d <= 3, else D = 0 (any d <= 8).
+template <int D, int KP>
+static __global__ void __launch_bounds__(kRowBlock) k_gauss_exact(GaussView gv, int64_t chunk,
+                                                                   const double *__restrict__ V,
+                                                                   double *__restrict__ Rp, const Ctl *__restrict__ ctl)
 {
     if (ctl && !ctl->active) return;
-    __shared__ double lx[kGaussTile * kGaussMaxDim];
-    __shared__ double lv[kGaussTile * KB];
+    constexpr int DM = D > 0 ? D : kGaussMaxDim;
+    const int d = D > 0 ? D : gv.d;
     const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
-    const bool has = i < gv.n;
-    const int d = gv.d;
-    double xi[kGaussMaxDim];
+    const int64_t ii = i < gv.n ? i : gv.n - 1; // rows past n compute row n - 1 and store nothing
+    const double *__restrict__ x = gv.x;
+    double xi[DM];
 #pragma unroll
-    for (int q = 0; q < kGaussMaxDim; ++q) xi[q] = (has && q < d) ? gv.x[i * d + q] : 0.0;
-    double acc[KB];
+    for (int q = 0; q < DM; ++q) xi[q] = q < d ? x[ii * d + q] : 0.0;
+    double acc[KP];
 #pragma unroll
-    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
+    const double nscale = -gv.inv2s2;
     const int64_t jb = (int64_t)blockIdx.y * chunk, je = min(gv.n, jb + chunk);
-    for (int64_t j0 = jb; j0 < je; j0 += kGaussTile) {
-        const int cnt = (int)min((int64_t)kGaussTile, je - j0);
-        __syncthreads(); // the previous tile has been consumed
-        for (int q = threadIdx.x; q < cnt * d; q += kRowBlock) lx[q] = gv.x[j0 * d + q];
-        for (int q = threadIdx.x; q < cnt * K; q += kRowBlock) lv[(q / K) * KB + q % K] = V[j0 * K + q];
-        __syncthreads();
-        if (!has) continue;
-        for (int t = 0; t < cnt; ++t) {
-            if (j0 + t == i) continue;
-            double r2 = 0.0;
+#pragma unroll 2
+    for (int64_t j = jb; j < je; ++j) {
+        double r2 = 0.0;
 #pragma unroll
-            for (int q = 0; q < kGaussMaxDim; ++q)
-                if (q < d) {
-                    const double df = xi[q] - lx[t * d + q];
-                    r2 += df * df;
-                }
-            const double w = exp(-r2 * gv.inv2s2);
+        for (int q = 0; q < DM; ++q)
+            if (q < d) {
+                const double df = xi[q] - x[j * d + q];
+                r2 = fma(df, df, r2);
+            }
+        double w = exp(r2 * nscale);
+        w = j == ii ? 0.0 : w;
 #pragma unroll
-            for (int c = 0; c < KB; ++c)
-                if (c < K) acc[c] += w * lv[t * KB + c];
-        }
+        for (int c = 0; c < KP; ++c) acc[c] = fma(w, V[j * KP + c], acc[c]);
     }
-    if (has) {
-        double *out = Rp + (int64_t)blockIdx.y * gv.n * K + i * K;
+    if (i < gv.n) {
+        double *out = Rp + ((int64_t)blockIdx.y * gv.n + i) * KP;
 #pragma unroll
-        for (int c = 0; c < KB; ++c)
-            if (c < K) out[c] = acc[c];
+        for (int c = 0; c < KP; ++c) out[c] = acc[c];
     }
 }
 
-// R = sum over the chunks y = 0, 1, ... of Rp[y] (in that order); count = n K.
+// R = sum over the chunks y = 0, 1, ... of Rp[y] (in that order); count = n KP.
 static __global__ void k_gauss_chunks_sum(int64_t count, int32_t chunks, const double *__restrict__ Rp,
                                           double *__restrict__ R, const Ctl *__restrict__ ctl)
 {
@@ -122,158 +125,193 @@ static __global__ void k_gauss_chunks_sum(int64_t count, int32_t chunks, const d
 // coordinate of grid index a along dimension q
 __device__ __forceinline__ double grid_coord(const GaussView &gv, int q, int a) { return gv.g0[q] + gv.h * (double)a; }
 
-// G0[a] = sum over points p in the cells within rw of a (cells in increasing linear order,
-// points in their binned order) of g_tau(a - x_p) V_p.  One thread per cell.
-template <int KB>
-static __global__ void __launch_bounds__(kRowBlock) k_grid_gather(GaussView gv, int32_t K, const double *__restrict__ V,
-                                                                   double *__restrict__ G0, const Ctl *__restrict__ ctl)
+// Vs[pp] = V[cell_pts[pp]] (stride KP): the gather's right-hand side in binned order.
+template <int KP>
+static __global__ void __launch_bounds__(kRowBlock) k_grid_bin_v(GaussView gv, const double *__restrict__ V,
+                                                                  double *__restrict__ Vs, const Ctl *__restrict__ ctl)
+{
+    if (ctl && !ctl->active) return;
+    for (int64_t t = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; t < gv.n * KP; t += (int64_t)gridDim.x * kRowBlock) {
+        const int64_t pp = t / KP;
+        Vs[t] = V[(int64_t)gv.cell_pts[pp] * KP + (t - pp * KP)];
+    }
+}
+
+// G0[a] = sum over the points p binned in the cells b with a - kGridRW - 1 <= b <= a + kGridRW
+// of g_tau(a - x_p) V_p (Vs: V in binned order, stride KP): the mirror of the grid points k_grid_interp visits
+// around a point's cell, so that both truncate the window on the same point-grid pairs.
+// Image colours crowd into a few clusters, so a cell near a cluster's centre has most of the
+// cluster in its box: the box is cut into its kGridWin slices along the last dimension, one
+// thread per (cell, slice) (blockIdx.y = slice), each writing its partial sum to Gp[slice]
+// (ncells x KP); k_gauss_chunks_sum adds the slices in increasing order.  Within a slice, the
+// cells with the same coordinates past dimension 0 are consecutive in the linear order, so
+// their points form one range of the binned order: the slice walks its rows in increasing
+// order and each row's points in binned order, reading the features and V of the points
+// contiguously (xs, Vs).
+template <int D, int KP>
+static __global__ void __launch_bounds__(kRowBlock) k_grid_gather(GaussView gv, const double *__restrict__ Vs,
+                                                                   double *__restrict__ Gp, const Ctl *__restrict__ ctl)
 {
     if (ctl && !ctl->active) return;
     const int64_t a = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
     if (a >= gv.ncells) return;
-    int ai[kGridMaxDim];
-    double ac[kGridMaxDim];
+    int ai[kGridMaxDim] = {0, 0, 0};
+    double ac[kGridMaxDim] = {0.0, 0.0, 0.0};
     int64_t rem = a;
 #pragma unroll
-    for (int q = kGridMaxDim - 1; q >= 0; --q) {
+    for (int q = D - 1; q >= 0; --q) {
         ai[q] = (int)(rem / gv.gstride[q]);
         rem -= (int64_t)ai[q] * gv.gstride[q];
-        ac[q] = q < gv.d ? grid_coord(gv, q, ai[q]) : 0.0;
+        ac[q] = grid_coord(gv, q, ai[q]);
     }
-    // the cells whose points the window of grid point a reaches: the mirror of the grid points
-    // k_grid_interp visits around a point's cell (cell - rw .. cell + rw + 1), so that the gather
-    // and the interpolation truncate the window on the same point-grid pairs
-    int lo[kGridMaxDim], hi[kGridMaxDim];
+    int lo[kGridMaxDim] = {0, 0, 0}, hi[kGridMaxDim] = {0, 0, 0};
 #pragma unroll
-    for (int q = 0; q < kGridMaxDim; ++q) {
-        lo[q] = q < gv.d ? max(ai[q] - gv.rw - 1, 0) : 0;
-        hi[q] = q < gv.d ? min(ai[q] + gv.rw, gv.gdim[q] - 1) : 0;
+    for (int q = 0; q < D; ++q) {
+        lo[q] = max(ai[q] - kGridRW - 1, 0);
+        hi[q] = min(ai[q] + kGridRW, gv.gdim[q] - 1);
     }
-    double acc[KB];
+    // this thread's slice: one index of the last dimension
+    const int bs = ai[D - 1] - kGridRW - 1 + (int)blockIdx.y;
+    const bool in_grid = bs >= 0 && bs < gv.gdim[D - 1];
+    lo[D - 1] = bs;
+    hi[D - 1] = bs;
+    const double *__restrict__ xs = gv.xs;
+    double acc[KP];
 #pragma unroll
-    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
+    if (in_grid) // a slice past the grid's edge is empty
     for (int b2 = lo[2]; b2 <= hi[2]; ++b2)
-        for (int b1 = lo[1]; b1 <= hi[1]; ++b1)
-            for (int b0 = lo[0]; b0 <= hi[0]; ++b0) {
-                const int64_t cb = (int64_t)b0 * gv.gstride[0] + (int64_t)b1 * gv.gstride[1] + (int64_t)b2 * gv.gstride[2];
-                const int32_t p0 = gv.cell_start[cb], p1 = gv.cell_start[cb + 1];
-                for (int32_t pp = p0; pp < p1; ++pp) {
-                    const int32_t p = gv.cell_pts[pp];
-                    double r2 = 0.0;
+        for (int b1 = lo[1]; b1 <= hi[1]; ++b1) {
+            const int64_t row = (int64_t)b1 * gv.gstride[1] + (int64_t)b2 * gv.gstride[2];
+            const int32_t p0 = gv.cell_start[row + lo[0]], p1 = gv.cell_start[row + hi[0] + 1];
+#pragma unroll 4
+            for (int64_t pp = p0; pp < p1; ++pp) {
+                double r2 = 0.0;
 #pragma unroll
-                    for (int q = 0; q < kGridMaxDim; ++q)
-                        if (q < gv.d) {
-                            const double df = ac[q] - gv.x[(int64_t)p * gv.d + q];
-                            r2 += df * df;
-                        }
-                    const double w = exp(-r2 * gv.inv2t2);
-#pragma unroll
-                    for (int c = 0; c < KB; ++c)
-                        if (c < K) acc[c] += w * V[(int64_t)p * K + c];
+                for (int q = 0; q < D; ++q) {
+                    const double df = ac[q] - xs[pp * D + q];
+                    r2 = fma(df, df, r2);
                 }
-            }
+                const double w = exp(-r2 * gv.inv2t2);
 #pragma unroll
-    for (int c = 0; c < KB; ++c)
-        if (c < K) G0[a * K + c] = acc[c];
+                for (int c = 0; c < KP; ++c) acc[c] = fma(w, Vs[pp * KP + c], acc[c]);
+            }
+        }
+    double *__restrict__ out = Gp + ((int64_t)blockIdx.y * gv.ncells + a) * KP;
+#pragma unroll
+    for (int c = 0; c < KP; ++c) out[c] = acc[c];
 }
 
-// out[a] = sum_{t = -rc..rc} g_s(t h) in[a + t e_axis] (zero past the grid).  One thread per cell.
-template <int KB>
-static __global__ void __launch_bounds__(kRowBlock) k_grid_conv(GaussView gv, int32_t K, int axis,
-                                                                 const double *__restrict__ in, double *__restrict__ out,
-                                                                 const Ctl *__restrict__ ctl)
+// out[a] = sum_{t = -kGridRC..kGridRC} g_s(t h) in[a + t e_axis] (zero past the grid).  One
+// thread per cell.
+template <int KP>
+static __global__ void __launch_bounds__(kRowBlock) k_grid_conv(GaussView gv, int axis, const double *__restrict__ in,
+                                                                 double *__restrict__ out, const Ctl *__restrict__ ctl)
 {
     if (ctl && !ctl->active) return;
     const int64_t a = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
     if (a >= gv.ncells) return;
     const int64_t st = gv.gstride[axis];
     const int ai = (int)((a / st) % gv.gdim[axis]);
-    double acc[KB];
+    double acc[KP];
 #pragma unroll
-    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
-    const int t0 = max(-gv.rc, -ai), t1 = min(gv.rc, gv.gdim[axis] - 1 - ai);
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
+    const int t0 = max(-kGridRC, -ai), t1 = min(kGridRC, gv.gdim[axis] - 1 - ai);
     for (int t = t0; t <= t1; ++t) {
-        const double dt = gv.h * (double)t;
-        const double w = exp(-dt * dt * gv.inv2s2g);
-        const double *src = in + (a + (int64_t)t * st) * K;
+        const double w = gv.ctap[t < 0 ? -t : t];
+        const double *src = in + (a + (int64_t)t * st) * KP;
 #pragma unroll
-        for (int c = 0; c < KB; ++c)
-            if (c < K) acc[c] += w * src[c];
+        for (int c = 0; c < KP; ++c) acc[c] = fma(w, src[c], acc[c]);
     }
 #pragma unroll
-    for (int c = 0; c < KB; ++c)
-        if (c < K) out[a * K + c] = acc[c];
+    for (int c = 0; c < KP; ++c) out[a * KP + c] = acc[c];
 }
 
-// R_i = c^d sum over cells a within rw of x_i of g_tau(x_i - a) G1[a], minus V_i (the self
-// term).  One thread per point.
-template <int KB>
-static __global__ void __launch_bounds__(kRowBlock) k_grid_interp(GaussView gv, int32_t K, const double *__restrict__ G1,
+// R_i = c^d sum over the grid points a with c_i - kGridRW <= a <= c_i + kGridRW + 1 (c_i the
+// cell of x_i; inside the grid, which keeps kGridRW + 2 cells to spare) of g_tau(x_i - a)
+// G1[a], minus V_i (the self term).  One thread per point.  The window factors over the
+// dimensions: the weights along dimension 0 are formed once per point (kGridWin of them, in
+// registers), those along dimensions 1 and 2 once per row of the window.
+template <int D, int KP>
+static __global__ void __launch_bounds__(kRowBlock) k_grid_interp(GaussView gv, const double *__restrict__ G1,
                                                                    const double *__restrict__ V, double *__restrict__ R,
                                                                    const Ctl *__restrict__ ctl)
 {
     if (ctl && !ctl->active) return;
     const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
     if (i >= gv.n) return;
-    double xi[kGridMaxDim];
-    int lo[kGridMaxDim], hi[kGridMaxDim];
+    int ci[kGridMaxDim] = {0, 0, 0};
+    double xi[kGridMaxDim] = {0.0, 0.0, 0.0};
     int64_t rem = gv.pt_cell[i];
 #pragma unroll
-    for (int q = kGridMaxDim - 1; q >= 0; --q) {
-        const int ci = (int)(rem / gv.gstride[q]);
-        rem -= (int64_t)ci * gv.gstride[q];
-        xi[q] = q < gv.d ? gv.x[i * gv.d + q] : 0.0;
-        lo[q] = q < gv.d ? max(ci - gv.rw, 0) : 0;
-        hi[q] = q < gv.d ? min(ci + gv.rw + 1, gv.gdim[q] - 1) : 0;
+    for (int q = D - 1; q >= 0; --q) {
+        ci[q] = (int)(rem / gv.gstride[q]);
+        rem -= (int64_t)ci[q] * gv.gstride[q];
+        xi[q] = gv.x[i * D + q];
     }
-    double acc[KB];
+    double w0[kGridWin];
 #pragma unroll
-    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
-    for (int b2 = lo[2]; b2 <= hi[2]; ++b2)
-        for (int b1 = lo[1]; b1 <= hi[1]; ++b1)
-            for (int b0 = lo[0]; b0 <= hi[0]; ++b0) {
-                const int bb[kGridMaxDim] = {b0, b1, b2};
-                double r2 = 0.0;
+    for (int t = 0; t < kGridWin; ++t) {
+        const double df = xi[0] - grid_coord(gv, 0, ci[0] - kGridRW + t);
+        w0[t] = exp(-df * df * gv.inv2t2);
+    }
+    double acc[KP];
 #pragma unroll
-                for (int q = 0; q < kGridMaxDim; ++q)
-                    if (q < gv.d) {
-                        const double df = xi[q] - grid_coord(gv, q, bb[q]);
-                        r2 += df * df;
-                    }
-                const double w = exp(-r2 * gv.inv2t2);
-                const double *src =
-                    G1 + ((int64_t)b0 * gv.gstride[0] + (int64_t)b1 * gv.gstride[1] + (int64_t)b2 * gv.gstride[2]) * K;
-#pragma unroll
-                for (int c = 0; c < KB; ++c)
-                    if (c < K) acc[c] += w * src[c];
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
+    constexpr int N2 = D >= 3 ? kGridWin : 1, N1 = D >= 2 ? kGridWin : 1;
+    for (int t2 = 0; t2 < N2; ++t2) {
+        double w2 = 1.0;
+        if (D >= 3) {
+            const double df = xi[2] - grid_coord(gv, 2, ci[2] - kGridRW + t2);
+            w2 = exp(-df * df * gv.inv2t2);
+        }
+        for (int t1 = 0; t1 < N1; ++t1) {
+            double w12 = w2;
+            if (D >= 2) {
+                const double df = xi[1] - grid_coord(gv, 1, ci[1] - kGridRW + t1);
+                w12 = w2 * exp(-df * df * gv.inv2t2);
             }
+            const int64_t base = (int64_t)(ci[0] - kGridRW) + (D >= 2 ? (int64_t)(ci[1] - kGridRW + t1) * gv.gstride[1] : 0) +
+                                 (D >= 3 ? (int64_t)(ci[2] - kGridRW + t2) * gv.gstride[2] : 0);
+            const double *__restrict__ src = G1 + base * KP;
 #pragma unroll
-    for (int c = 0; c < KB; ++c)
-        if (c < K) R[i * K + c] = gv.cnorm * acc[c] - V[i * K + c];
+            for (int t0 = 0; t0 < kGridWin; ++t0) {
+                const double w = w12 * w0[t0];
+#pragma unroll
+                for (int c = 0; c < KP; ++c) acc[c] = fma(w, src[t0 * KP + c], acc[c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < KP; ++c) R[i * KP + c] = gv.cnorm * acc[c] - V[i * KP + c];
 }
 
 // ---- the pieces of the iteration around R = W V ----------------------------------------
 
-// V = D^{-1/2} U, for P = L_s U and the objective.
+// V = D^{-1/2} U (stride KP, the padding zero), for P = L_s U and the objective.
 template <typename T>
-static __global__ void __launch_bounds__(kRowBlock) k_gauss_scale_u(int64_t n, int32_t K, const double *__restrict__ dinv,
+static __global__ void __launch_bounds__(kRowBlock) k_gauss_scale_u(int64_t n, int32_t K, int32_t KP,
+                                                                    const double *__restrict__ dinv,
                                                                     const T *__restrict__ U, double *__restrict__ V)
 {
-    for (int64_t t = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; t < n * K; t += (int64_t)gridDim.x * kRowBlock)
-        V[t] = dinv[t / K] * (double)U[t];
+    for (int64_t t = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; t < n * KP; t += (int64_t)gridDim.x * kRowBlock) {
+        const int64_t i = t / KP;
+        const int32_t c = (int32_t)(t - i * KP);
+        V[t] = c < K ? dinv[i] * (double)U[i * K + c] : 0.0;
+    }
 }
 
-// V = D^{-1/2} S_k, the one-hot rows of the iteration's vertices, for its label pass.
-static __global__ void __launch_bounds__(kRowBlock) k_gauss_scale_s(int64_t n, int32_t K, const double *__restrict__ dinv,
+// V = D^{-1/2} S_k (stride KP), the one-hot rows of the iteration's vertices, for its label pass.
+static __global__ void __launch_bounds__(kRowBlock) k_gauss_scale_s(int64_t n, int32_t KP, const double *__restrict__ dinv,
                                                                     const uint8_t *__restrict__ s0,
                                                                     const uint8_t *__restrict__ s1,
                                                                     const Ctl *__restrict__ ctl, double *__restrict__ V)
 {
     if (!ctl->active) return;
     const uint8_t *__restrict__ s = (ctl->k & 1) ? s1 : s0;
-    for (int64_t t = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; t < n * K; t += (int64_t)gridDim.x * kRowBlock) {
-        const int64_t i = t / K;
-        V[t] = (int32_t)(t - i * K) == (int32_t)s[i] ? dinv[i] : 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; t < n * KP; t += (int64_t)gridDim.x * kRowBlock) {
+        const int64_t i = t / KP;
+        V[t] = (int32_t)(t - i * KP) == (int32_t)s[i] ? dinv[i] : 0.0;
     }
 }
 
@@ -283,21 +321,24 @@ static __global__ void k_gauss_fill(int64_t n, double v, double *__restrict__ ou
         out[i] = v;
 }
 
-// P = U - D^{-1/2} R (R = W D^{-1/2} U), stored as PT.
+// P = U - D^{-1/2} R (R = W D^{-1/2} U, stride KP), stored as PT.
 template <typename T, typename PT>
-static __global__ void __launch_bounds__(kRowBlock) k_gauss_p(int64_t n, int32_t K, const double *__restrict__ dinv,
-                                                              const T *__restrict__ U, const double *__restrict__ R,
-                                                              PT *__restrict__ P)
+static __global__ void __launch_bounds__(kRowBlock) k_gauss_p(int64_t n, int32_t K, int32_t KP,
+                                                              const double *__restrict__ dinv, const T *__restrict__ U,
+                                                              const double *__restrict__ R, PT *__restrict__ P)
 {
-    for (int64_t t = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; t < n * K; t += (int64_t)gridDim.x * kRowBlock)
-        P[t] = (PT)((double)U[t] - dinv[t / K] * R[t]);
+    for (int64_t t = (int64_t)blockIdx.x * kRowBlock + threadIdx.x; t < n * K; t += (int64_t)gridDim.x * kRowBlock) {
+        const int64_t i = t / K;
+        P[t] = (PT)((double)U[t] - dinv[i] * R[i * KP + (t - i * K)]);
+    }
 }
 
-// Label pass of a Gaussian graph: Q_k = S_k - D^{-1/2} R with R = W D^{-1/2} S_k, rounded to
-// the graph's dtype; the per-row term Q_{i, s_i} summed per 256-row block; the finish of the
-// iteration by the last block (finish_if_last).
+// Label pass of a Gaussian graph: Q_k = S_k - D^{-1/2} R with R = W D^{-1/2} S_k (stride KP),
+// rounded to the graph's dtype; the per-row term Q_{i, s_i} summed per 256-row block; the
+// finish of the iteration by the last block (finish_if_last).
 template <typename T>
-static __global__ void __launch_bounds__(kRowBlock) k_gauss_label(GraphView<T> view, const double *__restrict__ dinv,
+static __global__ void __launch_bounds__(kRowBlock) k_gauss_label(GraphView<T> view, int32_t KP,
+                                                                  const double *__restrict__ dinv,
                                                                   const double *__restrict__ R)
 {
     const Ctl *__restrict__ ctl = view.ctl;
@@ -311,7 +352,7 @@ static __global__ void __launch_bounds__(kRowBlock) k_gauss_label(GraphView<T> v
         const int32_t si = (int32_t)s[i];
         const double di = dinv[i];
         for (int32_t c = 0; c < K; ++c) {
-            const T q = (T)((c == si ? 1.0 : 0.0) - di * R[i * K + c]);
+            const T q = (T)((c == si ? 1.0 : 0.0) - di * R[i * KP + c]);
             view.Q[i * K + c] = q;
             if (c == si) own = (double)q;
         }
@@ -321,10 +362,11 @@ static __global__ void __launch_bounds__(kRowBlock) k_gauss_label(GraphView<T> v
     finish_if_last(view, view.row_part, view.nb_row, view.lab_part, view.nb_row);
 }
 
-// Terms of E(U) of a Gaussian graph from U and R = W D^{-1/2} U (P = U - D^{-1/2} R): block
-// sums of <u_i, P_i>, sum u(1-u), omega_i ||uhat_i - u_i||^2 at part[j * nb + tile].
+// Terms of E(U) of a Gaussian graph from U and R = W D^{-1/2} U (stride KP; P = U - D^{-1/2}
+// R): block sums of <u_i, P_i>, sum u(1-u), omega_i ||uhat_i - u_i||^2 at part[j * nb + tile].
 template <typename T>
-static __global__ void __launch_bounds__(kRowBlock) k_gauss_energy(GraphView<T> view, const double *__restrict__ dinv,
+static __global__ void __launch_bounds__(kRowBlock) k_gauss_energy(GraphView<T> view, int32_t KP,
+                                                                   const double *__restrict__ dinv,
                                                                    const T *__restrict__ U, const double *__restrict__ R,
                                                                    double omega0, double *__restrict__ part)
 {
@@ -335,7 +377,7 @@ static __global__ void __launch_bounds__(kRowBlock) k_gauss_energy(GraphView<T> 
         const double di = dinv[i];
         for (int32_t c = 0; c < view.K; ++c) {
             const double u = (double)U[i * view.K + c];
-            const double p = u - di * R[i * view.K + c];
+            const double p = u - di * R[i * KP + c];
             acc[0] += u * p;
             acc[1] += u * (1.0 - u);
             if (y >= 0) {
@@ -349,7 +391,7 @@ static __global__ void __launch_bounds__(kRowBlock) k_gauss_energy(GraphView<T> 
 
 // d_i^{-1/2} from R = W 1; a degree at or below `floor` makes node i isolated (d_i^{-1/2} = 0,
 // its row of L_s the identity's).  The grid method takes floor = 1e-6: there the degree is
-// the grid sum minus the self term 1, and a few 1e-8 of it are the method's error.
+// the grid sum minus the self term 1, and about 1e-7 of it is the method's error.
 static __global__ void k_gauss_dinv(int64_t n, double floor_, const double *__restrict__ R, double *__restrict__ dinv)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -357,7 +399,6 @@ static __global__ void k_gauss_dinv(int64_t n, double floor_, const double *__re
 }
 
 // The Gershgorin radius 1 + d_i^{-1/2} (W D^{-1/2} 1)_i of row i of L_s (R2 = W dinv).
-
 static __global__ void k_gauss_rho(int64_t n, const double *__restrict__ dinv, const double *__restrict__ R2,
                                    double *__restrict__ rho)
 {
