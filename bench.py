@@ -407,6 +407,54 @@ def bench_image(gfw, ctx, reps: int = 10, cpu: bool = True) -> dict:
     return res
 
 
+def bench_incremental(gfw, ctx, n_old: int = 1_000_000, n_new: int = 1_000, K: int = 5) -> dict:
+    """Inference for new nodes: an SBM network of n_old nodes (expected degree 24, p_in/p_out =
+    8, 5% labelled) is segmented (GFW to tol 1e-6), grows by n_new nodes, and is solved again
+    from the old binary solution with the new rows at 1/K: by the full iteration and by the
+    incremental one (moving rows only), both to tol 1e-6, FP32.  Wall times of whole solves
+    (set-up included; labels returned, no stats), iterations, and the agreement of the two on
+    the new nodes."""
+    import numpy as np
+    import torch
+
+    from synth import configs
+
+    old, full = configs.grown_sbm(seed=11, n_old=n_old, n_new=n_new, K=K)
+    stream = torch.cuda.current_stream()
+    go = old.graph
+    Go = gfw.Graph.from_host(ctx, go.n, K, go.indptr, go.indices, go.data, old.labelled_idx, old.labels, gfw.F32)
+    r_old = gfw.solve(ctx, Go, gfw.params(max_iter=300, tol=1e-6), stream=stream)
+    lab_old = r_old["labels"].cpu().numpy()
+    Go.close()
+    g = full.graph
+    G = gfw.Graph.from_host(ctx, g.n, K, g.indptr, g.indices, g.data, full.labelled_idx, full.labels, gfw.F32)
+    U0 = torch.full((g.n, K), 1.0 / K, dtype=torch.float32, device="cuda")
+    U0[:n_old] = 0.0
+    U0[torch.arange(n_old, device="cuda"), torch.tensor(lab_old, device="cuda", dtype=torch.int64)] = 1.0
+    res = {"workload": f"grown SBM: {n_old} segmented nodes + {n_new} new, K={K}, nnz={g.nnz}, FP32, "
+                       "warm start to tol 1e-6"}
+    out = {}
+    for name, inc in (("full", False), ("incremental", True)):
+        prm = gfw.params(max_iter=300, tol=1e-6, U0=U0, incremental=inc)
+        r = gfw.solve(ctx, G, prm, stream=stream)  # warm-up, with the stats
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):  # labels only, as an inference call would ask
+            gfw.solve(ctx, G, prm, want_U=False, want_stats=False, stream=stream)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        out[name] = r
+        res[name] = {"solve_ms": round(ms, 3), "iterations": r["iters"],
+                     "us_per_iteration": round(1e3 * ms / max(r["iters"], 1), 2)}
+    la, lb = out["full"]["labels"].cpu().numpy(), out["incremental"]["labels"].cpu().numpy()
+    res["speedup"] = round(res["full"]["solve_ms"] / res["incremental"]["solve_ms"], 1)
+    res["new_node_agreement"] = round(float(np.mean(la[n_old:] == lb[n_old:])), 4)
+    res["new_node_accuracy"] = round(float(np.mean(lb[n_old:] == g.truth[n_old:])), 4)
+    G.close()
+    return res
+
+
 def solve_bytes_per_iteration(n: int, nnz: int, K: int, ubytes: int = 4) -> int:
     """Bytes one iteration of the path moves for a graph (FP32 values and U): the label pass
     (row pointers, index + value per entry, labels read, Q written) and the row kernel (U read
@@ -617,6 +665,7 @@ def main() -> int:
                     help="measured requests under load in the serving measurement, after 200 warm-up (0: skip)")
     ap.add_argument("--many-classes", type=int, default=1, help="run the many-classes measurement (0: skip)")
     ap.add_argument("--image", type=int, default=1, help="run the fully connected image measurement (0: skip)")
+    ap.add_argument("--incremental", type=int, default=1, help="run the new-node inference measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true", help="run only the 1 GiB calibration copies")
     ap.add_argument("--derive-traffic", metavar="DIR", help="write profiles/traffic.json from counter runs in DIR")
     args = ap.parse_args()
@@ -733,6 +782,9 @@ def main() -> int:
     if args.many_classes:
         extra["many_classes"] = bench_many_classes(gfw, ctx)
         log("[bench] many classes: " + json.dumps(extra["many_classes"]))
+    if args.incremental:
+        extra["incremental"] = bench_incremental(gfw, ctx)
+        log("[bench] incremental: " + json.dumps(extra["incremental"]))
     if args.image:
         extra["image"] = bench_image(gfw, ctx, cpu=not args.no_cpu)
         log("[bench] image: " + json.dumps(extra["image"]))

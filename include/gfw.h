@@ -126,6 +126,19 @@ typedef struct {
                             so only the new rows move.                                       */
     int32_t p_refresh;   /* recompute L_s U by a full SpMM every p_refresh iterations
                             (0 = only at the start); see gfw_solve                          */
+    int32_t incremental; /* 1: inference for new nodes (Section 4, closing remarks): a warm
+                            start from U0 that iterates only the rows of U0 that are not
+                            binary.  The GLMO keeps binary rows, so their rows of U, of the
+                            vertex matrix S and of the direction are fixed; each iteration
+                            then touches only the moving rows and their CSR entries.  When
+                            a history is asked for, E(U_k) is carried by the exact quadratic
+                            update E_{k+1} = E_k - alpha g_k + alpha^2 q_k / 2 from E(U_0)
+                            (one evaluation on the whole graph; without a history the
+                            history's E is not formed).  The
+                            iterates are those of the full iteration (sums in another
+                            order).  Needs U0, the GLMO, p_refresh = 0, a CSR graph and
+                            K <= 16 (GFW_E_INVALID_ARG / GFW_E_UNSUPPORTED otherwise); not
+                            in batches or the server.  0: every row every iteration.        */
 } gfw_params_t;
 
 typedef struct {
@@ -144,7 +157,7 @@ typedef struct gfw_server_s *gfw_server_t;
 GFW_API const char *gfw_status_string(gfw_status_t s);
 GFW_API const char *gfw_last_error(void);
 /* eps = 50, omega0 = 1000, max_iter = 30, tol = 1e-6, Armijo with delta = 0.5,
- * gamma = 1e-6, GLMO, no one-shot, lipschitz = 0, U0 = NULL, p_refresh = 0. */
+ * gamma = 1e-6, GLMO, no one-shot, lipschitz = 0, U0 = NULL, p_refresh = 0, incremental = 0. */
 GFW_API void gfw_params_default(gfw_params_t *p);
 /* Host-only checks (no GPU needed).  gfw_check_problem validates the scalar fields and,
  * for location == GFW_HOST, the whole CSR and label arrays (same codes as

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgfw.so")
-SOURCES = ["gfw_api.hip", "gfw_batch.hip", "gfw_gauss.hip"]
+SOURCES = ["gfw_api.hip", "gfw_batch.hip", "gfw_gauss.hip", "gfw_active.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

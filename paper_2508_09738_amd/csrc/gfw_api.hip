@@ -210,6 +210,13 @@ gfw_status_t check_params(const gfw_params_t *p, int32_t K)
     if (p->one_shot != 0 && p->one_shot != 1) return fail(GFW_E_INVALID_ARG, "one_shot must be 0 or 1");
     if (std::isnan(p->lipschitz)) return fail(GFW_E_INVALID_ARG, "lipschitz is NaN");
     if (p->p_refresh < 0) return fail(GFW_E_INVALID_ARG, "p_refresh must be >= 0");
+    if (p->incremental != 0 && p->incremental != 1) return fail(GFW_E_INVALID_ARG, "incremental must be 0 or 1");
+    if (p->incremental) {
+        if (!p->U0) return fail(GFW_E_INVALID_ARG, "an incremental solve starts from U0");
+        if (p->lmo != GFW_LMO_GREEDY) return fail(GFW_E_INVALID_ARG, "an incremental solve needs the GLMO");
+        if (p->p_refresh != 0) return fail(GFW_E_INVALID_ARG, "an incremental solve takes p_refresh = 0");
+        if (K > 16) return fail(GFW_E_UNSUPPORTED, "incremental solves take K <= 16");
+    }
     if (K < 2) return fail(GFW_E_INVALID_ARG, "K must be >= 2");
     return GFW_OK;
 }
@@ -255,6 +262,10 @@ void free_graph(gfw_graph_s *g)
     dfree(w.scratch);
     dfree(w.ctl);
     dfree(w.hist);
+    dfree(w.act_moving);
+    dfree(w.act_cnt);
+    dfree(w.act_rows);
+    dfree(w.act_m);
     if (w.iter_exec) (void)hipGraphExecDestroy(w.iter_exec);
     if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
     if (w.h_flag) (void)hipHostFree(w.h_flag);
@@ -1027,13 +1038,20 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     launch_row<T, KMAX>(g, 1, st);
     GFW_HIP_TRY(hipGetLastError());
     if ((s = trace_flush(cx, st)) != GFW_OK) return s;
+    return solve_outputs(g, prm, U_out, labels_out, s_out, stats, history, st);
+}
+
+template <typename T, typename ST>
+static gfw_status_t solve_outputs_t(gfw_graph_s *g, const gfw_params_t *prm, void *U_out, int32_t *labels_out,
+                                    int32_t *s_out, gfw_stats_t *stats, double *history, hipStream_t st)
+{
+    Workspace &w = g->ws;
+    const T *U = (const T *)w.U;
+    const int64_t nK = g->n * g->K;
     if (U_out) GFW_HIP_TRY(hipMemcpyAsync(U_out, U, sizeof(T) * nK, hipMemcpyDeviceToDevice, st));
     if (labels_out || s_out)
-    {
-        using ST = std::conditional_t<(KMAX > 16), uint16_t, uint8_t>;
         k_outputs<T, ST><<<grid_for(g->n, 256), 256, 0, st>>>(g->n, g->K, U, (const ST *)w.s0, (const ST *)w.s1,
                                                              w.ctl, labels_out, s_out);
-    }
     GFW_HIP_TRY(hipGetLastError());
     if (stats || history) {
         Ctl ch;
@@ -1061,6 +1079,16 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
         }
     }
     return GFW_OK;
+}
+
+gfw_status_t solve_outputs(gfw_graph_s *g, const gfw_params_t *prm, void *U_out, int32_t *labels_out, int32_t *s_out,
+                           gfw_stats_t *stats, double *history, hipStream_t st)
+{
+    if (g->dtype == GFW_F32)
+        return g->K > 16 ? solve_outputs_t<float, uint16_t>(g, prm, U_out, labels_out, s_out, stats, history, st)
+                         : solve_outputs_t<float, uint8_t>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    return g->K > 16 ? solve_outputs_t<double, uint16_t>(g, prm, U_out, labels_out, s_out, stats, history, st)
+                     : solve_outputs_t<double, uint8_t>(g, prm, U_out, labels_out, s_out, stats, history, st);
 }
 
 template <typename T>
@@ -1111,6 +1139,13 @@ static gfw_status_t objective_to_device(const gfw_graph_s *g, const gfw_params_t
     k_energy_sum<<<1, kFinishThreads, 0, st>>>(part, nb, inv_eps, E_dev);
     GFW_HIP_TRY(hipGetLastError());
     return GFW_OK;
+}
+
+gfw_status_t objective_on_device(const gfw_graph_s *g, const gfw_params_t *prm, const void *U, double *part,
+                                 double *E_dev, hipStream_t st)
+{
+    return g->dtype == GFW_F32 ? objective_to_device<float>(g, prm, (const float *)U, part, E_dev, st)
+                               : objective_to_device<double>(g, prm, (const double *)U, part, E_dev, st);
 }
 
 template <typename T>
@@ -1169,6 +1204,7 @@ void gfw_params_default(gfw_params_t *p)
     p->lipschitz = 0.0;
     p->U0 = nullptr;
     p->p_refresh = 0;
+    p->incremental = 0;
 }
 
 gfw_status_t gfw_check_problem(const gfw_problem_t *p) { return check_problem(p); }
@@ -1270,8 +1306,13 @@ gfw_status_t gfw_solve(gfw_context_t ctx, gfw_graph_t g, const gfw_params_t *prm
     if (s != GFW_OK) return s;
     GFW_HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    s = g->dtype == GFW_F32 ? solve_dispatch<float>(g, prm, U_out, labels_out, s_out, stats, history, st)
-                            : solve_dispatch<double>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    if (prm->incremental) {
+        if (g->gauss) return fail(GFW_E_UNSUPPORTED, "incremental solves take CSR graphs");
+        s = solve_incremental(g, prm, U_out, labels_out, s_out, stats, history, st);
+    } else {
+        s = g->dtype == GFW_F32 ? solve_dispatch<float>(g, prm, U_out, labels_out, s_out, stats, history, st)
+                                : solve_dispatch<double>(g, prm, U_out, labels_out, s_out, stats, history, st);
+    }
     if (s != GFW_OK) return s;
     if (stats) {
         double E = 0.0;

@@ -736,6 +736,7 @@ gfw_status_t gfw_solve_batched(gfw_context_t ctx, int32_t count, const gfw_graph
         gfw_status_t s = check_params(ps[(size_t)i], graphs[i]->K);
         if (s != GFW_OK) return s;
         if (ps[(size_t)i]->p_refresh != 0) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported in batches");
+        if (ps[(size_t)i]->incremental) return fail(GFW_E_UNSUPPORTED, "incremental solves are not batched");
     }
     std::vector<gfw_graph_s *> sorted_gs = gs;
     std::sort(sorted_gs.begin(), sorted_gs.end());
@@ -784,6 +785,7 @@ gfw_status_t gfw_server_submit(gfw_server_t sv, const gfw_problem_t *p, const gf
     if (s != GFW_OK) return s;
     if ((s = check_params(prm, p->K)) != GFW_OK) return s;
     if (prm->p_refresh) return fail(GFW_E_UNSUPPORTED, "p_refresh is not supported by the server");
+    if (prm->incremental) return fail(GFW_E_UNSUPPORTED, "incremental solves are not served");
     const size_t fp = request_footprint(p, prm->max_iter, prm->U0 != nullptr, sv->ctx->num_cu);
     if (fp > sv->budget) return fail(GFW_E_BUDGET, "request needs %zu bytes, budget is %zu", fp, sv->budget);
     auto *r = new (std::nothrow) ServerRequest();

@@ -59,6 +59,10 @@ struct Workspace {
     Ctl *ctl = nullptr;
     double *hist = nullptr;
     int64_t hist_cap = 0;
+    // incremental solves (allocated at the first one): moving-row flags, block counts and
+    // offsets, the moving rows and their count
+    uint8_t *act_moving = nullptr;
+    int32_t *act_cnt = nullptr, *act_rows = nullptr, *act_m = nullptr;
     // captured chunk of iterations (depends only on the buffers above)
     hipGraphExec_t iter_exec = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -186,6 +190,17 @@ template <typename T>
 void gauss_label(const gfw_graph_s *g, hipStream_t st);
 template <typename T>
 int gauss_energy(const gfw_graph_s *g, const T *U, double omega0, double *part, hipStream_t st);
+
+// The outputs of a solve whose iterations have ended (U, labels, vertices, stats, history),
+// E(U) into device memory (block partials in part), and the incremental solve
+// (gfw_active.hip).
+gfw_status_t solve_outputs(gfw_graph_s *g, const gfw_params_t *prm, void *U_out, int32_t *labels_out, int32_t *s_out,
+                           gfw_stats_t *stats, double *history, hipStream_t st);
+gfw_status_t objective_on_device(const gfw_graph_s *g, const gfw_params_t *prm, const void *U, double *part,
+                                 double *E_dev, hipStream_t st);
+gfw_status_t solve_incremental(gfw_graph_s *g, const gfw_params_t *prm, void *U_out, int32_t *labels_out,
+                               int32_t *s_out, gfw_stats_t *stats, double *history, hipStream_t st);
+SolveParams solve_params(const gfw_graph_s *g, const gfw_params_t *prm);
 
 template <typename T>
 GraphView<T> make_view(const gfw_graph_s *g)

@@ -67,6 +67,7 @@ struct Ctl {
     double *hist;        // 5 x hist_stride history (may be null)
     int32_t hist_stride;
     uint32_t ticket;     // label-pass workgroups done with the iteration (finish_if_last)
+    double E_run;        // incremental solves: E(U_k) carried by E_{k+1} = E_k - a g_k + a^2 q_k / 2
 };
 
 // ---------------------------------------------------------------------------------
@@ -1124,18 +1125,19 @@ __device__ __forceinline__ void init_body(const GraphView<T> &gv, const T *__res
 constexpr int kSpmmLanes = 4;
 constexpr int kSpmmThreads = kRowBlock * kSpmmLanes;
 
+// Row i of L U (lane l of the row's kSpmmLanes holds classes l, l + kSpmmLanes, ...); i < 0 or
+// i >= n gives zeros.
 template <typename T, int KB>
-__device__ __forceinline__ void spmm_rows(const GraphView<T> &gv, const T *__restrict__ Uin, const int tile,
-                                          double (&acc)[KB / kSpmmLanes])
+__device__ __forceinline__ void spmm_row(const GraphView<T> &gv, const T *__restrict__ Uin, const int64_t i,
+                                         double (&acc)[KB / kSpmmLanes])
 {
     constexpr int MC = KB / kSpmmLanes; // classes per lane
     constexpr int UN = 4;
     const int32_t K = gv.K;
     const int l = threadIdx.x % kSpmmLanes;
-    const int64_t i = (int64_t)tile * kRowBlock + threadIdx.x / kSpmmLanes;
 #pragma unroll
     for (int m = 0; m < MC; ++m) acc[m] = 0.0;
-    if (i >= gv.n) return;
+    if (i < 0 || i >= gv.n) return;
     const T *__restrict__ ui = Uin + i * K;
     bool diag_due = gv.diag_one != 0; // the identity's term is still to be added
     auto take = [&](const int32_t j, const double v, const T (&uj)[MC]) {
@@ -1193,6 +1195,13 @@ __device__ __forceinline__ void spmm_rows(const GraphView<T> &gv, const T *__res
             const int c = l + kSpmmLanes * m;
             if (c < K) acc[m] += (double)ui[c];
         }
+}
+
+template <typename T, int KB>
+__device__ __forceinline__ void spmm_rows(const GraphView<T> &gv, const T *__restrict__ Uin, const int tile,
+                                          double (&acc)[KB / kSpmmLanes])
+{
+    spmm_row<T, KB>(gv, Uin, (int64_t)tile * kRowBlock + threadIdx.x / kSpmmLanes, acc);
 }
 
 // P = L U for the rows of tile `tile`, stored as PT.  kSpmmThreads threads.

@@ -59,7 +59,8 @@ class GaussianProblem(C.Structure):
 class Params(C.Structure):
     _fields_ = [("eps", C.c_double), ("omega0", C.c_double), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("ls", C.c_int), ("delta", C.c_double), ("gamma", C.c_double), ("lmo", C.c_int),
-                ("one_shot", C.c_int32), ("lipschitz", C.c_double), ("U0", C.c_void_p), ("p_refresh", C.c_int32)]
+                ("one_shot", C.c_int32), ("lipschitz", C.c_double), ("U0", C.c_void_p), ("p_refresh", C.c_int32),
+                ("incremental", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -127,13 +128,14 @@ def check(status: int) -> None:
 
 def params(eps: float = 50.0, omega0: float = 1000.0, max_iter: int = 30, tol: float = 1e-6, ls: int = LS_ARMIJO,
            delta: float = 0.5, gamma: float = 1e-6, lmo: int = LMO_GREEDY, one_shot: bool = False,
-           lipschitz: float = 0.0, U0=None, p_refresh: int = 0) -> Params:
+           lipschitz: float = 0.0, U0=None, p_refresh: int = 0, incremental: bool = False) -> Params:
     pr = Params()
     lib().gfw_params_default(C.byref(pr))
     pr.eps, pr.omega0, pr.max_iter, pr.tol, pr.ls = eps, omega0, max_iter, tol, ls
     pr.delta, pr.gamma, pr.lmo, pr.one_shot, pr.lipschitz = delta, gamma, lmo, int(one_shot), lipschitz
     pr.U0 = None if U0 is None else U0.data_ptr()
     pr.p_refresh = p_refresh
+    pr.incremental = int(incremental)
     return pr
 
 
