@@ -61,13 +61,18 @@ def _code_only(text: str) -> str:
     return " ".join("".join(out).split())
 
 
+# The sources of the kernels whose HBM traffic is reported (the single-graph iteration: the
+# label passes and row kernels, their launch set-up), and of the copy kernel.
+TRAFFIC_SOURCES = ("gfw_api.hip", "gfw_internal.h", "gfw_kernels.h", "gfw_kernels_bigk.h")
+
+
 def kernel_sources_hash() -> str:
-    """Hash of the code (comments and layout excluded) of the library's sources: the HBM
-    traffic counters in profiles/traffic.json are reported only for the sources they were
-    taken on."""
+    """Hash of the code (comments and layout excluded) of the sources the measured kernels are
+    built from: the HBM traffic counters in profiles/traffic.json are reported only for the
+    sources they were taken on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2508_09738_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in TRAFFIC_SOURCES:
         with open(os.path.join(csrc, name), encoding="utf-8") as f:
             h.update(name.encode())
             h.update(_code_only(f.read()).encode())
@@ -766,7 +771,9 @@ def main() -> int:
     src_hash = kernel_sources_hash()
     tb = traffic_from_profile("label", src_hash)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb, "kernel": "k_label (L_s S label pass)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tb,
+                "kernel": ("k_label_sorted (column-sorted L_s S label pass, finish folded in)"
+                           if autotune["label_path"] == "sorted" else "k_label (L_s S label pass, finish folded in)"),
                 "algorithmic_bytes_per_launch": abytes, "avg_launch_us": round(label_us, 2)}
     copy_gbs = gfw.copy_bandwidth(ctx)
     roofline["achievable_copy_gbs"] = round(copy_gbs, 1)

@@ -647,6 +647,14 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
     double acc[KB];
 #pragma unroll
     for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    // FP32 values: the row's entries in groups of 8 from its first, each group summed per class
+    // in FP32 and added in FP64, the last (e - b) mod 8 entries added one by one in FP64 (the
+    // column-sorted pass's order: both passes give the same Q bit for bit).  A group may span
+    // two sub-tiles, so its partial sum lives across them.
+    float grp[KB];
+#pragma unroll
+    for (int c = 0; c < KB; ++c) grp[c] = 0.0f;
+    const int32_t full_end = b + ((e - b) & ~7);
     constexpr int PER = LT / kRowBlock;
     for (int32_t t0 = t_begin; t0 < t_end; t0 += LT) {
         const int cnt = (int)min((int32_t)LT, t_end - t0);
@@ -674,7 +682,49 @@ __device__ __forceinline__ void label_body(const GraphView<T> &gv, const int til
             }
         }
         __syncthreads();
-        if (has_row) {
+        if (has_row && sizeof(T) == 4) {
+            const int32_t pb = max(b, t0), pe = min(e, t0 + cnt);
+            int32_t p = pb;
+            while (p < pe) {
+                if (((p - b) & 7) == 0 && p + 8 <= pe && p + 8 <= full_end) {
+                    int32_t sj[8];
+                    float v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        sj[u] = (int32_t)ls[p + u - t0];
+                        v[u] = (float)lv[p + u - t0];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+#pragma unroll
+                        for (int c = 0; c < KB; ++c) grp[c] += (c == sj[u]) ? v[u] : 0.0f;
+#pragma unroll
+                    for (int c = 0; c < KB; ++c) {
+                        acc[c] += (double)grp[c];
+                        grp[c] = 0.0f;
+                    }
+                    p += 8;
+                } else if (p < full_end) {
+                    const int32_t sj = (int32_t)ls[p - t0];
+                    const float v = (float)lv[p - t0];
+#pragma unroll
+                    for (int c = 0; c < KB; ++c) grp[c] += (c == sj) ? v : 0.0f;
+                    if (((p - b) & 7) == 7)
+#pragma unroll
+                        for (int c = 0; c < KB; ++c) {
+                            acc[c] += (double)grp[c];
+                            grp[c] = 0.0f;
+                        }
+                    ++p;
+                } else {
+                    const int32_t sj = (int32_t)ls[p - t0];
+                    const double v = (double)lv[p - t0];
+#pragma unroll
+                    for (int c = 0; c < KB; ++c) acc[c] += (c == sj) ? v : 0.0;
+                    ++p;
+                }
+            }
+        } else if (has_row) {
             const int32_t pb = max(b, t0), pe = min(e, t0 + cnt);
             int32_t p = pb;
             for (; p + 4 <= pe; p += 4) {
@@ -822,10 +872,24 @@ __device__ __forceinline__ void sorted_row(const GraphView<T> &gv, const int32_t
             v[u] = a[e0 + p + u];
             sj[u] = (int32_t)llab[p + u];
         }
+        if constexpr (sizeof(T) == 4) {
+            // FP32 values: each group of 8 entries summed per class in FP32, the group sums added
+            // in FP64 (the plain pass sums in the same groups)
+            float part[KB];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+            for (int c = 0; c < KB; ++c) part[c] = 0.0f;
 #pragma unroll
-            for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? (double)v[u] : 0.0;
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < KB; ++c) part[c] += (c == sj[u]) ? (float)v[u] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < KB; ++c) acc[c] += (double)part[c];
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < KB; ++c) acc[c] += (c == sj[u]) ? (double)v[u] : 0.0;
+        }
     }
     for (; p + 4 <= re; p += 4) {
         T v[4];
