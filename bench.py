@@ -278,9 +278,10 @@ def bench_many_classes(gfw, ctx, steps: int = 3, n: int = 100_000, K: int = 585)
         ms, cnt = gfw.trace_get(ctx, kid)
         if cnt:
             per[name] = round(1e3 * ms / cnt, 2)
-    # row kernel: U and P read and written (16 n K); for the Q rows the row pointers 4(n+1),
-    # values 4 nnz and neighbour vertices 2 nnz; own vertex read and written (4n); labels (4n)
-    row_bytes = 16 * g.n * K + 4 * (g.n + 1) + 6 * g.nnz + 8 * g.n
+    # row kernel: U (FP32) and P (FP64) read and written (24 n K); for the Q rows the row
+    # pointers 4(n+1), values 4 nnz and neighbour vertices 2 nnz; own vertex read and written
+    # (4n); labels (4n)
+    row_bytes = 24 * g.n * K + 4 * (g.n + 1) + 6 * g.nnz + 8 * g.n
     achieved = row_bytes / (row_us * 1e-6) / 1e9
     acc = float(np.mean(last["labels"].cpu().numpy() == g.truth))
     G.close()
