@@ -71,6 +71,7 @@ struct BatchTables {
     std::vector<GraphView<T>> views;
     std::vector<TileRef> rows[3], plain[3], sorted[3], all_rows;
     int32_t sorted_lds[3] = {}; // dynamic LDS of a bucket's sorted launch: its largest tile
+    int32_t lt[3] = {kLabelTile, kLabelTile, kLabelTile}; // sub-tile of a bucket's plain label launch
     std::vector<TileRef> big_rows[kBigBuckets], big_lab; // K > 16: row tiles per MC bucket, 256-row label tiles
     // host staging of the per-graph control blocks, U_0 pointers and label destinations; kept
     // here so that they outlive the asynchronous copies that read them
@@ -102,6 +103,7 @@ struct BatchTables {
             plain[b].clear();
             sorted[b].clear();
             sorted_lds[b] = 0;
+            lt[b] = kLabelTile;
         }
         all_rows.clear();
         for (int b = 0; b < kBigBuckets; ++b) big_rows[b].clear();
@@ -166,11 +168,19 @@ static void batch_row_launch(BatchTables<T> &bt, int apply_only, hipStream_t st)
 }
 
 template <typename T, int KB>
+static void batch_label_plain(BatchTables<T> &bt, int b, int lt, hipStream_t st)
+{
+    const unsigned nb = (unsigned)bt.plain[b].size();
+    const size_t lds = sizeof(T) * kRowBlock * KB;
+    if (lt == 1024) k_label_batch<T, uint8_t, KB, 1024><<<nb, kRowBlock, lds, st>>>(bt.d_views, bt.d_plain[b]);
+    else if (lt == 4096) k_label_batch<T, uint8_t, KB, 4096><<<nb, kRowBlock, lds, st>>>(bt.d_views, bt.d_plain[b]);
+    else k_label_batch<T, uint8_t, KB, 2048><<<nb, kRowBlock, lds, st>>>(bt.d_views, bt.d_plain[b]);
+}
+
+template <typename T, int KB>
 static void batch_label_bucket(BatchTables<T> &bt, int b, hipStream_t st)
 {
-    if (!bt.plain[b].empty())
-        k_label_batch<T, uint8_t, KB><<<bt.plain[b].size(), kRowBlock, sizeof(T) * kRowBlock * KB, st>>>(bt.d_views,
-                                                                                                       bt.d_plain[b]);
+    if (!bt.plain[b].empty()) batch_label_plain<T, KB>(bt, b, bt.lt[b], st);
     if (!bt.sorted[b].empty())
         k_label_sorted_batch<T, uint8_t, KB><<<bt.sorted[b].size(), kSortedThreads, bt.sorted_lds[b], st>>>(
             bt.d_views, bt.d_sorted[b]);
@@ -386,6 +396,113 @@ static gfw_status_t batch_collect(BatchTables<T> &bt, bool labels, std::vector<d
     return GFW_OK;
 }
 
+// ---- the batch's label-pass autotuner ----------------------------------------------------
+// The plain label pass of each K bucket stages its CSR entries in sub-tiles of 1,024, 2,048 or
+// 4,096 entries: more entries give more gathers in flight per thread, fewer give more
+// workgroups per CU (half the LDS per block).  The sub-tile changes no sum, so the choice is
+// made by measurement: before a batch's first iteration, each size is launched on the batch's
+// own tiles (with every graph's ticket preset so that no timed launch makes a finish), the
+// fastest kept, and the choice cached per (dtype, bucket, log2 of the bucket's tile count).
+// The server uses the cached choices (a server batch is mid-solve, so it is never timed).
+struct TuneKey {
+    int dsz, bucket, size_class;
+    bool operator<(const TuneKey &o) const
+    {
+        return dsz != o.dsz ? dsz < o.dsz : bucket != o.bucket ? bucket < o.bucket : size_class < o.size_class;
+    }
+};
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune_lt;
+
+static TuneKey tune_key(int dsz, int b, size_t tiles)
+{
+    int c = 0;
+    while (((size_t)1 << (c + 1)) <= tiles) ++c;
+    return TuneKey{dsz, b, c};
+}
+
+template <typename T>
+static void batch_use_tuned(BatchTables<T> &bt)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int b = 0; b < 3; ++b) {
+        if (bt.plain[b].empty()) continue;
+        auto it = g_tune_lt.find(tune_key((int)sizeof(T), b, bt.plain[b].size()));
+        if (it != g_tune_lt.end()) bt.lt[b] = it->second;
+    }
+}
+
+template <typename T, int KB>
+static gfw_status_t tune_bucket(BatchTables<T> &bt, int b, hipStream_t st, int *best)
+{
+    static const int sizes[3] = {1024, 2048, 4096};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GFW_HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GFW_E_HIP, "hipEventCreate failed");
+    }
+    float bestms = -1.0f;
+    *best = kLabelTile;
+    gfw_status_t s = GFW_OK;
+    for (int v = 0; v < 3 && s == GFW_OK; ++v) {
+        batch_label_plain<T, KB>(bt, b, sizes[v], st); // warm-up
+        hipError_t e = hipEventRecord(e0, st);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) batch_label_plain<T, KB>(bt, b, sizes[v], st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) s = fail(GFW_E_HIP, "timing the batched label pass failed: %s", hipGetErrorString(e));
+        else if (bestms < 0.0f || ms < bestms) {
+            bestms = ms;
+            *best = sizes[v];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
+}
+
+// Times the plain label pass sizes of every bucket not in the cache (the batch's control
+// blocks are initialised and no iteration has run), then applies the cached choices.
+template <typename T>
+static gfw_status_t batch_tune(BatchTables<T> &bt, hipStream_t st)
+{
+    bool need = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int b = 0; b < 3; ++b)
+            if (!bt.plain[b].empty() && !g_tune_lt.count(tune_key((int)sizeof(T), b, bt.plain[b].size()))) need = true;
+    }
+    if (need) {
+        const int count = (int)bt.views.size();
+        k_set_tickets_batch<T><<<grid_for(count, 256), 256, 0, st>>>(bt.d_views, count, 0x80000000u);
+        gfw_status_t s = GFW_OK;
+        for (int b = 0; b < 3 && s == GFW_OK; ++b) {
+            if (bt.plain[b].empty()) continue;
+            const TuneKey key = tune_key((int)sizeof(T), b, bt.plain[b].size());
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                if (g_tune_lt.count(key)) continue;
+            }
+            int best = kLabelTile;
+            s = b == 0 ? tune_bucket<T, 4>(bt, b, st, &best) : b == 1 ? tune_bucket<T, 8>(bt, b, st, &best)
+                                                                   : tune_bucket<T, 16>(bt, b, st, &best);
+            if (s == GFW_OK) {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                g_tune_lt[key] = best;
+            }
+        }
+        k_set_tickets_batch<T><<<grid_for(count, 256), 256, 0, st>>>(bt.d_views, count, 0u);
+        GFW_HIP_TRY(hipGetLastError());
+        if (s != GFW_OK) return s;
+    }
+    batch_use_tuned<T>(bt);
+    return GFW_OK;
+}
+
 template <typename T>
 static gfw_status_t solve_batched_impl(gfw_context_s *cx, int32_t count, gfw_graph_s *const *gs,
                                        const gfw_params_t *const *prms, void *const *U_out,
@@ -401,6 +518,7 @@ static gfw_status_t solve_batched_impl(gfw_context_s *cx, int32_t count, gfw_gra
     bool watch = false;
     gfw_status_t s = batch_prepare<T>(bt, count, gs, prms, labels_out, st, true, &max_iter, &watch);
     if (s != GFW_OK) return s;
+    if ((s = batch_tune<T>(bt, st)) != GFW_OK) return s;
     // every graph advances in the same launches until its own stop
     if ((s = batch_run<T>(bt, max_iter, watch, st, nullptr, true)) != GFW_OK) return s;
     batch_row_launch<T>(bt, 1, st); // commit the last pending updates
@@ -542,6 +660,7 @@ static gfw_status_t server_step(gfw_server_s *sv, std::vector<ServerRequest *> &
     if ((s = batch_prepare<T>(bt, (int32_t)gs.size(), gs.data(), ps.data(), nullptr, st, false, nullptr, nullptr)) !=
         GFW_OK)
         return s;
+    batch_use_tuned<T>(bt);
     if ((s = batch_run<T>(bt, kMacroIters, false, st, nullptr)) != GFW_OK) return s;
     batch_commit<T>(bt, st);
     // which requests are finished

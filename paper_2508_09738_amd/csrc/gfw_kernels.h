@@ -1340,12 +1340,23 @@ static __global__ void __launch_bounds__(kRowBlock) k_label(GraphView<T> gv)
     label_body<T, ST, KB, kLabelTileSingle>(gv, blockIdx.x);
 }
 
-template <typename T, typename ST, int KB>
+// LT: CSR entries staged per sub-tile (1,024, 2,048 or 4,096, chosen per batch by measurement;
+// the sub-tiles change no sum)
+template <typename T, typename ST, int KB, int LT>
 static __global__ void __launch_bounds__(kRowBlock) k_label_batch(const GraphView<T> *__restrict__ views,
                                                             const TileRef *__restrict__ refs)
 {
     const TileRef r = refs[blockIdx.x];
-    label_body<T, ST, KB, kLabelTile>(views[r.graph], r.tile);
+    label_body<T, ST, KB, LT>(views[r.graph], r.tile);
+}
+
+// The label-pass ticket of every graph of a batch set to `value` (a preset that no pass
+// completes keeps timing launches from making a finish; 0 restores it).
+template <typename T>
+static __global__ void k_set_tickets_batch(const GraphView<T> *__restrict__ views, int32_t count, unsigned int value)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) *views[i].ticket = value;
 }
 
 template <typename T, typename ST, int KB>
