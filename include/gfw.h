@@ -189,7 +189,9 @@ GFW_API gfw_status_t gfw_graph_create(gfw_context_t ctx, const gfw_problem_t *p,
  * dense.  The library never forms it: each product with L_s = I - D^{-1/2} W D^{-1/2} sums
  * the weights from the features (the paper uses an NFFT-based fast summation for these
  * products, Section 5.1).  method: GFW_GAUSS_EXACT forms every weight (O(n^2 K) per product,
- * FP64 sums, 1 <= d <= 8); GFW_GAUSS_GRID, for 1 <= d <= 3, gathers the points onto a grid of
+ * 1 <= d <= 8; each weight formed in the graph's dtype — an FP32 graph from its FP32 features
+ * with the FP32 exponential, as an FP32 CSR graph stores FP32 values — and summed in FP64);
+ * GFW_GAUSS_GRID, for 1 <= d <= 3, gathers the points onto a grid of
  * spacing sigma / 2 with a Gaussian window, convolves the grid with a Gaussian and
  * interpolates back, the widths chosen so that the composite kernel is the Gaussian of width
  * sigma (windows cut at 5 widths: a relative error of about 1e-7 per product; O((n + cells)
@@ -197,8 +199,10 @@ GFW_API gfw_status_t gfw_graph_create(gfw_context_t ctx, const gfw_problem_t *p,
  * GFW_E_UNSUPPORTED when the grid would exceed 2^26 / KP cells, KP = K rounded up to 4, 8 or
  * 16), and makes a node whose degree
  * is at most 1e-6 isolated;
- * GFW_GAUSS_AUTO takes the grid when d <= 3 and its estimated work is below n^2, else the
- * exact sums.  The graph is then used by
+ * GFW_GAUSS_AUTO takes the method of the smaller modelled time (the grid only when d <= 3 and
+ * it fits): the grid at about 7.3 ps per unit of its work estimate (point and cell visits,
+ * (n + cells) 14^d) plus 20 us, the exact sums at 0.8 ps (FP32 graph) or 1.3 ps (FP64) per
+ * pair, rates measured on an MI355X.  The graph is then used by
  * gfw_solve, gfw_objective, gfw_objective_noalloc and gfw_spmm like any other (K <= 16);
  * gfw_solve_batched and the server return GFW_E_UNSUPPORTED for it.  features: n x d of dtype,
  * row-major, finite (GFW_E_GRAPH otherwise); sigma > 0 and finite.  Labels as in

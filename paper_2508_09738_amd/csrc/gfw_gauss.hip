@@ -20,6 +20,7 @@ struct GaussGraph {
     int32_t chunks = 1;          // exact method: chunks of the points summed apart
     int64_t chunk = 0;           // points per chunk
     double *x = nullptr;         // n x d features (FP64)
+    float *xf = nullptr;         // the same in FP32, for an FP32 graph's exact sums
     double *dinv = nullptr;      // n
     int32_t *cell_start = nullptr, *cell_pts = nullptr, *pt_cell = nullptr;
     double *V = nullptr, *R = nullptr; // n x kp
@@ -33,6 +34,7 @@ void gauss_free(GaussGraph *gg)
 {
     if (!gg) return;
     dfree(gg->x);
+    dfree(gg->xf);
     dfree(gg->dinv);
     dfree(gg->cell_start);
     dfree(gg->cell_pts);
@@ -53,7 +55,9 @@ static void apply_exact(const GaussGraph &gg, const double *V, double *R, const 
 {
     const GaussView &v = gg.view;
     double *out = gg.chunks > 1 ? gg.Rp : R;
-    k_gauss_exact<D, KP><<<dim3((unsigned)cdiv(v.n, kRowBlock), gg.chunks), kRowBlock, 0, st>>>(v, gg.chunk, V, out, ctl);
+    const dim3 grid((unsigned)cdiv(v.n, kRowBlock), gg.chunks);
+    if (gg.xf) k_gauss_exact<D, KP, float><<<grid, kRowBlock, 0, st>>>(v, gg.chunk, V, out, ctl);
+    else k_gauss_exact<D, KP, double><<<grid, kRowBlock, 0, st>>>(v, gg.chunk, V, out, ctl);
     if (gg.chunks > 1)
         k_gauss_chunks_sum<<<grid_for(v.n * KP, 256, 4096), 256, 0, st>>>(v.n * KP, gg.chunks, gg.Rp, R, ctl);
 }
@@ -259,7 +263,10 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
     for (double v : xh)
         if (!std::isfinite(v)) return fail(GFW_E_GRAPH, "a feature is not finite");
 
-    // method: exact, grid, or the one of smaller estimated work
+    // method: exact, grid, or the one of smaller modelled time.  Rates measured on gfx950 at K <= 4
+    // (both methods scale alike with KP): the grid about 7.3 ps per unit of its work estimate plus
+    // about 20 us of fixed launches; the exact sums 0.8 ps per pair with FP32 weights, 1.3 ps with
+    // FP64 ones.
     int method = p->method;
     GridPlan gp;
     if (method != GFW_GAUSS_EXACT && d <= kGridMaxDim) gp = plan_grid(xh, n, d, p->sigma);
@@ -269,8 +276,11 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
         return fail(GFW_E_UNSUPPORTED, "the grid for sigma = %g over these features has %lld cells (at most %lld for K "
                     "= %d); use the exact method or a larger sigma", p->sigma, (long long)gp.v.ncells,
                     (long long)(kGridMaxElems / KP), K);
-    if (method == GFW_GAUSS_AUTO)
-        method = (grid_fits && gp.work < (double)n * (double)n) ? GFW_GAUSS_GRID : GFW_GAUSS_EXACT;
+    if (method == GFW_GAUSS_AUTO) {
+        const double grid_ps = 7.3 * gp.work + 2e7;
+        const double exact_ps = (p->dtype == GFW_F32 ? 0.8 : 1.3) * (double)n * (double)n;
+        method = (grid_fits && grid_ps < exact_ps) ? GFW_GAUSS_GRID : GFW_GAUSS_EXACT;
+    }
 
     gfw_graph_s *g = new (std::nothrow) gfw_graph_s();
     if (!g) return fail(GFW_E_NOMEM, "host allocation failed");
@@ -307,6 +317,15 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
     if ((s = dalloc((void **)&gg.V, 8 * nK)) != GFW_OK) return s;
     if ((s = dalloc((void **)&gg.R, 8 * nK)) != GFW_OK) return s;
     GFW_HIP_TRY(hipMemcpyAsync(gg.x, xh.data(), 8 * xh.size(), hipMemcpyHostToDevice, st));
+    std::vector<float> xfh;
+    if (method == GFW_GAUSS_EXACT && p->dtype == GFW_F32) {
+        // the FP32 features the caller gave (an FP32 graph forms its weights in FP32)
+        xfh.resize(xh.size());
+        for (size_t t = 0; t < xh.size(); ++t) xfh[t] = (float)xh[t];
+        if ((s = dalloc((void **)&gg.xf, 4 * xfh.size())) != GFW_OK) return s;
+        GFW_HIP_TRY(hipMemcpyAsync(gg.xf, xfh.data(), 4 * xfh.size(), hipMemcpyHostToDevice, st));
+        GFW_HIP_TRY(hipStreamSynchronize(st)); // before xfh can go out of scope
+    }
 
     GaussView &v = gg.view;
     if (method == GFW_GAUSS_GRID) {
@@ -359,6 +378,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
     v.d = d;
     v.inv2s2 = 1.0 / (2.0 * p->sigma * p->sigma);
     v.x = gg.x;
+    v.xf = gg.xf;
     v.dinv = gg.dinv;
     v.cell_start = gg.cell_start;
     v.cell_pts = gg.cell_pts;

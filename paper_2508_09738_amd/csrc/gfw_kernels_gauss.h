@@ -44,6 +44,7 @@ struct GaussView {
     int32_t d;
     double inv2s2;               // 1 / (2 sigma^2)
     const double *x;             // n x d features
+    const float *xf;             // the features in FP32 (FP32 graphs: their weights are FP32)
     const double *dinv;          // d_i^{-1/2} (0 for an isolated node)
     // grid method
     int32_t gdim[kGridMaxDim];   // cells per dimension (1 past d)
@@ -67,8 +68,11 @@ struct GaussView {
 // chunk y sums its points in increasing order into Rp[y], and k_gauss_chunks_sum adds the
 // chunks in increasing order.  Every thread of a workgroup visits the same point j at the
 // same time, so x_j and V_j are uniform: they are read with scalar loads and broadcast from
-// scalar registers (no LDS staging).  D = d for d <= 3, else D = 0 (any d <= 8).
-template <int D, int KP>
+// scalar registers (no LDS staging).  D = d for d <= 3, else D = 0 (any d <= 8).  W: the
+// type each weight is formed in — the graph's dtype (an FP32 graph forms its weights from the
+// FP32 features with the FP32 exponential, as an FP32 CSR graph stores its values in FP32); the
+// sums are FP64 either way.
+template <int D, int KP, typename W>
 static __global__ void __launch_bounds__(kRowBlock) k_gauss_exact(GaussView gv, int64_t chunk,
                                                                    const double *__restrict__ V,
                                                                    double *__restrict__ Rp, const Ctl *__restrict__ ctl)
@@ -78,25 +82,27 @@ static __global__ void __launch_bounds__(kRowBlock) k_gauss_exact(GaussView gv, 
     const int d = D > 0 ? D : gv.d;
     const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
     const int64_t ii = i < gv.n ? i : gv.n - 1; // rows past n compute row n - 1 and store nothing
-    const double *__restrict__ x = gv.x;
-    double xi[DM];
+    const W *__restrict__ x;
+    if constexpr (sizeof(W) == 4) x = gv.xf;
+    else x = gv.x;
+    W xi[DM];
 #pragma unroll
-    for (int q = 0; q < DM; ++q) xi[q] = q < d ? x[ii * d + q] : 0.0;
+    for (int q = 0; q < DM; ++q) xi[q] = q < d ? x[ii * d + q] : (W)0;
     double acc[KP];
 #pragma unroll
     for (int c = 0; c < KP; ++c) acc[c] = 0.0;
-    const double nscale = -gv.inv2s2;
+    const W nscale = (W)(-gv.inv2s2);
     const int64_t jb = (int64_t)blockIdx.y * chunk, je = min(gv.n, jb + chunk);
 #pragma unroll 2
     for (int64_t j = jb; j < je; ++j) {
-        double r2 = 0.0;
+        W r2 = (W)0;
 #pragma unroll
         for (int q = 0; q < DM; ++q)
             if (q < d) {
-                const double df = xi[q] - x[j * d + q];
+                const W df = xi[q] - x[j * d + q];
                 r2 = fma(df, df, r2);
             }
-        double w = exp(r2 * nscale);
+        double w = (double)exp(r2 * nscale);
         w = j == ii ? 0.0 : w;
 #pragma unroll
         for (int c = 0; c < KP; ++c) acc[c] = fma(w, V[j * KP + c], acc[c]);
