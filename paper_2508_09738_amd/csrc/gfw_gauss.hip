@@ -26,7 +26,9 @@ struct GaussGraph {
     double *V = nullptr, *R = nullptr; // n x kp
     double *Rp = nullptr;        // chunks x n x kp (exact method, chunks > 1)
     double *G0 = nullptr, *G1 = nullptr; // ncells x kp (grid method)
-    double *Gp = nullptr;        // kGridWin x ncells x kp: the gather's slices (grid method)
+    double *Tp = nullptr;        // nparts x 64 x kp: the gather's part sums (grid method)
+    GatherPart *parts = nullptr; // the gather's work list
+    int32_t *part_first = nullptr; // per gather task, its first part
     double *xs = nullptr, *Vs = nullptr; // n x d features and n x kp V in binned order (grid method)
 };
 
@@ -44,7 +46,9 @@ void gauss_free(GaussGraph *gg)
     dfree(gg->Rp);
     dfree(gg->G0);
     dfree(gg->G1);
-    dfree(gg->Gp);
+    dfree(gg->Tp);
+    dfree(gg->parts);
+    dfree(gg->part_first);
     dfree(gg->xs);
     dfree(gg->Vs);
     delete gg;
@@ -68,8 +72,9 @@ static void apply_grid(const GaussGraph &gg, const double *V, double *R, const C
     const GaussView &v = gg.view;
     const unsigned nc = (unsigned)cdiv(v.ncells, kRowBlock);
     k_grid_bin_v<KP><<<grid_for(v.n * KP, kRowBlock, 4096), kRowBlock, 0, st>>>(v, V, gg.Vs, ctl);
-    k_grid_gather<D, KP><<<dim3(nc, kGridWin), kRowBlock, 0, st>>>(v, gg.Vs, gg.Gp, ctl);
-    k_gauss_chunks_sum<<<grid_for(v.ncells * KP, 256, 8192), 256, 0, st>>>(v.ncells * KP, kGridWin, gg.Gp, gg.G0, ctl);
+    if (v.nparts > 0) // one wavefront per part
+        k_grid_gather<D, KP><<<(unsigned)cdiv(v.nparts, kRowBlock / 64), kRowBlock, 0, st>>>(v, gg.Vs, gg.Tp, ctl);
+    k_grid_parts_sum<D, KP><<<nc, kRowBlock, 0, st>>>(v, gg.Tp, gg.G0, ctl);
     const double *in = gg.G0;
     double *out = gg.G1;
     for (int q = 0; q < D; ++q) {
@@ -78,7 +83,7 @@ static void apply_grid(const GaussGraph &gg, const double *V, double *R, const C
         out = const_cast<double *>(in);
         in = done;
     }
-    k_grid_interp<D, KP><<<(unsigned)cdiv(v.n, kRowBlock), kRowBlock, 0, st>>>(v, in, V, R, ctl);
+    k_grid_interp<D, KP><<<(unsigned)cdiv(v.n, 64), kInterpThreads, 0, st>>>(v, in, V, R, ctl);
 }
 
 template <int KP>
@@ -208,6 +213,56 @@ GridPlan plan_grid(const std::vector<double> &xh, int64_t n, int d, double sigma
     return gp;
 }
 
+// The grid gather's work list: every task's union points (its rows in order, each row's points
+// in binned order) cut into parts of at most `cap` points; first[t] is task t's first part.
+// cap is at least 256 and large enough that the parts number about 16 wavefronts per SIMD.
+template <int D>
+void plan_gather(const GaussView &v, const std::vector<int32_t> &start, int num_cu, std::vector<GatherPart> &parts,
+                 std::vector<int32_t> &first)
+{
+    const int64_t tasks = grid_tasks<D>(v.gdim);
+    std::vector<int64_t> rows_of;
+    int64_t total = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t cap = std::max<int64_t>(256, total / (16LL * 4 * std::max(num_cu, 1)));
+        if (pass == 1) first.assign((size_t)tasks + 1, 0);
+        for (int64_t t = 0; t < tasks; ++t) {
+            if (pass == 1) first[(size_t)t] = (int32_t)parts.size();
+            const GatherTask g = gather_task<D>(v.gdim, v.gstride, t, 0);
+            if (!g.in_grid) continue;
+            GatherPart cur{(int32_t)t, 0, 0, 0};
+            bool open = false;
+            for (int r = 0; r < gather_rows<D>(g); ++r) {
+                int b1, b2;
+                int64_t row;
+                gather_row<D>(g, v.gstride, r, b1, b2, row);
+                int64_t c = (int64_t)start[(size_t)(row + g.uhi[0] + 1)] - start[(size_t)(row + g.ulo[0])];
+                if (pass == 0) {
+                    total += c;
+                    continue;
+                }
+                int64_t off = 0;
+                while (c > 0) {
+                    if (!open) {
+                        cur = GatherPart{(int32_t)t, r, (int32_t)off, 0};
+                        open = true;
+                    }
+                    const int64_t take = std::min(c, cap - cur.count);
+                    cur.count += (int32_t)take;
+                    c -= take;
+                    off += take;
+                    if (cur.count == cap) {
+                        parts.push_back(cur);
+                        open = false;
+                    }
+                }
+            }
+            if (open) parts.push_back(cur);
+        }
+        if (pass == 1) first[(size_t)tasks] = (int32_t)parts.size();
+    }
+}
+
 template <typename T>
 void features_to_f64(const void *src, int64_t count, std::vector<double> &out)
 {
@@ -264,7 +319,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
         if (!std::isfinite(v)) return fail(GFW_E_GRAPH, "a feature is not finite");
 
     // method: exact, grid, or the one of smaller modelled time.  Rates measured on gfx950 at K <= 4
-    // (both methods scale alike with KP): the grid about 7.3 ps per unit of its work estimate plus
+    // (both methods scale alike with KP): the grid about 2.2 ps per unit of its work estimate plus
     // about 20 us of fixed launches; the exact sums 0.8 ps per pair with FP32 weights, 1.3 ps with
     // FP64 ones.
     int method = p->method;
@@ -277,7 +332,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
                     "= %d); use the exact method or a larger sigma", p->sigma, (long long)gp.v.ncells,
                     (long long)(kGridMaxElems / KP), K);
     if (method == GFW_GAUSS_AUTO) {
-        const double grid_ps = 7.3 * gp.work + 2e7;
+        const double grid_ps = 2.2 * gp.work + 2e7;
         const double exact_ps = (p->dtype == GFW_F32 ? 0.8 : 1.3) * (double)n * (double)n;
         method = (grid_fits && grid_ps < exact_ps) ? GFW_GAUSS_GRID : GFW_GAUSS_EXACT;
     }
@@ -352,7 +407,18 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
         if ((s = dalloc((void **)&gg.pt_cell, 4 * (size_t)n)) != GFW_OK) return s;
         if ((s = dalloc((void **)&gg.G0, 8 * (size_t)v.ncells * KP)) != GFW_OK) return s;
         if ((s = dalloc((void **)&gg.G1, 8 * (size_t)v.ncells * KP)) != GFW_OK) return s;
-        if ((s = dalloc((void **)&gg.Gp, 8 * (size_t)v.ncells * KP * kGridWin)) != GFW_OK) return s;
+        std::vector<GatherPart> parts;
+        std::vector<int32_t> first;
+        if (d == 1) plan_gather<1>(v, start, ctx->num_cu, parts, first);
+        else if (d == 2) plan_gather<2>(v, start, ctx->num_cu, parts, first);
+        else plan_gather<3>(v, start, ctx->num_cu, parts, first);
+        v.nparts = (int64_t)parts.size();
+        if ((s = dalloc((void **)&gg.parts, sizeof(GatherPart) * parts.size())) != GFW_OK) return s;
+        if ((s = dalloc((void **)&gg.part_first, 4 * first.size())) != GFW_OK) return s;
+        if ((s = dalloc((void **)&gg.Tp, 8 * (size_t)v.nparts * 64 * KP)) != GFW_OK) return s;
+        GFW_HIP_TRY(hipMemcpyAsync(gg.parts, parts.data(), sizeof(GatherPart) * parts.size(), hipMemcpyHostToDevice, st));
+        GFW_HIP_TRY(hipMemcpyAsync(gg.part_first, first.data(), 4 * first.size(), hipMemcpyHostToDevice, st));
+        GFW_HIP_TRY(hipStreamSynchronize(st)); // parts and first go out of scope
         if ((s = dalloc((void **)&gg.xs, 8 * xh.size())) != GFW_OK) return s;
         if ((s = dalloc((void **)&gg.Vs, 8 * nK)) != GFW_OK) return s;
         std::vector<double> xsh(xh.size());
@@ -362,7 +428,10 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
         GFW_HIP_TRY(hipStreamSynchronize(st));
         GFW_HIP_TRY(hipMemcpyAsync(gg.cell_start, start.data(), 4 * start.size(), hipMemcpyHostToDevice, st));
         GFW_HIP_TRY(hipMemcpyAsync(gg.cell_pts, pts.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
-        GFW_HIP_TRY(hipMemcpyAsync(gg.pt_cell, pc.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
+        // the points' cells in binned order
+        std::vector<int32_t> pcb((size_t)n);
+        for (int64_t pp = 0; pp < n; ++pp) pcb[(size_t)pp] = pc[(size_t)pts[(size_t)pp]];
+        GFW_HIP_TRY(hipMemcpyAsync(gg.pt_cell, pcb.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st));
         GFW_HIP_TRY(hipStreamSynchronize(st)); // the host vectors go out of scope
     } else {
         // chunks of the points summed apart: about 8 waves per SIMD over the rows, each chunk
@@ -384,6 +453,8 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
     v.cell_pts = gg.cell_pts;
     v.xs = gg.xs;
     v.pt_cell = gg.pt_cell;
+    v.parts = gg.parts;
+    v.part_first = gg.part_first;
 
     // labels (checked on the device: range, repeats, classes)
     unsigned int *flags = nullptr;

@@ -4,8 +4,9 @@
 // Gaussian similarity in Section 1), no self-loops.  The n x n matrix is never formed: every
 // product R = W V (V n x K) is summed from the features, by one of two methods.
 //
-//  * exact: R_i = sum_{j != i} w_ij V_j, the weights formed where they are used (FP64);
-//    O(n^2 K), the reference operator and the right one for images of a few 10^4 pixels.
+//  * exact: R_i = sum_{j != i} w_ij V_j, the weights formed where they are used (in the
+//    graph's dtype, summed in FP64); O(n^2 K), the reference operator and the right one for
+//    images of a few 10^4 pixels.
 //  * grid (d <= 3): a fast summation in the spirit of the NFFT-based one the paper uses.
 //    With unnormalised Gaussians g_w(r) = exp(-r^2 / (2 w^2)) and sigma^2 = 2 tau^2 + s^2,
 //    the convolution g_tau * g_s * g_tau is (2 pi tau^2 s / sigma) g_sigma per dimension, so
@@ -58,7 +59,16 @@ struct GaussView {
     const int32_t *cell_start;   // ncells + 1: the points of cell a are cell_pts[cell_start[a] ..)
     const int32_t *cell_pts;
     const double *xs;            // n x d: the features in binned order (xs[pp] = x[cell_pts[pp]])
-    const int32_t *pt_cell;      // n: the linear cell of each point (the binning above, point-wise)
+    const int32_t *pt_cell;      // n: the linear cell of each point in binned order (pt_cell[pp] = cell of cell_pts[pp])
+    const struct GatherPart *parts; // the gather's work list (grid method)
+    const int32_t *part_first;   // per gather task, its first part (tasks + 1 entries)
+    int64_t nparts;
+};
+
+// One wavefront's share of the grid gather: `count` consecutive points of task `task`'s union
+// box, starting `off` points into its union row `row`.
+struct GatherPart {
+    int32_t task, row, off, count;
 };
 
 // ---- exact method -------------------------------------------------------------------
@@ -146,66 +156,208 @@ static __global__ void __launch_bounds__(kRowBlock) k_grid_bin_v(GaussView gv, c
 // G0[a] = sum over the points p binned in the cells b with a - kGridRW - 1 <= b <= a + kGridRW
 // of g_tau(a - x_p) V_p (Vs: V in binned order, stride KP): the mirror of the grid points k_grid_interp visits
 // around a point's cell, so that both truncate the window on the same point-grid pairs.
-// Image colours crowd into a few clusters, so a cell near a cluster's centre has most of the
-// cluster in its box: the box is cut into its kGridWin slices along the last dimension, one
-// thread per (cell, slice) (blockIdx.y = slice), each writing its partial sum to Gp[slice]
-// (ncells x KP); k_gauss_chunks_sum adds the slices in increasing order.  Within a slice, the
-// cells with the same coordinates past dimension 0 are consecutive in the linear order, so
-// their points form one range of the binned order: the slice walks its rows in increasing
-// order and each row's points in binned order, reading the features and V of the points
-// contiguously (xs, Vs).
+// The cells are taken in blocks of 64 (4 x 4 x 4, 8 x 8 or 64 of them by dimension), and the
+// box of a cell is cut into its kGridWin slices along the last dimension L.  A task is a (block,
+// last-dimension index bl) pair: the union of the block's boxes on that slice, whose rows (the
+// cells with the same coordinates past dimension 0, consecutive in the linear order) hold
+// consecutive ranges of the binned order.  Image colours crowd into a few clusters, so the
+// tasks' point counts differ by orders of magnitude: each task is cut into parts of at most a
+// fixed number of points (the work list, planned when the graph is made), one wavefront per part.
+// All 64 lanes visit the same point at the same time, so the point's features and V are uniform
+// (scalar loads, broadcast from scalar registers), and each lane adds the point only if it lies
+// in its own cell's box.  Part p writes its 64 lane sums to Tp[p] (64 x KP); k_grid_parts_sum
+// adds, for each cell, its slices in increasing order and each slice's parts in increasing order.
+template <int D> struct GridBlock {
+    static constexpr int b0 = D == 1 ? 64 : D == 2 ? 8 : 4, b1 = D == 1 ? 1 : D == 2 ? 8 : 4, b2 = D == 3 ? 4 : 1;
+    static constexpr int bl = D == 1 ? b0 : D == 2 ? b1 : b2; // block extent along the last dimension
+    static constexpr int slices = bl + kGridWin - 1;          // last-dimension indices a block's boxes reach
+};
+
+// The geometry of gather task `task` for the lane with offsets `off` in its block: the lane's
+// cell (valid when inside the grid), its slice index y (mine: the cell's box reaches bl), the
+// union of the block's boxes (ulo..uhi, uniform) and the lane's own box (llo..lhi), both
+// clipped to the grid, along L both the one index bl.  Used by the host to plan the parts.
+struct GatherTask {
+    int ai[kGridMaxDim], ulo[kGridMaxDim], uhi[kGridMaxDim], llo[kGridMaxDim], lhi[kGridMaxDim];
+    int bl, y;
+    int64_t a;
+    bool valid, mine, in_grid;
+};
+
+template <int D>
+__host__ __device__ inline GatherTask gather_task(const int32_t (&gdim)[kGridMaxDim], const int64_t (&gstride)[kGridMaxDim],
+                                                  int64_t task, int lane)
+{
+    using B = GridBlock<D>;
+    constexpr int L = D - 1;
+    GatherTask g{};
+    const int64_t blk = task / B::slices;
+    const int ys = (int)(task - blk * B::slices);
+    const int nb0 = (gdim[0] + B::b0 - 1) / B::b0, nb1 = (gdim[1] + B::b1 - 1) / B::b1;
+    const int bk[kGridMaxDim] = {(int)(blk % nb0), (int)((blk / nb0) % nb1), (int)(blk / ((int64_t)nb0 * nb1))};
+    const int bsz[kGridMaxDim] = {B::b0, B::b1, B::b2};
+    const int off[kGridMaxDim] = {lane % B::b0, (lane / B::b0) % B::b1, lane / (B::b0 * B::b1)};
+    g.bl = bk[L] * bsz[L] - kGridRW - 1 + ys;
+    g.in_grid = g.bl >= 0 && g.bl < gdim[L];
+    g.valid = true;
+    g.a = 0;
+    for (int q = 0; q < kGridMaxDim; ++q) {
+        g.ai[q] = 0;
+        g.ulo[q] = g.uhi[q] = g.llo[q] = g.lhi[q] = 0;
+    }
+    for (int q = 0; q < D; ++q) {
+        g.ai[q] = bk[q] * bsz[q] + off[q];
+        g.valid = g.valid && g.ai[q] < gdim[q];
+        g.a += (int64_t)g.ai[q] * gstride[q];
+        if (q == L) {
+            g.ulo[q] = g.uhi[q] = g.llo[q] = g.lhi[q] = g.bl;
+        } else {
+            g.ulo[q] = bk[q] * bsz[q] - kGridRW - 1 > 0 ? bk[q] * bsz[q] - kGridRW - 1 : 0;
+            g.uhi[q] = bk[q] * bsz[q] + bsz[q] - 1 + kGridRW < gdim[q] - 1 ? bk[q] * bsz[q] + bsz[q] - 1 + kGridRW
+                                                                          : gdim[q] - 1;
+            g.llo[q] = g.ai[q] - kGridRW - 1 > 0 ? g.ai[q] - kGridRW - 1 : 0;
+            g.lhi[q] = g.ai[q] + kGridRW < gdim[q] - 1 ? g.ai[q] + kGridRW : gdim[q] - 1;
+        }
+    }
+    g.y = g.bl - (g.ai[L] - kGridRW - 1);
+    g.mine = g.valid && g.y >= 0 && g.y < kGridWin;
+    return g;
+}
+
+// Union rows of a task: for d = 3 the rows b1 = ulo[1] .. uhi[1] of slice b2 = bl; otherwise the
+// one row of the slice.  row_lin is the linear index of the row's cell 0.
+template <int D> __host__ __device__ inline int gather_rows(const GatherTask &g) { return D == 3 ? g.uhi[1] - g.ulo[1] + 1 : 1; }
+
+template <int D>
+__host__ __device__ inline void gather_row(const GatherTask &g, const int64_t (&gstride)[kGridMaxDim], int r, int &b1, int &b2,
+                                           int64_t &row_lin)
+{
+    b1 = D == 3 ? g.ulo[1] + r : D == 2 ? g.bl : 0;
+    b2 = D == 3 ? g.bl : 0;
+    row_lin = (int64_t)b1 * gstride[1] + (int64_t)b2 * gstride[2];
+}
+
+template <int D> __host__ __device__ inline int64_t grid_tasks(const int32_t (&gdim)[kGridMaxDim])
+{
+    using B = GridBlock<D>;
+    return (int64_t)((gdim[0] + B::b0 - 1) / B::b0) * ((gdim[1] + B::b1 - 1) / B::b1) * ((gdim[2] + B::b2 - 1) / B::b2) *
+           B::slices;
+}
+
+// acc += g_tau(a - x) v when `in` (the arithmetic of one point's term of the gather)
+template <int D, int KP>
+__device__ __forceinline__ void gather_term(const double (&ac)[kGridMaxDim], const double (&x)[D], const double (&v)[KP],
+                                            double inv2t2, bool in, double (&acc)[KP])
+{
+    double r2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        const double df = ac[q] - x[q];
+        r2 = fma(df, df, r2);
+    }
+    const double w = exp(-r2 * inv2t2);
+#pragma unroll
+    for (int c = 0; c < KP; ++c) {
+        const double t = fma(w, v[c], acc[c]);
+        acc[c] = in ? t : acc[c];
+    }
+}
+
 template <int D, int KP>
 static __global__ void __launch_bounds__(kRowBlock) k_grid_gather(GaussView gv, const double *__restrict__ Vs,
-                                                                   double *__restrict__ Gp, const Ctl *__restrict__ ctl)
+                                                                   double *__restrict__ Tp, const Ctl *__restrict__ ctl)
 {
+    if (ctl && !ctl->active) return;
+    const int64_t p = (int64_t)blockIdx.x * (kRowBlock / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    if (p >= gv.nparts) return;
+    const GatherPart part = gv.parts[p];
+    const int lane = (int)threadIdx.x & 63;
+    const GatherTask g = gather_task<D>(gv.gdim, gv.gstride, part.task, lane);
+    double ac[kGridMaxDim] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < D; ++q) ac[q] = grid_coord(gv, q, g.ai[q]);
+    const double *__restrict__ xs = gv.xs;
+    const int32_t *__restrict__ cs = gv.cell_start;
+    double acc[KP];
+#pragma unroll
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
+    const int nrows = gather_rows<D>(g);
+    int32_t left = part.count, skip = part.off;
+    for (int r = part.row; r < nrows && left > 0; ++r) {
+        int b1, b2;
+        int64_t row;
+        gather_row<D>(g, gv.gstride, r, b1, b2, row);
+        const int32_t P0 = cs[row + g.ulo[0]] + skip;
+        const int32_t P1 = (int32_t)min((int64_t)cs[row + g.uhi[0] + 1], (int64_t)P0 + left);
+        skip = 0;
+        if (P0 >= P1) continue;
+        left -= P1 - P0;
+        const bool on = g.mine && b1 >= g.llo[1] && b1 <= g.lhi[1] && b2 >= g.llo[2] && b2 <= g.lhi[2];
+        const int32_t p0 = on ? cs[row + g.llo[0]] : 0, p1 = on ? cs[row + g.lhi[0] + 1] : 0;
+        // the points' data are loaded for batches of 4 points ahead of their use (every lane
+        // computes every point's term; a lane keeps it only for the points of its own box)
+        int32_t pp = P0;
+        for (; pp + 4 <= P1; pp += 4) {
+            double xb[4][D], vb[4][KP];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int q = 0; q < D; ++q) xb[u][q] = xs[(int64_t)(pp + u) * D + q];
+#pragma unroll
+                for (int c = 0; c < KP; ++c) vb[u][c] = Vs[(int64_t)(pp + u) * KP + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) gather_term<D, KP>(ac, xb[u], vb[u], gv.inv2t2, pp + u >= p0 && pp + u < p1, acc);
+        }
+        for (; pp < P1; ++pp) {
+            double xb[D], vb[KP];
+#pragma unroll
+            for (int q = 0; q < D; ++q) xb[q] = xs[(int64_t)pp * D + q];
+#pragma unroll
+            for (int c = 0; c < KP; ++c) vb[c] = Vs[(int64_t)pp * KP + c];
+            gather_term<D, KP>(ac, xb, vb, gv.inv2t2, pp >= p0 && pp < p1, acc);
+        }
+    }
+    double *__restrict__ out = Tp + (p * 64 + lane) * KP;
+#pragma unroll
+    for (int c = 0; c < KP; ++c) out[c] = acc[c];
+}
+
+// G0[a] = sum over the slices y = 0 .. kGridWin - 1 of cell a (in that order) of the parts of the
+// slice's task (in order).  One thread per cell.
+template <int D, int KP>
+static __global__ void __launch_bounds__(kRowBlock) k_grid_parts_sum(GaussView gv, const double *__restrict__ Tp,
+                                                                      double *__restrict__ G0, const Ctl *__restrict__ ctl)
+{
+    using B = GridBlock<D>;
+    constexpr int L = D - 1;
     if (ctl && !ctl->active) return;
     const int64_t a = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
     if (a >= gv.ncells) return;
     int ai[kGridMaxDim] = {0, 0, 0};
-    double ac[kGridMaxDim] = {0.0, 0.0, 0.0};
     int64_t rem = a;
 #pragma unroll
     for (int q = D - 1; q >= 0; --q) {
         ai[q] = (int)(rem / gv.gstride[q]);
         rem -= (int64_t)ai[q] * gv.gstride[q];
-        ac[q] = grid_coord(gv, q, ai[q]);
     }
-    int lo[kGridMaxDim] = {0, 0, 0}, hi[kGridMaxDim] = {0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-        lo[q] = max(ai[q] - kGridRW - 1, 0);
-        hi[q] = min(ai[q] + kGridRW, gv.gdim[q] - 1);
-    }
-    // this thread's slice: one index of the last dimension
-    const int bs = ai[D - 1] - kGridRW - 1 + (int)blockIdx.y;
-    const bool in_grid = bs >= 0 && bs < gv.gdim[D - 1];
-    lo[D - 1] = bs;
-    hi[D - 1] = bs;
-    const double *__restrict__ xs = gv.xs;
+    const int bsz[kGridMaxDim] = {B::b0, B::b1, B::b2};
+    const int nb0 = (gv.gdim[0] + B::b0 - 1) / B::b0, nb1 = (gv.gdim[1] + B::b1 - 1) / B::b1;
+    const int bk[kGridMaxDim] = {ai[0] / B::b0, ai[1] / B::b1, ai[2] / B::b2};
+    const int lane = ai[0] % B::b0 + B::b0 * (ai[1] % B::b1 + B::b1 * (ai[2] % B::b2));
+    const int64_t blk = bk[0] + (int64_t)nb0 * (bk[1] + (int64_t)nb1 * bk[2]);
     double acc[KP];
 #pragma unroll
     for (int c = 0; c < KP; ++c) acc[c] = 0.0;
-    if (in_grid) // a slice past the grid's edge is empty
-    for (int b2 = lo[2]; b2 <= hi[2]; ++b2)
-        for (int b1 = lo[1]; b1 <= hi[1]; ++b1) {
-            const int64_t row = (int64_t)b1 * gv.gstride[1] + (int64_t)b2 * gv.gstride[2];
-            const int32_t p0 = gv.cell_start[row + lo[0]], p1 = gv.cell_start[row + hi[0] + 1];
-#pragma unroll 4
-            for (int64_t pp = p0; pp < p1; ++pp) {
-                double r2 = 0.0;
+    for (int y = 0; y < kGridWin; ++y) {
+        const int ys = (ai[L] - kGridRW - 1 + y) - (bk[L] * bsz[L] - kGridRW - 1);
+        const int64_t t = blk * B::slices + ys;
+        for (int32_t q = gv.part_first[t]; q < gv.part_first[t + 1]; ++q)
 #pragma unroll
-                for (int q = 0; q < D; ++q) {
-                    const double df = ac[q] - xs[pp * D + q];
-                    r2 = fma(df, df, r2);
-                }
-                const double w = exp(-r2 * gv.inv2t2);
+            for (int c = 0; c < KP; ++c) acc[c] += Tp[((int64_t)q * 64 + lane) * KP + c];
+    }
 #pragma unroll
-                for (int c = 0; c < KP; ++c) acc[c] = fma(w, Vs[pp * KP + c], acc[c]);
-            }
-        }
-    double *__restrict__ out = Gp + ((int64_t)blockIdx.y * gv.ncells + a) * KP;
-#pragma unroll
-    for (int c = 0; c < KP; ++c) out[c] = acc[c];
+    for (int c = 0; c < KP; ++c) G0[a * KP + c] = acc[c];
 }
 
 // out[a] = sum_{t = -kGridRC..kGridRC} g_s(t h) in[a + t e_axis] (zero past the grid).  One
@@ -235,61 +387,87 @@ static __global__ void __launch_bounds__(kRowBlock) k_grid_conv(GaussView gv, in
 
 // R_i = c^d sum over the grid points a with c_i - kGridRW <= a <= c_i + kGridRW + 1 (c_i the
 // cell of x_i; inside the grid, which keeps kGridRW + 2 cells to spare) of g_tau(x_i - a)
-// G1[a], minus V_i (the self term).  One thread per point.  The window factors over the
-// dimensions: the weights along dimension 0 are formed once per point (kGridWin of them, in
-// registers), those along dimensions 1 and 2 once per row of the window.
+// G1[a], minus V_i (the self term).  A workgroup takes 64 consecutive points of the binned
+// order (neighbouring points read overlapping windows of G1) with kGridWin wavefronts:
+// wavefront t sums, for each of the 64 points (one per lane), the window's slice at index t
+// along the last dimension (the window factors over the dimensions: the weights along
+// dimension 0 are formed once per lane, in registers, those along dimension 1 once per row),
+// and the first wavefront adds the kGridWin slice sums in increasing order.  Splitting the
+// window keeps the chip busy for images of a few 10^4 pixels.
+constexpr int kInterpThreads = 64 * kGridWin;
+
 template <int D, int KP>
-static __global__ void __launch_bounds__(kRowBlock) k_grid_interp(GaussView gv, const double *__restrict__ G1,
-                                                                   const double *__restrict__ V, double *__restrict__ R,
-                                                                   const Ctl *__restrict__ ctl)
+static __global__ void __launch_bounds__(kInterpThreads) k_grid_interp(GaussView gv, const double *__restrict__ G1,
+                                                                        const double *__restrict__ V,
+                                                                        double *__restrict__ R, const Ctl *__restrict__ ctl)
 {
+    constexpr int CW = KP < 4 ? KP : 4; // classes reduced through LDS per pass
+    __shared__ double part[kGridWin][64][CW];
     if (ctl && !ctl->active) return;
-    const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
-    if (i >= gv.n) return;
-    int ci[kGridMaxDim] = {0, 0, 0};
-    double xi[kGridMaxDim] = {0.0, 0.0, 0.0};
-    int64_t rem = gv.pt_cell[i];
-#pragma unroll
-    for (int q = D - 1; q >= 0; --q) {
-        ci[q] = (int)(rem / gv.gstride[q]);
-        rem -= (int64_t)ci[q] * gv.gstride[q];
-        xi[q] = gv.x[i * D + q];
-    }
-    double w0[kGridWin];
-#pragma unroll
-    for (int t = 0; t < kGridWin; ++t) {
-        const double df = xi[0] - grid_coord(gv, 0, ci[0] - kGridRW + t);
-        w0[t] = exp(-df * df * gv.inv2t2);
-    }
+    const int t = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    const int64_t pp = (int64_t)blockIdx.x * 64 + lane;
+    const bool pt = pp < gv.n;
     double acc[KP];
 #pragma unroll
     for (int c = 0; c < KP; ++c) acc[c] = 0.0;
-    constexpr int N2 = D >= 3 ? kGridWin : 1, N1 = D >= 2 ? kGridWin : 1;
-    for (int t2 = 0; t2 < N2; ++t2) {
-        double w2 = 1.0;
-        if (D >= 3) {
-            const double df = xi[2] - grid_coord(gv, 2, ci[2] - kGridRW + t2);
-            w2 = exp(-df * df * gv.inv2t2);
+    if (pt) {
+        int ci[kGridMaxDim] = {0, 0, 0};
+        double xi[kGridMaxDim] = {0.0, 0.0, 0.0};
+        int64_t rem = gv.pt_cell[pp];
+#pragma unroll
+        for (int q = D - 1; q >= 0; --q) {
+            ci[q] = (int)(rem / gv.gstride[q]);
+            rem -= (int64_t)ci[q] * gv.gstride[q];
+            xi[q] = gv.xs[pp * D + q];
         }
-        for (int t1 = 0; t1 < N1; ++t1) {
-            double w12 = w2;
-            if (D >= 2) {
-                const double df = xi[1] - grid_coord(gv, 1, ci[1] - kGridRW + t1);
-                w12 = w2 * exp(-df * df * gv.inv2t2);
-            }
-            const int64_t base = (int64_t)(ci[0] - kGridRW) + (D >= 2 ? (int64_t)(ci[1] - kGridRW + t1) * gv.gstride[1] : 0) +
-                                 (D >= 3 ? (int64_t)(ci[2] - kGridRW + t2) * gv.gstride[2] : 0);
-            const double *__restrict__ src = G1 + base * KP;
+        // this wavefront's slice: index t along the last dimension
+        const double dfl = xi[D - 1] - grid_coord(gv, D - 1, ci[D - 1] - kGridRW + t);
+        const double wl = exp(-dfl * dfl * gv.inv2t2);
+        if constexpr (D == 1) {
+            const double *__restrict__ src = G1 + (int64_t)(ci[0] - kGridRW + t) * KP;
+#pragma unroll
+            for (int c = 0; c < KP; ++c) acc[c] = fma(wl, src[c], acc[c]);
+        } else {
+            double w0[kGridWin];
 #pragma unroll
             for (int t0 = 0; t0 < kGridWin; ++t0) {
-                const double w = w12 * w0[t0];
+                const double df = xi[0] - grid_coord(gv, 0, ci[0] - kGridRW + t0);
+                w0[t0] = exp(-df * df * gv.inv2t2);
+            }
+            constexpr int N1 = D >= 3 ? kGridWin : 1;
+            for (int t1 = 0; t1 < N1; ++t1) {
+                double w1 = wl;
+                int64_t base = (int64_t)(ci[0] - kGridRW) + (int64_t)(ci[D - 1] - kGridRW + t) * gv.gstride[D - 1];
+                if (D >= 3) {
+                    const double df = xi[1] - grid_coord(gv, 1, ci[1] - kGridRW + t1);
+                    w1 = wl * exp(-df * df * gv.inv2t2);
+                    base += (int64_t)(ci[1] - kGridRW + t1) * gv.gstride[1];
+                }
+                const double *__restrict__ src = G1 + base * KP;
 #pragma unroll
-                for (int c = 0; c < KP; ++c) acc[c] = fma(w, src[t0 * KP + c], acc[c]);
+                for (int t0 = 0; t0 < kGridWin; ++t0) {
+                    const double w = w1 * w0[t0];
+#pragma unroll
+                    for (int c = 0; c < KP; ++c) acc[c] = fma(w, src[t0 * KP + c], acc[c]);
+                }
             }
         }
     }
+    const int64_t i = pt ? gv.cell_pts[pp] : 0;
 #pragma unroll
-    for (int c = 0; c < KP; ++c) R[i * KP + c] = gv.cnorm * acc[c] - V[i * KP + c];
+    for (int c0 = 0; c0 < KP; c0 += CW) {
+        if (c0 > 0) __syncthreads(); // the previous pass has read part
+#pragma unroll
+        for (int c = 0; c < CW; ++c) part[t][lane][c] = acc[c0 + c];
+        __syncthreads();
+        if (t == 0 && pt)
+#pragma unroll
+            for (int c = 0; c < CW; ++c) {
+                double sum = 0.0;
+                for (int u = 0; u < kGridWin; ++u) sum += part[u][lane][c];
+                R[i * KP + c0 + c] = gv.cnorm * sum - V[i * KP + c0 + c];
+            }
+    }
 }
 
 // ---- the pieces of the iteration around R = W V ----------------------------------------
