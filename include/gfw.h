@@ -200,7 +200,7 @@ GFW_API gfw_status_t gfw_graph_create(gfw_context_t ctx, const gfw_problem_t *p,
  * 16), and makes a node whose degree
  * is at most 1e-6 isolated;
  * GFW_GAUSS_AUTO takes the method of the smaller modelled time (the grid only when d <= 3 and
- * it fits): the grid at about 2.2 ps per unit of its work estimate (point and cell visits,
+ * it fits): the grid at about 1.8 ps per unit of its work estimate (point and cell visits,
  * (n + cells) 14^d) plus 20 us, the exact sums at 0.8 ps (FP32 graph) or 1.3 ps (FP64) per
  * pair, rates measured on an MI355X.  The graph is then used by
  * gfw_solve, gfw_objective, gfw_objective_noalloc and gfw_spmm like any other (K <= 16);

@@ -319,7 +319,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
         if (!std::isfinite(v)) return fail(GFW_E_GRAPH, "a feature is not finite");
 
     // method: exact, grid, or the one of smaller modelled time.  Rates measured on gfx950 at K <= 4
-    // (both methods scale alike with KP): the grid about 2.2 ps per unit of its work estimate plus
+    // (both methods scale alike with KP): the grid about 1.8 ps per unit of its work estimate plus
     // about 20 us of fixed launches; the exact sums 0.8 ps per pair with FP32 weights, 1.3 ps with
     // FP64 ones.
     int method = p->method;
@@ -332,7 +332,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
                     "= %d); use the exact method or a larger sigma", p->sigma, (long long)gp.v.ncells,
                     (long long)(kGridMaxElems / KP), K);
     if (method == GFW_GAUSS_AUTO) {
-        const double grid_ps = 2.2 * gp.work + 2e7;
+        const double grid_ps = 1.8 * gp.work + 2e7;
         const double exact_ps = (p->dtype == GFW_F32 ? 0.8 : 1.3) * (double)n * (double)n;
         method = (grid_fits && grid_ps < exact_ps) ? GFW_GAUSS_GRID : GFW_GAUSS_EXACT;
     }

@@ -263,6 +263,53 @@ __device__ __forceinline__ void gather_term(const double (&ac)[kGridMaxDim], con
     }
 }
 
+// The per-lane constants of the 3-D gather's factored window (see k_grid_gather).
+struct GatherFactor {
+    int u, q;       // the point of the batch and the dimension of the factor this lane forms
+    double coord;   // the grid coordinate the factor is taken at
+    int src[kGridMaxDim]; // per dimension, the lane (within a point's 12) holding this lane's factor
+};
+
+// One union row's points [P0, P1) for d = 3, in batches of 5: lanes 0..59 form the batch's 12
+// window factors per point g_tau(c - x_q) (c the block's 4 coordinates per dimension), each
+// lane's weight is the product of its three factors (read from the lanes that formed them), and
+// a lane adds w V_p only for the points of its own box [p0, p1).  Every lane of the wavefront
+// runs this (the shuffles read all lanes).
+template <int KP>
+__device__ __forceinline__ void gather_row_3d(const GaussView &gv, const double *__restrict__ Vs, const GatherFactor &fx,
+                                              int32_t P0, int32_t P1, int32_t p0, int32_t p1, double (&acc)[KP])
+{
+    constexpr int NB = 5;
+    const double *__restrict__ xs = gv.xs;
+    // the batch's feature is loaded one batch ahead; its V rows and the factors' shuffles are
+    // issued together (points past P1 repeat the last one, and add nothing)
+    double xq = xs[(int64_t)min(P0 + fx.u, P1 - 1) * 3 + fx.q];
+    for (int32_t pp = P0; pp < P1; pp += NB) {
+        const double xn = xs[(int64_t)min(pp + NB + fx.u, P1 - 1) * 3 + fx.q];
+        const double df = fx.coord - xq;
+        const double f = exp(-df * df * gv.inv2t2);
+        double vb[NB][KP];
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+#pragma unroll
+            for (int c = 0; c < KP; ++c) vb[u][c] = Vs[(int64_t)min(pp + u, P1 - 1) * KP + c];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const double f0 = __shfl(f, 12 * u + fx.src[0]);
+            const double f1 = __shfl(f, 12 * u + fx.src[1]);
+            const double f2 = __shfl(f, 12 * u + fx.src[2]);
+            const double w = f0 * f1 * f2;
+            const bool in = pp + u < P1 && pp + u >= p0 && pp + u < p1;
+#pragma unroll
+            for (int c = 0; c < KP; ++c) {
+                const double t = fma(w, vb[u][c], acc[c]);
+                acc[c] = in ? t : acc[c];
+            }
+        }
+        xq = xn;
+    }
+}
+
 template <int D, int KP>
 static __global__ void __launch_bounds__(kRowBlock) k_grid_gather(GaussView gv, const double *__restrict__ Vs,
                                                                    double *__restrict__ Tp, const Ctl *__restrict__ ctl)
@@ -281,6 +328,19 @@ static __global__ void __launch_bounds__(kRowBlock) k_grid_gather(GaussView gv, 
     double acc[KP];
 #pragma unroll
     for (int c = 0; c < KP; ++c) acc[c] = 0.0;
+    // d = 3: the window factors over the dimensions, and the block's 64 cells take only 4
+    // coordinates per dimension: lane l < 60 forms factor (l % 12) / 4 (the dimension q), l % 4
+    // (the block's q-th coordinate) of point l / 12 of a batch of 5
+    GatherFactor fx{};
+    if constexpr (D == 3) {
+        const int offs[kGridMaxDim] = {lane % 4, (lane / 4) % 4, lane / 16};
+        const int fq = (lane % 12) / 4, fo = lane % 4;
+        fx.u = lane / 12;
+        fx.q = fq;
+        fx.coord = grid_coord(gv, fq, g.ai[fq] - offs[fq] + fo);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) fx.src[q] = 4 * q + offs[q];
+    }
     const int nrows = gather_rows<D>(g);
     int32_t left = part.count, skip = part.off;
     for (int r = part.row; r < nrows && left > 0; ++r) {
@@ -294,6 +354,10 @@ static __global__ void __launch_bounds__(kRowBlock) k_grid_gather(GaussView gv, 
         left -= P1 - P0;
         const bool on = g.mine && b1 >= g.llo[1] && b1 <= g.lhi[1] && b2 >= g.llo[2] && b2 <= g.lhi[2];
         const int32_t p0 = on ? cs[row + g.llo[0]] : 0, p1 = on ? cs[row + g.lhi[0] + 1] : 0;
+        if constexpr (D == 3) {
+            gather_row_3d<KP>(gv, Vs, fx, P0, P1, p0, p1, acc);
+            continue;
+        }
         // the points' data are loaded for batches of 4 points ahead of their use (every lane
         // computes every point's term; a lane keeps it only for the points of its own box)
         int32_t pp = P0;
