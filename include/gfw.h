@@ -291,7 +291,7 @@ GFW_API gfw_status_t gfw_objective(gfw_context_t ctx, gfw_graph_t g, const gfw_p
  * goes to the DEVICE double *E_dev, ordered on `stream`.  Its block partials live in a fixed
  * scratch array of 3 x 65536 doubles (1.5 MiB) that the library holds on each device it
  * runs on until the process ends; graphs needing more partial blocks than that (n above
- * 16,777,216 for K <= 16, above 524,288 for K > 16) get GFW_E_UNSUPPORTED before any launch.
+ * 16,777,216 for K <= 16, above 262,144 for K > 16) get GFW_E_UNSUPPORTED before any launch.
  * Every call on a device shares that device's array: calls that overlap on one device (on
  * different streams, or from different threads) race and must be serialised by the caller.
  */

@@ -31,7 +31,7 @@
 namespace gfw {
 
 constexpr int kBigThreads = 256;                             // 4 wavefronts per block
-constexpr int kBigRowsPerWave = 2;                           // rows a wavefront takes in turn
+constexpr int kBigRowsPerWave = 1;                           // rows a wavefront takes in turn
 constexpr int kBigRowsPerBlock = kBigRowsPerWave * (kBigThreads / 64);
 
 // Wavefront minimum (the DPP steps of wave_sum).

@@ -42,8 +42,8 @@ def test_noalloc_objective_equals_objective(dtype):
 def test_noalloc_objective_rejects_graphs_beyond_its_scratch():
     import torch
 
-    K = 17  # a wavefront per 2 rows: 65,536 blocks hold 524,288 rows
-    g = graphs.path_graph(524_289, K)
+    K = 17  # a wavefront per row: 65,536 blocks hold 262,144 rows
+    g = graphs.path_graph(262_145, K)
     say("[gpu] noalloc objective size limit")
     G = gpu_graph(g, K, [0], [0], gfw.F32)
     U = torch.full((g.n, K), 1.0 / K, dtype=torch.float32, device="cuda")
