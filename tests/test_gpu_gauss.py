@@ -82,6 +82,31 @@ def test_spmm_grid_within_its_error_bound(d, n, sigma):
     assert np.abs(np_of(gfw.spmm(ctx(), ge, torch_u(U, gfw.F64))) - ref).max() <= 1e-12
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("dtype", [gfw.F64, gfw.F32])
+def test_spmm_grid_clustered(d, dtype):
+    """Tight clusters (as image colours are): every gather task that reaches a cluster holds far
+    more points than a part, so the work list cuts it; the product stays within the grid's
+    error bound and is the same on every call."""
+    rg = np.random.default_rng(40 + d)
+    n, sigma, K = 3000, 0.1, 4
+    centres = 0.2 + 0.6 * rg.random((3, d))
+    x = centres[rg.integers(0, 3, n)] + 0.03 * rg.standard_normal((n, d))
+    say(f"[gpu] gauss spmm grid clustered d={d} dtype={dtype} n={n}")
+    U = _simplex_rows(n, K, 50 + d)
+    g = gfw.Graph.gaussian(ctx(), x, K, sigma, np.zeros(0, np.int32), np.zeros(0, np.int32), dtype, gfw.GAUSS_GRID)
+    Ut = torch_u(U, dtype)
+    got1 = np_of(gfw.spmm(ctx(), g, Ut)).astype(np.float64)
+    got2 = np_of(gfw.spmm(ctx(), g, Ut)).astype(np.float64)
+    assert np.array_equal(got1, got2)
+    xin = x.astype(np.float32).astype(np.float64) if dtype == gfw.F32 else x
+    ref = O.spmm(_dense_L(xin, sigma), np_of(Ut).astype(np.float64))
+    err = np.abs(got1 - ref).max()
+    say(f"[gpu]   grid error {err:.3e}")
+    # FP32: U and the result are stored in FP32 (a few 1e-7 of entries of order 1)
+    assert err <= (GRID_ABS if dtype == gfw.F64 else GRID_ABS + 2e-6)
+
+
 def _small_image(K=4, seed=11, H=36, W=41):
     return configs.color_image(seed, H, W, K)
 
