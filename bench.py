@@ -8,8 +8,8 @@ output.  Graph upload and operator set-up happen before the timed region.
 
 value = executed FW iterations per second over the timed steps.  The roofline entry is
 for the dominant kernel (the label pass), with its duration measured by HIP events around
-every one of its launches in the timed region (the other kernels are launched without
-events there).  cpu_baseline times the FP64 oracle on a few iterations of the same
+every one of its launches in the last timed step (the other kernels are launched without
+events; the other steps replay the iteration graphs with no event in the stream).  cpu_baseline times the FP64 oracle on a few iterations of the same
 graph on the host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -737,10 +737,10 @@ def main() -> int:
     untraced = it_u / (time.perf_counter() - t_u)
     log(f"[bench] untraced: {untraced:.1f} it/s")
 
-    # timed steps: every label pass bracketed by HIP events (its mean duration is the
-    # roofline's); the other kernels are launched without events
+    # timed steps: in the last one every label pass is bracketed by HIP events (its mean
+    # duration is the roofline's; the library launches a traced solve without its iteration
+    # graphs), the others replay the iteration graphs with no event in the stream
     gfw.trace_reset(ctx)
-    gfw.trace_enable(ctx, gfw.TRACE_LABEL)
     iters_total = 0
     last = None
     torch.cuda.synchronize()
@@ -748,6 +748,8 @@ def main() -> int:
     ev0.record(stream)
     t_start = time.perf_counter()
     for s in range(args.steps):
+        if s == args.steps - 1:
+            gfw.trace_enable(ctx, gfw.TRACE_LABEL)
         last = gfw.solve(ctx, G, prm, want_stats=True, stream=stream)
         iters_total += last["iters"]
     ev1.record(stream)
@@ -761,7 +763,7 @@ def main() -> int:
 
     ms, cnt = gfw.trace_get(ctx, gfw.KERNEL_LABEL)
     label_us = 1e3 * ms / cnt
-    log(f"[bench] label pass in the timed steps: {label_us:.2f} us over {cnt} launches")
+    log(f"[bench] label pass in the last timed step: {label_us:.2f} us over {cnt} launches")
 
     # one more solve outside the timed region with every launch bracketed: the durations of
     # all kernel classes
