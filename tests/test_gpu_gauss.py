@@ -82,17 +82,17 @@ def test_spmm_grid_within_its_error_bound(d, n, sigma):
     assert np.abs(np_of(gfw.spmm(ctx(), ge, torch_u(U, gfw.F64))) - ref).max() <= 1e-12
 
 
-@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("d,K", [(1, 4), (2, 4), (3, 4), (3, 7), (3, 12)])
 @pytest.mark.parametrize("dtype", [gfw.F64, gfw.F32])
-def test_spmm_grid_clustered(d, dtype):
+def test_spmm_grid_clustered(d, K, dtype):
     """Tight clusters (as image colours are): every gather task that reaches a cluster holds far
     more points than a part, so the work list cuts it; the product stays within the grid's
-    error bound and is the same on every call."""
+    error bound and is the same on every call (row strides 4, 8 and 16)."""
     rg = np.random.default_rng(40 + d)
-    n, sigma, K = 3000, 0.1, 4
+    n, sigma = 3000, 0.1
     centres = 0.2 + 0.6 * rg.random((3, d))
     x = centres[rg.integers(0, 3, n)] + 0.03 * rg.standard_normal((n, d))
-    say(f"[gpu] gauss spmm grid clustered d={d} dtype={dtype} n={n}")
+    say(f"[gpu] gauss spmm grid clustered d={d} K={K} dtype={dtype} n={n}")
     U = _simplex_rows(n, K, 50 + d)
     g = gfw.Graph.gaussian(ctx(), x, K, sigma, np.zeros(0, np.int32), np.zeros(0, np.int32), dtype, gfw.GAUSS_GRID)
     Ut = torch_u(U, dtype)
