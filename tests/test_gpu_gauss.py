@@ -232,6 +232,14 @@ def test_device_features_and_edge_cases():
     Ud = _simplex_rows(80, 2, 2)
     ref = O.spmm(_dense_L(xd, 0.3), Ud)
     assert np.abs(np_of(gfw.spmm(ctx(), gdup, torch_u(Ud, gfw.F64))) - ref).max() <= 1e-12
+    # the same two cases by the grid summation: one node is isolated (its grid degree is the
+    # self term only), duplicated points within the grid's error bound
+    g1g = gfw.Graph.gaussian(ctx(), np.zeros((1, 2)), 2, 1.0, np.array([0], np.int32), np.array([1], np.int32),
+                             gfw.F64, gfw.GAUSS_GRID)
+    assert np_of(gfw.solve(ctx(), g1g, gfw.params(max_iter=5))["labels"]).tolist() == [1]
+    gdupg = gfw.Graph.gaussian(ctx(), xd, 2, 0.3, np.zeros(0, np.int32), np.zeros(0, np.int32), gfw.F64,
+                               gfw.GAUSS_GRID)
+    assert np.abs(np_of(gfw.spmm(ctx(), gdupg, torch_u(Ud, gfw.F64))) - ref).max() <= GRID_ABS
     # d = 8, the exact method's largest
     x8 = rg.standard_normal((300, 8))
     g8 = gfw.Graph.gaussian(ctx(), x8, 2, 2.0, np.zeros(0, np.int32), np.zeros(0, np.int32), gfw.F64)
