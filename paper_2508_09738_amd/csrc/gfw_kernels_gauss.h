@@ -163,9 +163,10 @@ static __global__ void __launch_bounds__(kRowBlock) k_grid_bin_v(GaussView gv, c
 // consecutive ranges of the binned order.  Image colours crowd into a few clusters, so the
 // tasks' point counts differ by orders of magnitude: each task is cut into parts of at most a
 // fixed number of points (the work list, planned when the graph is made), one wavefront per part.
-// All 64 lanes visit the same point at the same time, so the point's features and V are uniform
-// (scalar loads, broadcast from scalar registers), and each lane adds the point only if it lies
-// in its own cell's box.  Part p writes its 64 lane sums to Tp[p] (64 x KP); k_grid_parts_sum
+// All 64 lanes visit the same point at the same time, so the point's V (and, for d < 3, its
+// features) are uniform (scalar loads, broadcast from scalar registers), and each lane adds the
+// point only if it lies in its own cell's box; in 3-D the window is formed from per-dimension
+// factors (gather_row_3d).  Part p writes its 64 lane sums to Tp[p] (64 x KP); k_grid_parts_sum
 // adds, for each cell, its slices in increasing order and each slice's parts in increasing order.
 template <int D> struct GridBlock {
     static constexpr int b0 = D == 1 ? 64 : D == 2 ? 8 : 4, b1 = D == 1 ? 1 : D == 2 ? 8 : 4, b2 = D == 3 ? 4 : 1;
@@ -173,10 +174,11 @@ template <int D> struct GridBlock {
     static constexpr int slices = bl + kGridWin - 1;          // last-dimension indices a block's boxes reach
 };
 
-// The geometry of gather task `task` for the lane with offsets `off` in its block: the lane's
-// cell (valid when inside the grid), its slice index y (mine: the cell's box reaches bl), the
-// union of the block's boxes (ulo..uhi, uniform) and the lane's own box (llo..lhi), both
-// clipped to the grid, along L both the one index bl.  Used by the host to plan the parts.
+// The geometry of gather task `task` for lane `lane` of its wavefront: the lane's cell (valid
+// when inside the grid), its slice index y (mine: the cell's box reaches bl), the union of the
+// block's boxes (ulo..uhi, the same for every lane) and the lane's own box (llo..lhi), both
+// clipped to the grid, along L both the one index bl.  The host plans the parts with it, the
+// gather kernel walks them with it.
 struct GatherTask {
     int ai[kGridMaxDim], ulo[kGridMaxDim], uhi[kGridMaxDim], llo[kGridMaxDim], lhi[kGridMaxDim];
     int bl, y;
