@@ -115,8 +115,8 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
 #pragma unroll
         for (int m = 0; m < MC; ++m) {
             const int c = lane + 64 * m;
-            u[m] = c < K ? Ui[c] : (T)0;
-            p[m] = c < K ? Pi[c] : 0.0;
+            u[m] = c < K ? __builtin_nontemporal_load(Ui + c) : (T)0;
+            p[m] = c < K ? __builtin_nontemporal_load(Pi + c) : 0.0;
         }
         bool bl = true;
 #pragma unroll
@@ -162,7 +162,7 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
                 if (c < K) {
                     // Q_{k-1} rounded to the graph's dtype, as the small-K label pass stores it
                     p[m] = om * p[m] + alpha * (double)(T)q[m];
-                    Pi[c] = p[m];
+                    __builtin_nontemporal_store(p[m], Pi + c);
                 }
             }
             // a row whose direction e_{s_i} - u_i is zero (binary, kept by the GLMO) stays as it is
@@ -178,7 +178,7 @@ __device__ __forceinline__ void row_big_body(const GraphView<T> &gv, const int t
                     const int c = lane + 64 * m;
                     if (c < K) {
                         u[m] = (T)(om * (double)u[m] + (c == spi ? alpha : 0.0));
-                        Ui[c] = u[m];
+                        __builtin_nontemporal_store(u[m], Ui + c);
                         if (!(u[m] == (T)0 || u[m] == (T)1)) bl = false;
                     }
                 }
