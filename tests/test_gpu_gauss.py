@@ -221,6 +221,11 @@ def test_device_features_and_edge_cases():
                             torch.tensor(lab, device="cuda"), gfw.F64, gfw.GAUSS_EXACT)
     U = torch_u(_simplex_rows(500, 3, 1), gfw.F64)
     assert torch.equal(gfw.spmm(ctx(), gh, U), gfw.spmm(ctx(), gd, U))
+    # the grid method bins the points on the host: device features give the same graph
+    ghg = gfw.Graph.gaussian(ctx(), x, 3, 0.2, idx, lab, gfw.F64, gfw.GAUSS_GRID)
+    gdg = gfw.Graph.gaussian(ctx(), torch.tensor(x, device="cuda"), 3, 0.2, torch.tensor(idx, device="cuda"),
+                             torch.tensor(lab, device="cuda"), gfw.F64, gfw.GAUSS_GRID)
+    assert torch.equal(gfw.spmm(ctx(), ghg, U), gfw.spmm(ctx(), gdg, U))
     # one node: no edges, degree 0, L_s = I; the solve keeps the label (or 1/K)
     g1 = gfw.Graph.gaussian(ctx(), np.zeros((1, 2)), 2, 1.0, np.array([0], np.int32), np.array([1], np.int32), gfw.F64)
     r = gfw.solve(ctx(), g1, gfw.params(max_iter=5))
