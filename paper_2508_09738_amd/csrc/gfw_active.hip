@@ -61,29 +61,29 @@ static __global__ void __launch_bounds__(kRowBlock) k_act_mark(int64_t n, int32_
 }
 
 // Exclusive prefix sum of cnt[0..nb) into off[], and the total into *m (one workgroup of 1024
-// threads: contiguous chunks per thread, the chunk sums scanned by thread 0).
+// threads: contiguous chunks per thread, the chunk sums scanned across the workgroup in ten
+// doubling steps through LDS).
 static __global__ void __launch_bounds__(1024) k_act_scan(int32_t nb, const int32_t *__restrict__ cnt,
                                                           int32_t *__restrict__ off, int32_t *__restrict__ m)
 {
-    __shared__ int32_t part[1024];
+    __shared__ int32_t part[2][1024];
     const int t = threadIdx.x;
     const int32_t per = (nb + 1023) / 1024;
     const int32_t b0 = t * per, b1 = min(nb, b0 + per);
     int32_t sum = 0;
     for (int32_t b = b0; b < b1; ++b) sum += cnt[b];
-    part[t] = sum;
+    // inclusive scan of the chunk sums (ping-pong buffers)
+    int cur = 0;
+    part[cur][t] = sum;
     __syncthreads();
-    if (t == 0) {
-        int32_t run = 0;
-        for (int j = 0; j < 1024; ++j) {
-            const int32_t v = part[j];
-            part[j] = run;
-            run += v;
-        }
-        *m = run;
+    for (int d = 1; d < 1024; d <<= 1) {
+        const int32_t v = part[cur][t] + (t >= d ? part[cur][t - d] : 0);
+        part[cur ^ 1][t] = v;
+        cur ^= 1;
+        __syncthreads();
     }
-    __syncthreads();
-    int32_t run = part[t];
+    if (t == 1023) *m = part[cur][1023];
+    int32_t run = part[cur][t] - sum;
     for (int32_t b = b0; b < b1; ++b) {
         off[b] = run;
         run += cnt[b];
@@ -107,13 +107,17 @@ static __global__ void __launch_bounds__(kRowBlock) k_act_scatter(int64_t n, con
     if (mv) act[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)i;
 }
 
-// P_a[r] = row act[r] of L_s U (FP64), kSpmmLanes lanes per row, the full SpMM's row sums.
+// P_a[r] = row act[r] of L_s U (FP64), kSpmmLanes lanes per row, the full SpMM's row sums;
+// kActSpmmRows rows per workgroup, so that a few thousand rows still spread over the CUs.
+constexpr int kActSpmmRows = 64;
+
 template <typename T, int KB>
-static __global__ void __launch_bounds__(kSpmmThreads) k_act_spmm(GraphView<T> gv, const int32_t *__restrict__ act,
-                                                                  int32_t m, double *__restrict__ Pa)
+static __global__ void __launch_bounds__(kActSpmmRows * kSpmmLanes) k_act_spmm(GraphView<T> gv,
+                                                                               const int32_t *__restrict__ act,
+                                                                               int32_t m, double *__restrict__ Pa)
 {
     constexpr int MC = KB / kSpmmLanes;
-    const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x / kSpmmLanes;
+    const int64_t r = (int64_t)blockIdx.x * kActSpmmRows + threadIdx.x / kSpmmLanes;
     const int64_t i = r < m ? act[r] : -1;
     double acc[MC];
     spmm_row<T, KB>(gv, gv.U, i, acc);
@@ -306,7 +310,8 @@ static gfw_status_t incremental_impl(gfw_graph_s *g, const gfw_params_t *prm, vo
     GFW_HIP_TRY(hipStreamSynchronize(st));
     const unsigned nb = (unsigned)act_blocks(m);
     hipEvent_t ev = trace_begin(cx, GFW_KERNEL_SPMM, st);
-    k_act_spmm<T, KB><<<nb, kSpmmThreads, 0, st>>>(v, act, m, Pa);
+    k_act_spmm<T, KB><<<(unsigned)std::max<int64_t>(1, cdiv(m, kActSpmmRows)), kActSpmmRows * kSpmmLanes, 0, st>>>(
+        v, act, m, Pa);
     trace_end(cx, GFW_KERNEL_SPMM, ev, st);
     if (!w.h_flag) GFW_HIP_TRY(hipHostMalloc((void **)&w.h_flag, 2 * sizeof(int32_t), hipHostMallocDefault));
     for (int i = 0; i < 2; ++i)
