@@ -194,8 +194,9 @@ GFW_API gfw_status_t gfw_graph_create(gfw_context_t ctx, const gfw_problem_t *p,
  * GFW_GAUSS_GRID, for 1 <= d <= 3, gathers the points onto a grid of
  * spacing sigma / 2 with a Gaussian window, convolves the grid with a Gaussian and
  * interpolates back, the widths chosen so that the composite kernel is the Gaussian of width
- * sigma (windows cut at 5 widths: a relative error of about 1e-7 per product; O((n + cells)
- * 14^d K) per product, the cells spanning the range of the features in steps of sigma / 2;
+ * sigma (windows cut at 5 widths: a relative error of about 1e-7 per product, and about 7e-8
+ * more for an FP32 graph, whose convolved grid is stored in FP32; O((n + cells) 14^d K) per
+ * product, the cells spanning the range of the features in steps of sigma / 2;
  * GFW_E_UNSUPPORTED when the grid would exceed 2^26 / KP cells, KP = K rounded up to 4, 8 or
  * 16), and makes a node whose degree
  * is at most 1e-6 isolated;

@@ -26,6 +26,7 @@ struct GaussGraph {
     double *V = nullptr, *R = nullptr; // n x kp
     double *Rp = nullptr;        // chunks x n x kp (exact method, chunks > 1)
     double *G0 = nullptr, *G1 = nullptr; // ncells x kp (grid method)
+    float *G1f = nullptr;        // the convolved grid in FP32 (grid method, FP32 graph)
     double *Tp = nullptr;        // nparts x 64 x kp: the gather's part sums (grid method)
     GatherPart *parts = nullptr; // the gather's work list
     int32_t *part_first = nullptr; // per gather task, its first part
@@ -47,6 +48,7 @@ void gauss_free(GaussGraph *gg)
     dfree(gg->G0);
     dfree(gg->G1);
     dfree(gg->Tp);
+    dfree(gg->G1f);
     dfree(gg->parts);
     dfree(gg->part_first);
     dfree(gg->xs);
@@ -75,15 +77,22 @@ static void apply_grid(const GaussGraph &gg, const double *V, double *R, const C
     if (v.nparts > 0) // one wavefront per part
         k_grid_gather<D, KP><<<(unsigned)cdiv(v.nparts, kRowBlock / 64), kRowBlock, 0, st>>>(v, gg.Vs, gg.Tp, ctl);
     k_grid_parts_sum<D, KP><<<nc, kRowBlock, 0, st>>>(v, gg.Tp, gg.G0, ctl);
+    // the convolution one axis at a time; an FP32 graph's last pass stores the grid in FP32
     const double *in = gg.G0;
     double *out = gg.G1;
     for (int q = 0; q < D; ++q) {
-        k_grid_conv<KP><<<nc, kRowBlock, 0, st>>>(v, q, in, out, ctl);
+        if (q == D - 1 && gg.G1f) {
+            k_grid_conv<KP, float><<<nc, kRowBlock, 0, st>>>(v, q, in, gg.G1f, ctl);
+            break;
+        }
+        k_grid_conv<KP, double><<<nc, kRowBlock, 0, st>>>(v, q, in, out, ctl);
         double *done = out;
         out = const_cast<double *>(in);
         in = done;
     }
-    k_grid_interp<D, KP><<<(unsigned)cdiv(v.n, 64), kInterpThreads, 0, st>>>(v, in, V, R, ctl);
+    const unsigned ni = (unsigned)cdiv(v.n, 64);
+    if (gg.G1f) k_grid_interp<D, KP, float><<<ni, kInterpThreads, 0, st>>>(v, gg.G1f, V, R, ctl);
+    else k_grid_interp<D, KP, double><<<ni, kInterpThreads, 0, st>>>(v, in, V, R, ctl);
 }
 
 template <int KP>
@@ -407,6 +416,7 @@ gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t
         if ((s = dalloc((void **)&gg.pt_cell, 4 * (size_t)n)) != GFW_OK) return s;
         if ((s = dalloc((void **)&gg.G0, 8 * (size_t)v.ncells * KP)) != GFW_OK) return s;
         if ((s = dalloc((void **)&gg.G1, 8 * (size_t)v.ncells * KP)) != GFW_OK) return s;
+        if (p->dtype == GFW_F32 && (s = dalloc((void **)&gg.G1f, 4 * (size_t)v.ncells * KP)) != GFW_OK) return s;
         std::vector<GatherPart> parts;
         std::vector<int32_t> first;
         if (d == 1) plan_gather<1>(v, start, ctx->num_cu, parts, first);

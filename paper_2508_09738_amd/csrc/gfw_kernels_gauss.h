@@ -426,11 +426,11 @@ static __global__ void __launch_bounds__(kRowBlock) k_grid_parts_sum(GaussView g
     for (int c = 0; c < KP; ++c) G0[a * KP + c] = acc[c];
 }
 
-// out[a] = sum_{t = -kGridRC..kGridRC} g_s(t h) in[a + t e_axis] (zero past the grid).  One
-// thread per cell.
-template <int KP>
+// out[a] = sum_{t = -kGridRC..kGridRC} g_s(t h) in[a + t e_axis] (zero past the grid), stored as
+// OT.  One thread per cell.
+template <int KP, typename OT>
 static __global__ void __launch_bounds__(kRowBlock) k_grid_conv(GaussView gv, int axis, const double *__restrict__ in,
-                                                                 double *__restrict__ out, const Ctl *__restrict__ ctl)
+                                                                 OT *__restrict__ out, const Ctl *__restrict__ ctl)
 {
     if (ctl && !ctl->active) return;
     const int64_t a = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
@@ -448,7 +448,7 @@ static __global__ void __launch_bounds__(kRowBlock) k_grid_conv(GaussView gv, in
         for (int c = 0; c < KP; ++c) acc[c] = fma(w, src[c], acc[c]);
     }
 #pragma unroll
-    for (int c = 0; c < KP; ++c) out[a * KP + c] = acc[c];
+    for (int c = 0; c < KP; ++c) out[a * KP + c] = (OT)acc[c];
 }
 
 // R_i = c^d sum over the grid points a with c_i - kGridRW <= a <= c_i + kGridRW + 1 (c_i the
@@ -459,11 +459,13 @@ static __global__ void __launch_bounds__(kRowBlock) k_grid_conv(GaussView gv, in
 // along the last dimension (the window factors over the dimensions: the weights along
 // dimension 0 are formed once per lane, in registers, those along dimension 1 once per row),
 // and the first wavefront adds the kGridWin slice sums in increasing order.  Splitting the
-// window keeps the chip busy for images of a few 10^4 pixels.
+// window keeps the chip busy for images of a few 10^4 pixels.  The reads of G1 bound the kernel
+// (L1 bandwidth): GT is the type G1 is stored in (FP32 for an FP32 graph, half the bytes; the
+// sums stay FP64).
 constexpr int kInterpThreads = 64 * kGridWin;
 
-template <int D, int KP>
-static __global__ void __launch_bounds__(kInterpThreads) k_grid_interp(GaussView gv, const double *__restrict__ G1,
+template <int D, int KP, typename GT>
+static __global__ void __launch_bounds__(kInterpThreads) k_grid_interp(GaussView gv, const GT *__restrict__ G1,
                                                                         const double *__restrict__ V,
                                                                         double *__restrict__ R, const Ctl *__restrict__ ctl)
 {
@@ -490,9 +492,9 @@ static __global__ void __launch_bounds__(kInterpThreads) k_grid_interp(GaussView
         const double dfl = xi[D - 1] - grid_coord(gv, D - 1, ci[D - 1] - kGridRW + t);
         const double wl = exp(-dfl * dfl * gv.inv2t2);
         if constexpr (D == 1) {
-            const double *__restrict__ src = G1 + (int64_t)(ci[0] - kGridRW + t) * KP;
+            const GT *__restrict__ src = G1 + (int64_t)(ci[0] - kGridRW + t) * KP;
 #pragma unroll
-            for (int c = 0; c < KP; ++c) acc[c] = fma(wl, src[c], acc[c]);
+            for (int c = 0; c < KP; ++c) acc[c] = fma(wl, (double)src[c], acc[c]);
         } else {
             double w0[kGridWin];
 #pragma unroll
@@ -509,12 +511,12 @@ static __global__ void __launch_bounds__(kInterpThreads) k_grid_interp(GaussView
                     w1 = wl * exp(-df * df * gv.inv2t2);
                     base += (int64_t)(ci[1] - kGridRW + t1) * gv.gstride[1];
                 }
-                const double *__restrict__ src = G1 + base * KP;
+                const GT *__restrict__ src = G1 + base * KP;
 #pragma unroll
                 for (int t0 = 0; t0 < kGridWin; ++t0) {
                     const double w = w1 * w0[t0];
 #pragma unroll
-                    for (int c = 0; c < KP; ++c) acc[c] = fma(w, src[t0 * KP + c], acc[c]);
+                    for (int c = 0; c < KP; ++c) acc[c] = fma(w, (double)src[t0 * KP + c], acc[c]);
                 }
             }
         }
