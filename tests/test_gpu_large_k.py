@@ -64,6 +64,15 @@ def test_lockstep_large_k_wide_rows(dtype, K):
     lockstep(prob, dtype, [0, 1, 6], label=f"lfr K={K}")
 
 
+@pytest.mark.parametrize("mc", [2, 3, 4, 6, 7, 8, 9, 11, 12, 13, 14, 15])
+def test_lockstep_every_classes_per_lane(mc):
+    """Every other classes-per-lane instantiation of the many-class kernels (mc classes per lane,
+    K = 64 mc - 20) in lockstep with the oracle (FP64, a small LFR-shaped network)."""
+    K = 64 * mc - 20
+    prob = configs.lfr_many_classes(seed=mc, n=6 * K, K=K, frac=0.05, max_iter=10)
+    lockstep(prob, gfw.F64, [0, 1, 4], label=f"lfr K={K}")
+
+
 def test_lockstep_large_k_variants_f64():
     prob = configs.lfr_many_classes(seed=7, n=2000, K=70, frac=0.05, max_iter=30)
     lockstep(prob, gfw.F64, [0, 3, 12], lmo=O.LMO_FULL, label="full-lmo K=70")
