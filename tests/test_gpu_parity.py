@@ -164,13 +164,14 @@ def test_lockstep_sbm_small(dtype):
     _lockstep(prob, dtype, [0, 1, 2, 5, 20, 80, 299], label="sbm_small")
 
 
+@pytest.mark.parametrize("dtype", [gfw.F64, gfw.F32])
 @pytest.mark.parametrize("K", list(range(2, 17)))
-def test_lockstep_every_class_count(K):
+def test_lockstep_every_class_count(K, dtype):
     """The single-graph row kernel and label pass are compiled for each K from 2 to 16: each
-    instantiation in lockstep with the oracle (FP64, a small SBM with K blocks)."""
+    instantiation in lockstep with the oracle (a small SBM with K blocks)."""
     prob = configs.sbm_small(seed=20 + K, n_per=60, K=K)
     prob.max_iter = 40
-    _lockstep(prob, gfw.F64, [0, 1, 3, 10, 39], label=f"sbm K={K}")
+    _lockstep(prob, dtype, [0, 1, 3, 10, 39], label=f"sbm K={K}")
 
 
 def test_lockstep_knn_f32():
