@@ -76,12 +76,13 @@ def _oracle_warm(full, U0, **kw):
     return O.solve(L, full.K, full.labelled_idx, full.labels, U0=U0, **kw)
 
 
-@pytest.mark.parametrize("one_shot", [False, True])
-def test_incremental_matches_the_oracle_f64(one_shot):
+@pytest.mark.parametrize("one_shot,K", [(False, 3), (True, 3), (False, 7), (False, 13)])
+def test_incremental_matches_the_oracle_f64(one_shot, K):
     """The incremental solve (moving rows only) against the oracle's full iteration from the
-    same U_0: the same iterates up to the order of the sums."""
-    say(f"[gpu] incremental solve f64 one_shot={one_shot}")
-    old, full = configs.grown_sbm(seed=6, n_old=3000, n_new=150)
+    same U_0: the same iterates up to the order of the sums (K in each class-count bucket of
+    the moving-row kernels: 4, 8 and 16)."""
+    say(f"[gpu] incremental solve f64 one_shot={one_shot} K={K}")
+    old, full = configs.grown_sbm(seed=6, n_old=3000, n_new=150, K=K)
     U0 = _warm_start(old, full)
     kw = dict(max_iter=100, tol=1e-6)
     ro = _oracle_warm(full, U0, osfw=one_shot, **kw)
