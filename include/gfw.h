@@ -241,12 +241,16 @@ GFW_API gfw_status_t gfw_graph_footprint(gfw_graph_t g, size_t *graph_bytes, siz
  * GFW_TUNE_LABEL_PLAIN_NS / GFW_TUNE_LABEL_SORTED_NS the mean launch times measured by
  * the last value-3 tuning, in ns (0 if none); GFW_TUNE_SORTED_WIDE_CHUNKS (query only) the
  * number of 64-entry runs of the column-sorted copy whose columns span more than 32767, so
- * that their entries read the column from the CSR instead (0 before the copy is built). */
+ * that their entries read the column from the CSR instead (0 before the copy is built);
+ * GFW_TUNE_GAUSS_METHOD (query only) the method a fully connected Gaussian graph sums its
+ * products with, GFW_GAUSS_EXACT or GFW_GAUSS_GRID (what GFW_GAUSS_AUTO chose), 0 for a graph
+ * given by its entries. */
 typedef enum {
     GFW_TUNE_LABEL_PATH = 0,
     GFW_TUNE_LABEL_PLAIN_NS = 1,
     GFW_TUNE_LABEL_SORTED_NS = 2,
-    GFW_TUNE_SORTED_WIDE_CHUNKS = 3
+    GFW_TUNE_SORTED_WIDE_CHUNKS = 3,
+    GFW_TUNE_GAUSS_METHOD = 4
 } gfw_tune_t;
 GFW_API gfw_status_t gfw_graph_tune(gfw_graph_t g, gfw_tune_t key, int64_t value);
 GFW_API gfw_status_t gfw_graph_query(gfw_graph_t g, gfw_tune_t key, int64_t *value);

@@ -1294,6 +1294,7 @@ gfw_status_t gfw_graph_query(gfw_graph_t g, gfw_tune_t key, int64_t *value)
     case GFW_TUNE_LABEL_PLAIN_NS: *value = (int64_t)(1e3 * g->label_us[0]); return GFW_OK;
     case GFW_TUNE_LABEL_SORTED_NS: *value = (int64_t)(1e3 * g->label_us[1]); return GFW_OK;
     case GFW_TUNE_SORTED_WIDE_CHUNKS: *value = g->wide_chunks; return GFW_OK;
+    case GFW_TUNE_GAUSS_METHOD: *value = g->gauss ? gauss_method(g->gauss) : 0; return GFW_OK;
     default: return fail(GFW_E_INVALID_ARG, "unknown tuning key %d", (int)key);
     }
 }

@@ -33,6 +33,8 @@ struct GaussGraph {
     double *xs = nullptr, *Vs = nullptr; // n x d features and n x kp V in binned order (grid method)
 };
 
+int gauss_method(const GaussGraph *gg) { return gg->method; }
+
 void gauss_free(GaussGraph *gg)
 {
     if (!gg) return;

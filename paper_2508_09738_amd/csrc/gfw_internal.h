@@ -184,6 +184,7 @@ inline int64_t fold_blocks(const gfw_graph_s *g)
 gfw_status_t gauss_graph_create(gfw_context_s *ctx, const gfw_gaussian_problem_t *p, gfw_graph_s **out,
                                 hipStream_t st);
 void gauss_free(GaussGraph *gg);
+int gauss_method(const GaussGraph *gg); // GFW_GAUSS_EXACT or GFW_GAUSS_GRID
 template <typename T, typename PT>
 void gauss_spmm(const gfw_graph_s *g, const T *U, PT *P, hipStream_t st);
 template <typename T>

@@ -33,7 +33,7 @@ EXPORTED = [
     "gfw_graph_tune", "gfw_graph_query", "gfw_objective_noalloc", "gfw_copy_bandwidth", "gfw_graph_create_gaussian",
 ]
 GAUSS_AUTO, GAUSS_EXACT, GAUSS_GRID = 0, 1, 2
-TUNE_LABEL_PATH, TUNE_LABEL_PLAIN_NS, TUNE_LABEL_SORTED_NS, TUNE_SORTED_WIDE_CHUNKS = 0, 1, 2, 3
+TUNE_LABEL_PATH, TUNE_LABEL_PLAIN_NS, TUNE_LABEL_SORTED_NS, TUNE_SORTED_WIDE_CHUNKS, TUNE_GAUSS_METHOD = 0, 1, 2, 3, 4
 LABEL_PATH_AUTO, LABEL_PATH_PLAIN, LABEL_PATH_SORTED, LABEL_PATH_MEASURED = 0, 1, 2, 3
 KERNEL_ROW, KERNEL_LABEL, KERNEL_FINISH, KERNEL_SPMM = 0, 1, 2, 3
 

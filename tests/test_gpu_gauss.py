@@ -14,7 +14,7 @@ from oracle import oracle as O
 from paper_2508_09738_amd import gfw
 from synth import configs, graphs
 
-from gpu_helpers import ctx, lockstep, np_of, say, torch_u
+from gpu_helpers import ctx, gpu_graph, lockstep, np_of, say, torch_u
 
 pytestmark = pytest.mark.gpu
 
@@ -207,6 +207,22 @@ def test_full_size_image_sampled_rows():
         P = np_of(gfw.spmm(ctx(), G, r["U"]))
         ref = O.gaussian_laplacian_rows(ip.features, ip.sigma, U, rows, deg=deg)
         assert np.abs(P[rows] - ref).max() <= tol
+
+
+def test_automatic_method_choice():
+    """GFW_GAUSS_AUTO takes the grid for Table 2's largest image (its modelled time is the
+    smaller by 2-4x in both dtypes) and the exact sums for a few points; the query reports it."""
+    ip = configs.color_image(7)
+    for dt in (gfw.F32, gfw.F64):
+        G = _gpu(ip, dt, gfw.GAUSS_AUTO)
+        assert G.query(gfw.TUNE_GAUSS_METHOD) == gfw.GAUSS_GRID
+    x = np.random.default_rng(3).random((50, 3))
+    none = np.zeros(0, np.int32)
+    assert gfw.Graph.gaussian(ctx(), x, 2, 0.2, none, none).query(gfw.TUNE_GAUSS_METHOD) == gfw.GAUSS_EXACT
+    for m in (gfw.GAUSS_EXACT, gfw.GAUSS_GRID):
+        assert gfw.Graph.gaussian(ctx(), x, 2, 0.2, none, none, gfw.F64, m).query(gfw.TUNE_GAUSS_METHOD) == m
+    g = graphs.path_graph(10, 2)
+    assert gpu_graph(g, 2, [0], [1], gfw.F64).query(gfw.TUNE_GAUSS_METHOD) == 0
 
 
 def test_device_features_and_edge_cases():
