@@ -232,7 +232,6 @@ void plan_gather(const GaussView &v, const std::vector<int32_t> &start, int num_
                  std::vector<int32_t> &first)
 {
     const int64_t tasks = grid_tasks<D>(v.gdim);
-    std::vector<int64_t> rows_of;
     int64_t total = 0;
     for (int pass = 0; pass < 2; ++pass) {
         const int64_t cap = std::max<int64_t>(256, total / (16LL * 4 * std::max(num_cu, 1)));
