@@ -986,7 +986,6 @@ static gfw_status_t solve_impl(gfw_graph_s *g, const gfw_params_t *prm, void *U_
     Workspace &w = g->ws;
     T *U = (T *)w.U;
     double *P = w.P;
-    const int64_t nK = g->n * g->K;
     gfw_context_s *cx = g->ctx;
     Ctl c0;
     std::memset(&c0, 0, sizeof(c0));
