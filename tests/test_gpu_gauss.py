@@ -209,6 +209,26 @@ def test_full_size_image_sampled_rows():
         assert np.abs(P[rows] - ref).max() <= tol
 
 
+def test_high_resolution_grid_against_exact():
+    """The 1024 x 1024 image (n = 1,048,576), where the oracle's dense degrees are out of reach:
+    the grid summation against the exact sums (pinned to the oracle at the smaller sizes) on
+    every row, within the grid's error bound, in the FP64 graph's arithmetic."""
+    import torch
+
+    ip = configs.color_image(7, H=1024, W=1024)
+    say(f"[gpu] gauss 1024x1024: grid against exact, n={ip.n}")
+    U = _simplex_rows(ip.n, ip.K, 77)
+    Ut = torch_u(U, gfw.F64)
+    ge = _gpu(ip, gfw.F64, gfw.GAUSS_EXACT)
+    Pe = gfw.spmm(ctx(), ge, Ut)
+    ge.close()
+    gg = _gpu(ip, gfw.F64, gfw.GAUSS_GRID)
+    Pg = gfw.spmm(ctx(), gg, Ut)
+    err = float(torch.max(torch.abs(Pg - Pe)))
+    say(f"[gpu]   grid error against exact {err:.3e}")
+    assert err <= GRID_ABS
+
+
 def test_automatic_method_choice():
     """GFW_GAUSS_AUTO takes the grid for Table 2's largest image (its modelled time is the
     smaller by 2-4x in both dtypes) and the exact sums for a few points; the query reports it."""
