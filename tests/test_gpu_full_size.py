@@ -89,3 +89,30 @@ def test_full_size_knn_mixture():
         assert dE <= bound[dt]
         if dt == gfw.F64:
             assert same_steps
+
+
+def test_full_size_new_nodes_incremental():
+    """The new-node workload at its benchmarked size: 1,000 nodes joining a segmented network
+    of 1,000,000 (K = 5).  The old network is segmented by the oracle (its OpenMP build); from
+    that warm start the incremental solve (moving rows only) and the full iteration agree: old
+    rows untouched, the new nodes' labels identical, U within FP32 rounding, the same number of
+    iterations and the objective to 1e-6."""
+    say("[gpu] full size: 1,000,000 + 1,000 new nodes, incremental against the full iteration")
+    old, full = configs.grown_sbm(seed=11, n_old=1_000_000, n_new=1000, K=5)
+    r_old = O.solve_problem(old, max_iter=100, parallel=True)
+    U0 = np.full((full.n, full.K), 1.0 / full.K, dtype=np.float32)
+    U0[:old.n] = 0.0
+    U0[np.arange(old.n), r_old["labels"]] = 1.0
+    G = gpu_graph(full.graph, full.K, full.labelled_idx, full.labels, gfw.F32)
+    Ut = torch_u(U0, gfw.F32)
+    a = gfw.solve(ctx(), G, gfw.params(max_iter=300, tol=1e-6, U0=Ut))
+    b = gfw.solve(ctx(), G, gfw.params(max_iter=300, tol=1e-6, U0=Ut, incremental=True))
+    Ua, Ub = np_of(a["U"]), np_of(b["U"])
+    np.testing.assert_array_equal(Ub[:old.n], U0[:old.n])
+    assert np.abs(Ua - Ub).max() <= 1e-5
+    la, lb = np_of(a["labels"]), np_of(b["labels"])
+    assert np.array_equal(la[old.n:], lb[old.n:])
+    assert abs(a["iters"] - b["iters"]) <= 1
+    assert b["objective"] == pytest.approx(a["objective"], rel=1e-6)
+    say(f"[gpu]   iterations {a['iters']} / {b['iters']}; new-node accuracy "
+        f"{np.mean(lb[old.n:] == full.graph.truth[old.n:]):.4f}")
