@@ -116,3 +116,12 @@ def test_full_size_new_nodes_incremental():
     assert b["objective"] == pytest.approx(a["objective"], rel=1e-6)
     say(f"[gpu]   iterations {a['iters']} / {b['iters']}; new-node accuracy "
         f"{np.mean(lb[old.n:] == full.graph.truth[old.n:]):.4f}")
+
+
+def test_full_size_many_classes_lockstep():
+    """The many-classes workload at its benchmarked size (LFR-shaped, n = 100,000, K = 585, FP32,
+    the 10-classes-per-lane row kernel) in lockstep with the oracle."""
+    say("[gpu] full size: LFR-shaped n=100,000, K=585")
+    prob = configs.lfr_many_classes()
+    prob.max_iter = 12
+    lockstep(prob, gfw.F32, [0, 1, 10], label="lfr100000", traj_parallel=True)
